@@ -1,0 +1,244 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This package only draws initial configurations (positions, radii, velocities,
+materials, box descriptions).  It holds none of the simulated method's
+arithmetic: no contact law, no time-step rule, no integrator.  A time step of
+0.0 in a scene means "let the simulator pick it" and each side applies its own
+rule.
+
+Workloads follow the paper's set-up (Section "Performance evaluation"):
+spheres placed without initial overlap in a box, optionally seeded with
+touching pairs so that contacts exist from the first step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 150303553
+WALL_ALL = 0x3F  # six faces: bit 2a = low face of axis a, bit 2a+1 = high face
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+def build_helper(force: bool = False) -> str:
+    """Compile gen/rsa.c into gen/librsa.so (gcc, host code only)."""
+    src = os.path.join(_HERE, "rsa.c")
+    out = os.path.join(_HERE, "librsa.so")
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(src):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+        os.replace(tmp, out)
+    return out
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        lib = ctypes.CDLL(build_helper())
+        lib.rsa_place.restype = ctypes.c_int
+        lib.rsa_place.argtypes = [
+            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32,
+            ctypes.c_double, ctypes.c_double, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p]
+        _LIB = lib
+    return _LIB
+
+
+@dataclass
+class Material:
+    E: float = 3.0e9          # Young's modulus [Pa]
+    poisson: float = 0.3
+    G: float = 3.0e9 / (2 * 1.3)  # shear modulus [Pa]
+    density: float = 1200.0   # [kg/m^3]
+    restitution: float = 0.5
+    mu: float = 0.3           # sliding friction coefficient
+
+    @staticmethod
+    def make(E=3.0e9, poisson=0.3, density=1200.0, restitution=0.5, mu=0.3, G=None):
+        return Material(E=E, poisson=poisson, G=E / (2 * (1 + poisson)) if G is None else G,
+                        density=density, restitution=restitution, mu=mu)
+
+
+@dataclass
+class Scene:
+    """One simulation's inputs, in SI units.  Arrays are in particle-id order."""
+    lo: np.ndarray
+    hi: np.ndarray
+    x: np.ndarray            # (n,3) float64
+    v: np.ndarray            # (n,3) float64
+    w: np.ndarray            # (n,3) float64 angular velocity
+    r: np.ndarray            # (n,)  float64 holding float32-representable values
+    mat: np.ndarray          # (n,)  uint16 material index
+    materials: list
+    walls: int = WALL_ALL
+    periodic: int = 0
+    gravity: tuple = (0.0, 0.0, -9.81)
+    shear_rate: float = 0.0
+    dt: float = 0.0          # 0 = simulator's own rule
+    steps: int = 1
+    kn_form: int = 0         # 0 = as printed, 1 = textbook Hertz
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.r.shape[0])
+
+    def copy(self) -> "Scene":
+        import copy
+        return copy.deepcopy(self)
+
+
+def f32(a):
+    """Round to float32-representable values (kept in float64)."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+def lognormal_radii(rng, n, median=4e-6, sigma=0.15, rmin=2e-6, rmax=8e-6):
+    r = median * np.exp(sigma * rng.standard_normal(n))
+    return f32(np.clip(r, rmin, rmax))
+
+
+def rsa(r, lo, hi, periodic=0, p_touch=0.0, touch_max=2e-3, seed=0, max_attempts=100000):
+    """Random sequential addition; returns (n,3) positions (raises if it jams)."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    lo = np.ascontiguousarray(lo, dtype=np.float64)
+    hi = np.ascontiguousarray(hi, dtype=np.float64)
+    n = r.shape[0]
+    x = np.zeros((n, 3), dtype=np.float64)
+    got = _lib().rsa_place(n, r.ctypes.data, lo.ctypes.data, hi.ctypes.data, periodic,
+                           float(p_touch), float(touch_max), int(seed) & (2**64 - 1),
+                           int(max_attempts), x.ctypes.data)
+    if got != n:
+        raise RuntimeError("RSA placed only %d of %d spheres" % (got, n))
+    return x
+
+
+def box_side(r, phi):
+    """Side of the cube holding spheres r at volume fraction phi."""
+    return float((np.sum(4.0 / 3.0 * np.pi * np.asarray(r) ** 3) / phi) ** (1.0 / 3.0))
+
+
+def _finish(rng, x, r, lo, hi, materials, vel_sigma=0.1, **kw):
+    n = r.shape[0]
+    v = vel_sigma * rng.standard_normal((n, 3))
+    w = np.zeros((n, 3))
+    mat = np.zeros(n, dtype=np.uint16)
+    return Scene(lo=np.asarray(lo, float), hi=np.asarray(hi, float), x=x, v=v, w=w, r=r,
+                 mat=mat, materials=materials, **kw)
+
+
+def config_plain(seed=None, n=2000):
+    """Monodisperse r = 5 um, phi = 0.3, six walls, gravity, 1000 steps.
+
+    The stated 200 um box would give phi = 0.131 for 2,000 spheres; N and phi
+    are kept and the box side follows from them (151.7 um at N = 2000)."""
+    seed = SEED_BASE + 0 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = f32(np.full(n, 5e-6))
+    L = box_side(r, 0.3)
+    lo, hi = np.zeros(3), np.full(3, L)
+    x = rsa(r, lo, hi, seed=seed)
+    mats = [Material.make(restitution=0.5, mu=0.3)]
+    return _finish(rng, x, r, lo, hi, mats, steps=1000, name="plain-2k-fp64",
+                   meta=dict(phi=0.3))
+
+
+def config_dilute(seed=None, n=1_000_000, p_touch=0.5, touch_max=2e-3):
+    """1M polydisperse spheres (lognormal, median 4 um, sigma_log 0.15, clipped
+    to [2, 8] um), walled box at phi = 0.1, gravity, 200 steps.  Half of the
+    spheres are placed touching an earlier one so that about one contact per
+    particle exists from the first step."""
+    seed = SEED_BASE + 1 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = lognormal_radii(rng, n)
+    L = box_side(r, 0.1)
+    lo, hi = np.zeros(3), np.full(3, L)
+    x = rsa(r, lo, hi, p_touch=p_touch, touch_max=touch_max, seed=seed)
+    mats = [Material.make(restitution=0.5, mu=0.3)]
+    return _finish(rng, x, r, lo, hi, mats, steps=200, name="dilute-1m-mixed",
+                   meta=dict(phi=0.1, p_touch=p_touch))
+
+
+def config_batch_job(k, m, n=None):
+    """Job m of a batched workload: N log-uniform in [1k, 200k], phi ~ U[0.1, 0.3]
+    by RSA (touch-seeded), restitution ~ U[0.3, 0.9], mu ~ U[0.1, 0.5]."""
+    seed = SEED_BASE + 1000 * k + m
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if n is None:
+        n = int(np.exp(rng.uniform(np.log(1e3), np.log(2e5))))
+    phi = float(rng.uniform(0.1, 0.3))
+    eps = float(rng.uniform(0.3, 0.9))
+    mu = float(rng.uniform(0.1, 0.5))
+    r = lognormal_radii(rng, n)
+    L = box_side(r, phi)
+    lo, hi = np.zeros(3), np.full(3, L)
+    x = rsa(r, lo, hi, p_touch=0.5, seed=seed)
+    mats = [Material.make(restitution=eps, mu=mu)]
+    return _finish(rng, x, r, lo, hi, mats, steps=500, name="batch-job-%d" % m,
+                   meta=dict(phi=phi))
+
+
+# ---------------------------------------------------------------- tiny scenes
+def scene_pair(r1=5e-6, r2=5e-6, gap=-1e-9, v1=(0.1, 0, 0), v2=(-0.1, 0, 0), w1=(0, 0, 0),
+               w2=(0, 0, 0), material=None, walls=0, L=100e-6, gravity=(0.0, 0.0, 0.0),
+               offset=(0.0, 0.0, 0.0)):
+    """Two spheres on the x axis, centre distance r1 + r2 + gap."""
+    material = material or Material.make()
+    c = np.full(3, L / 2) + np.asarray(offset, float)
+    d = r1 + r2 + gap
+    x = np.array([c - [d / 2, 0, 0], c + [d / 2, 0, 0]])
+    return Scene(lo=np.zeros(3), hi=np.full(3, L), x=x, v=np.array([v1, v2], float),
+                 w=np.array([w1, w2], float), r=f32([r1, r2]), mat=np.zeros(2, np.uint16),
+                 materials=[material], walls=walls, periodic=0, gravity=tuple(gravity),
+                 name="pair")
+
+
+def scene_cluster(seed, n_side=4, r=5e-6, overlap_max=2e-3, vel_sigma=0.05, jitter=0.0,
+                  walls=WALL_ALL, gravity=(0.0, 0.0, -9.81), polydisperse=False):
+    """A compressed simple-cubic cluster: neighbours overlap by dn/r in
+    U[0, overlap_max) so that every particle has several contacts."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = n_side ** 3
+    rr = lognormal_radii(rng, n, median=r, sigma=0.05, rmin=0.8 * r, rmax=1.2 * r) \
+        if polydisperse else f32(np.full(n, r))
+    spacing = 2 * r * (1 - overlap_max / 2)
+    idx = np.stack(np.meshgrid(np.arange(n_side), np.arange(n_side), np.arange(n_side),
+                               indexing="ij"), -1).reshape(-1, 3)
+    x = (idx + 0.5) * spacing + 3 * r
+    x = x + jitter * r * rng.uniform(-1, 1, size=x.shape)
+    L = n_side * spacing + 6 * r
+    mats = [Material.make()]
+    return _finish(rng, x, rr, np.zeros(3), np.full(3, L), mats, vel_sigma=vel_sigma,
+                   walls=walls, gravity=tuple(gravity), name="cluster")
+
+
+def scene_random(seed, n, phi=0.3, p_touch=0.7, touch_max=2e-3, walls=WALL_ALL,
+                 periodic=0, gravity=(0.0, 0.0, -9.81), polydisperse=True, vel_sigma=0.1,
+                 shear_rate=0.0, n_materials=1):
+    """Seeded random RSA fill with touch seeding; optionally periodic or several materials."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = lognormal_radii(rng, n) if polydisperse else f32(np.full(n, 4e-6))
+    L = box_side(r, phi)
+    lo, hi = np.zeros(3), np.full(3, L)
+    x = rsa(r, lo, hi, periodic=periodic, p_touch=p_touch, touch_max=touch_max, seed=seed)
+    mats = [Material.make(restitution=0.5, mu=0.3)]
+    for k in range(1, n_materials):
+        mats.append(Material.make(E=float(rng.uniform(1e9, 5e9)),
+                                  poisson=float(rng.uniform(0.2, 0.4)),
+                                  density=float(rng.uniform(800, 2500)),
+                                  restitution=float(rng.uniform(0.3, 0.9)),
+                                  mu=float(rng.uniform(0.1, 0.5))))
+    sc = _finish(rng, x, r, lo, hi, mats, vel_sigma=vel_sigma, walls=walls, periodic=periodic,
+                 gravity=tuple(gravity), shear_rate=shear_rate, name="random")
+    if n_materials > 1:
+        sc.mat = rng.integers(0, n_materials, size=n).astype(np.uint16)
+    if shear_rate:
+        # affine shear profile u = shear_rate * y along x
+        sc.v[:, 0] += shear_rate * (x[:, 1] - lo[1])
+    return sc

@@ -1,0 +1,496 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code: closed forms of the
+Hertz contact (evaluated with scipy's quadrature / ODE integrators), textbook
+special cases, conservation and balance laws that hold exactly for the
+semi-implicit Euler step, brute force on tiny inputs, a hand-worked fixture,
+and library neighbour search (scipy cKDTree).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate, spatial
+
+import gen
+import oracle
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------- helpers
+def nondim_collision(alpha):
+    """Head-on collision s'' = -s^1.5 - alpha s^0.25 s', s(0)=0, s'(0)=1 in the
+    time unit (m*/k_n)^(2/5) v0^(-1/5): returns (contact time, restitution,
+    max overlap) from scipy's DOP853."""
+    def f(t, y):
+        s = max(y[0], 0.0)
+        return [y[1], -s ** 1.5 - alpha * s ** 0.25 * y[1]]
+
+    def out(t, y):
+        return y[0]
+    out.terminal = True
+    out.direction = -1
+    sol = integrate.solve_ivp(f, [0, 50], [0.0, 1.0], method="DOP853", rtol=1e-12, atol=1e-14,
+                              events=out, dense_output=True)
+    tc = sol.t_events[0][0]
+    e = -sol.y_events[0][0][1]
+    ts = np.linspace(0, tc, 20001)
+    smax = sol.sol(ts)[0].max()
+    return tc, e, smax
+
+
+def hertz_time_constant():
+    """Elastic contact time from the energy integral
+    t = 2 int_0^smax ds / sqrt(1 - 4/5 s^(5/2)), smax = (5/4)^(2/5)."""
+    smax = 1.25 ** 0.4
+    val, _ = integrate.quad(lambda s: 1.0 / math.sqrt(max(1.0 - 0.8 * s ** 2.5, 1e-300)), 0, smax,
+                            limit=200)
+    return 2.0 * val
+
+
+def textbook_hertz_kn(E1, nu1, E2, nu2, r1, r2):
+    """Hertz: F = 4/3 E* sqrt(R*) d^(3/2), 1/E* = (1-nu1^2)/E1 + (1-nu2^2)/E2 (Johnson, Contact Mechanics, ch. 4)."""
+    Es = 1.0 / ((1 - nu1 ** 2) / E1 + (1 - nu2 ** 2) / E2)
+    Rs = r1 * r2 / (r1 + r2) if r2 else r1
+    return 4.0 / 3.0 * Es * math.sqrt(Rs)
+
+
+def run_collision(scene, dt, max_steps=200000):
+    """Run the oracle until the (only) contact ends; returns the sim, the number
+    of steps in contact and the largest overlap seen."""
+    s = oracle.Sim(scene, dt=dt, mode=0)
+    steps_in = 0
+    dmax = 0.0
+    for _ in range(max_steps):
+        s.step(keep_contact_forces=False)
+        if len(s.hist):
+            steps_in += 1
+            d = np.linalg.norm(s.x[1] - s.x[0]) if scene.n == 2 else 0
+            dmax = max(dmax, float(scene.r[0] + scene.r[-1] - d) if scene.n == 2 else 0.0)
+        elif steps_in:
+            break
+    return s, steps_in, dmax
+
+
+# --------------------------------------------------------- the contact law
+@pytest.mark.parametrize("eps", [0.1, 0.3, 0.5, 0.7, 0.9, 0.99])
+def test_alpha_restitutes_eps_exactly(eps):
+    # The damping prefactor must make the model's head-on restitution equal eps.
+    _, e, _ = nondim_collision(oracle.alpha(eps))
+    assert abs(e - eps) < 1e-7
+
+
+def test_hertz_time_constant_matches_beta_form():
+    # 3.2180654597 = (4/5) B(2/5, 1/2) (5/4)^(2/5); the oracle's own constant
+    # comes from that form, the test from the energy integral and the ODE.
+    c_quad = hertz_time_constant()
+    c_ode, e, smax = nondim_collision(0.0)
+    assert abs(c_quad - c_ode) < 1e-8
+    assert abs(e - 1.0) < 1e-9
+    assert abs(smax - 1.25 ** 0.4) < 1e-6
+    assert abs(oracle.contact_time(1.0, 1.0, 1.0) - c_quad) < 1e-9
+
+
+@pytest.mark.parametrize("v0", [0.02, 0.2])
+def test_elastic_headon_contact_time_and_overlap_textbook(v0):
+    # kn_form 1 must be textbook Hertz; contact time and peak overlap follow.
+    mat = gen.Material.make(restitution=1.0, mu=0.3)
+    sc = gen.scene_pair(r1=5e-6, r2=4e-6, gap=1e-13, v1=(v0 / 2, 0, 0), v2=(-v0 / 2, 0, 0),
+                        material=mat)
+    sc.kn_form = 1
+    kn = textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, 5e-6, 4e-6)
+    m1 = 1200 * 4 / 3 * math.pi * (5e-6) ** 3
+    m2 = 1200 * 4 / 3 * math.pi * (4e-6) ** 3
+    ms = m1 * m2 / (m1 + m2)
+    tc = hertz_time_constant() * (ms / kn) ** 0.4 * v0 ** -0.2
+    dmax = (5 * ms * v0 ** 2 / (4 * kn)) ** 0.4
+    s, n_in, dmax_sim = run_collision(sc, dt=tc / 1000)
+    assert abs(n_in * s.dt - tc) / tc < 2e-3
+    assert abs(dmax_sim - dmax) / dmax < 2e-3
+    vrel = s.v[1, 0] - s.v[0, 0]
+    assert abs(vrel / v0 - 1.0) < 2e-3  # elastic
+
+
+def test_printed_kn_is_paper_factor_times_textbook():
+    # As printed, k_n uses (2 - sigma^2)/E where Hertz has (1 - sigma^2)/E, so
+    # the contact time scales by ((2 - s^2)/(1 - s^2))^(2/5).
+    mat = gen.Material.make(restitution=1.0)
+    sc = gen.scene_pair(gap=1e-13, v1=(0.05, 0, 0), v2=(-0.05, 0, 0), material=mat)
+    sc1 = sc.copy()
+    sc1.kn_form = 1
+    tc0 = hertz_time_constant()
+    kn1 = textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, 5e-6, 5e-6)
+    kn0 = kn1 * (1 - 0.09) / (2 - 0.09)
+    m = 1200 * 4 / 3 * math.pi * (5e-6) ** 3
+    t_print = tc0 * (m / 2 / kn0) ** 0.4 * 0.1 ** -0.2
+    s, n_in, _ = run_collision(sc, dt=t_print / 1000)
+    assert abs(n_in * s.dt - t_print) / t_print < 2e-3
+
+
+@pytest.mark.parametrize("eps,v0", [(0.3, 0.01), (0.5, 0.1), (0.5, 1.0), (0.9, 0.1)])
+def test_restitution_equals_eps_independent_of_speed(eps, v0):
+    mat = gen.Material.make(restitution=eps)
+    sc = gen.scene_pair(gap=1e-13, v1=(v0 / 2, 0, 0), v2=(-v0 / 2, 0, 0), material=mat)
+    P = oracle.params(sc, dt=1.0)
+    m = oracle.mass(1200, 5e-6)
+    tc = hertz_time_constant() * (m / 2 / oracle.kn(P, 0, 0, 5e-6, 5e-6)) ** 0.4 * v0 ** -0.2
+    s, n_in, _ = run_collision(sc, dt=tc / 1000)
+    e = (s.v[1, 0] - s.v[0, 0]) / v0
+    assert abs(e - eps) < 2e-3
+    # damped contact time from the nondimensional ODE
+    tcd, _, _ = nondim_collision(oracle.alpha(eps))
+    tdim = tcd * (m / 2 / oracle.kn(P, 0, 0, 5e-6, 5e-6)) ** 0.4 * v0 ** -0.2
+    assert abs(n_in * s.dt - tdim) / tdim < 3e-3
+
+
+def test_wall_headon_uses_particle_mass_and_radius():
+    # A face is a sphere of infinite radius and mass: m* = m, r* = r.
+    v0 = 0.1
+    mat = gen.Material.make(restitution=1.0)
+    L = 100e-6
+    r = 5e-6
+    sc = gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([[L / 2, L / 2, r + 1e-13]]),
+                   v=np.array([[0, 0, -v0]]), w=np.zeros((1, 3)), r=gen.f32([r]),
+                   mat=np.zeros(1, np.uint16), materials=[mat], walls=gen.WALL_ALL,
+                   gravity=(0, 0, 0))
+    sc.kn_form = 1
+    kn = textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, r, 0)
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    tc = hertz_time_constant() * (m / kn) ** 0.4 * v0 ** -0.2
+    s = oracle.Sim(sc, dt=tc / 1000, mode=0)
+    n_in = 0
+    for _ in range(5000):
+        s.step()
+        if len(s.hist):
+            assert int(s.hist.j[0]) == oracle.FACE_ID + 4  # low z face
+            n_in += 1
+        elif n_in:
+            break
+    assert abs(n_in * s.dt - tc) / tc < 2e-3
+    assert abs(s.v[0, 2] - v0) / v0 < 2e-3
+
+
+def test_tangential_stick_oscillation_period():
+    # A sphere pressed on a face by a constant load, no damping, no sliding:
+    # the contact point's slip u obeys u'' = -(k_t (1/m + r^2/I)) u, so the
+    # period is 2 pi sqrt(m / (3.5 k_t)) with Mindlin's k_t = 8 G* sqrt(r dn),
+    # 1/G* = (2 - nu)/G + (2 - nu)/G.  A sign error in the rotational term of
+    # Eq. (2), the lever arm or k_t changes the period (or makes it grow).
+    mat = gen.Material.make(restitution=1.0, mu=100.0)
+    r = 5e-6
+    L = 100e-6
+    g = 1e4
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    kn = textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, r, 0) * (1 - 0.09) / (2 - 0.09)
+    d0 = (m * g / kn) ** (2 / 3)
+    Gs = 1.0 / (2 * (2 - mat.poisson) / mat.G)
+    kt = 8 * Gs * math.sqrt(r * d0)
+    T = 2 * math.pi * math.sqrt(m / (3.5 * kt))
+    u0 = 1e-6
+    sc = gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([[L / 2, L / 2, r - d0]]),
+                   v=np.array([[u0, 0, 0]]), w=np.zeros((1, 3)), r=gen.f32([r]),
+                   mat=np.zeros(1, np.uint16), materials=[mat], walls=gen.WALL_ALL,
+                   gravity=(0, 0, -g))
+    dt = T / 2000
+    r = float(sc.r[0])
+    s = oracle.Sim(sc, dt=dt, mode=0)
+    slip = []
+    for _ in range(3000):
+        s.step()
+        # contact-point velocity along x for n = -z: v_x + (w x (-r z))_x = v_x - r w_y
+        slip.append(s.v[0, 0] - r * s.w[0, 1])
+    slip = np.array(slip)
+    # zero crossings of the slip velocity (it starts at +u0 as a cosine)
+    zc = np.where(np.sign(slip[:-1]) != np.sign(slip[1:]))[0]
+    assert len(zc) >= 2
+    period = 2 * (zc[1] - zc[0]) * dt
+    assert abs(period - T) / T < 5e-3
+    assert np.abs(slip).max() < 1.01 * u0  # bounded: no growth
+
+
+def test_gross_sliding_spin_ratio_and_speed_loss():
+    # Sliding on a face, the tangential impulse each step is mu |F_n| dt along a
+    # fixed direction, so r dw / |dv_t| = m r^2 / I = 5/2 exactly, and the
+    # speed drop is mu sum |F_n| dt / m.
+    mat = gen.Material.make(restitution=0.5, mu=0.3)
+    r = 5e-6
+    L = 100e-6
+    g = 1e4
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    P0 = oracle.params(gen.scene_pair(material=mat), dt=1.0)
+    kn = oracle.kn(P0, 0, 0, r, 0)
+    d0 = (m * g / kn) ** (2 / 3)
+    sc = gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([[L / 2, L / 2, r - d0]]),
+                   v=np.array([[0.05, 0, 0]]), w=np.zeros((1, 3)), r=gen.f32([r]),
+                   mat=np.zeros(1, np.uint16), materials=[mat], walls=gen.WALL_ALL,
+                   gravity=(0, 0, -g))
+    r = float(sc.r[0])  # the stored radius is float32-representable
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    s = oracle.Sim(sc, dt=1e-9, mode=0)
+    v0, w0 = s.v[0].copy(), s.w[0].copy()
+    fn_sum = 0.0
+    for _ in range(200):
+        s.step(keep_contact_forces=True)
+        fn_sum += abs(s.cF[0, 2])
+    dv = s.v[0, 0] - v0[0]
+    dw = s.w[0, 1] - w0[1]
+    assert dv < 0 < dw  # friction slows it and spins it towards rolling (w_y > 0)
+    assert abs(r * dw / dv + 2.5) < 1e-9
+    assert abs(-dv - 0.3 * fn_sum * s.dt / m) / (-dv) < 1e-9
+
+
+def _pair_normals(x, hist):
+    i = hist.i.astype(np.int64)
+    j = hist.j.astype(np.int64)
+    part = hist.j < oracle.FACE_ID
+    d = np.zeros((len(i), 3))
+    d[part] = x[j[part]] - x[i[part]]
+    return part, d
+
+
+def test_cap_on_particle_contacts():
+    sc = gen.scene_cluster(seed=11, n_side=4, vel_sigma=1.0, polydisperse=True, walls=0,
+                           gravity=(0, 0, 0))
+    s = oracle.Sim(sc, mode=0)
+    seen_capped = 0
+    for _ in range(10):
+        x0 = s.x.copy()
+        s.step(keep_contact_forces=True)
+        part, d = _pair_normals(x0, s.hist)
+        n = d[part] / np.linalg.norm(d[part], axis=1)[:, None]
+        F = s.cF[part]
+        fn = np.abs(np.sum(F * n, 1))
+        ft = np.linalg.norm(F - np.sum(F * n, 1)[:, None] * n, axis=1)
+        assert np.all(ft <= 0.3 * fn * (1 + 1e-9) + 1e-30)
+        seen_capped += int(np.sum(ft > 0.3 * fn * (1 - 1e-9)))
+    assert seen_capped > 0  # the cap was actually exercised
+
+
+def test_newton_third_law_bitwise():
+    sc = gen.scene_cluster(seed=3, n_side=4, vel_sigma=0.3, polydisperse=True, walls=0,
+                           gravity=(0, 0, 0))
+    sc.w = np.random.default_rng(1).normal(0, 1e4, size=sc.w.shape)
+    s = oracle.Sim(sc, mode=0)
+    for _ in range(15):
+        s.step(keep_contact_forces=True)
+        h = s.hist
+        idx = {(int(a), int(b)): k for k, (a, b) in enumerate(zip(h.i, h.j))}
+        assert len(idx) > 50
+        for (a, b), k in idx.items():
+            kk = idx[(b, a)]
+            assert np.array_equal(s.cF[k], -s.cF[kk])
+            assert np.array_equal(h.dt[k], -h.dt[kk])
+            # T_ij / r_i and T_ji / r_j are both n x F
+            np.testing.assert_allclose(s.cT[k] / sc.r[a], s.cT[kk] / sc.r[b], rtol=1e-13,
+                                       atol=1e-30)
+
+
+def test_linear_momentum_conserved_periodic():
+    sc = gen.scene_random(seed=5, n=300, phi=0.25, walls=0, periodic=7, gravity=(0, 0, 0))
+    s = oracle.Sim(sc, mode=1)
+    m = 1200 * 4 / 3 * np.pi * sc.r ** 3
+    p0 = (m[:, None] * s.v).sum(0)
+    scale = (m[:, None] * np.abs(s.v)).sum(0)
+    for _ in range(30):
+        s.step()
+    p1 = (m[:, None] * s.v).sum(0)
+    assert len(s.hist) > 100
+    assert np.all(np.abs(p1 - p0) <= 1e-13 * scale)
+
+
+def test_angular_momentum_balance_exact():
+    # For the semi-implicit step, L(n+1) - L(n) = dt sum_i (x_i x F_i + T_i)
+    # with x_i at the start of the step, and pairwise that sum equals
+    # dt sum_{i<j} dn_ij (n_ij x F_ij) (lever arm the full radius).
+    sc = gen.scene_cluster(seed=9, n_side=4, vel_sigma=0.3, polydisperse=True, walls=0,
+                           gravity=(0, 0, 0))
+    s = oracle.Sim(sc, mode=0)
+    m = 1200 * 4 / 3 * np.pi * sc.r ** 3
+    I = 0.4 * m * sc.r ** 2
+
+    def L(s):
+        return (m[:, None] * np.cross(s.x, s.v)).sum(0) + (I[:, None] * s.w).sum(0)
+
+    for _ in range(5):
+        x0 = s.x.copy()
+        L0 = L(s)
+        s.step(keep_contact_forces=True)
+        dL = L(s) - L0
+        pred = s.dt * (np.cross(x0, s.F).sum(0) + s.T.sum(0))
+        h = s.hist
+        part, d = _pair_normals(x0, h)
+        assert part.all()
+        dist = np.linalg.norm(d, axis=1)
+        n = d / dist[:, None]
+        dn = sc.r[h.i] + sc.r[h.j] - dist
+        pair = s.dt * 0.5 * (dn[:, None] * np.cross(n, s.cF)).sum(0)
+        scale = s.dt * np.abs(np.cross(x0, s.F)).sum()
+        assert np.all(np.abs(dL - pred) <= 1e-9 * scale)
+        assert np.all(np.abs(pred - pair) <= 1e-9 * scale)
+
+
+def test_free_flight_closed_form():
+    sc = gen.scene_random(seed=2, n=50, phi=0.002, p_touch=0.0, walls=0, gravity=(0.3, -1.0, -9.81),
+                          vel_sigma=0.01)
+    s = oracle.Sim(sc, dt=1e-6, mode=1)
+    x0, v0 = sc.x.copy(), sc.v.copy()
+    g = np.array(sc.gravity)
+    k = 40
+    for _ in range(k):
+        s.step()
+        assert len(s.hist) == 0
+    np.testing.assert_allclose(s.v, v0 + k * 1e-6 * g, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(s.x, x0 + k * 1e-6 * v0 + g * 1e-12 * k * (k + 1) / 2,
+                               rtol=1e-12, atol=1e-15)
+
+
+def test_frictionless_elastic_oblique_energy():
+    mat = gen.Material.make(restitution=1.0, mu=0.0)
+    sc = gen.scene_pair(r1=5e-6, r2=4e-6, gap=1e-13, v1=(0.1, 0, 0), v2=(-0.05, 0.02, 0),
+                        material=mat, offset=(0, 0, 0))
+    sc.x[1, 1] += 3e-6  # oblique impact
+    sc.x[1, 0] -= 0.5e-6
+    m = 1200 * 4 / 3 * np.pi * sc.r ** 3
+    ke0 = 0.5 * (m[:, None] * sc.v ** 2).sum()
+    s = oracle.Sim(sc, dt=2e-11, mode=0)
+    seen = False
+    for _ in range(200000):
+        s.step()
+        if len(s.hist):
+            seen = True
+        elif seen:
+            break
+    assert seen
+    ke1 = 0.5 * (m[:, None] * s.v ** 2).sum()
+    assert abs(ke1 - ke0) / ke0 < 1e-5
+    assert np.allclose(s.w, 0)  # no tangential force, no spin
+
+
+# ---------------------------------------------------------- contact set
+def _pairs_from_kdtree(x, r, walls, lo, hi):
+    """Contact set via scipy's k-d tree (library neighbour search) then the
+    overlap predicate on the few candidates."""
+    tree = spatial.cKDTree(x)
+    cand = tree.query_pairs(2 * r.max(), output_type="ndarray")
+    out = set()
+    for a, b in cand:
+        d = x[b] - x[a]
+        d2 = d[0] * d[0] + d[1] * d[1]
+        d2 = d2 + d[2] * d[2]
+        if d2 < (r[a] + r[b]) ** 2:
+            out.add((int(a), int(b)))
+            out.add((int(b), int(a)))
+    for i in range(len(r)):
+        for f in range(6):
+            if walls & (1 << f):
+                a = f >> 1
+                dist = hi[a] - x[i, a] if f & 1 else x[i, a] - lo[a]
+                if dist < r[i]:
+                    out.add((i, oracle.FACE_ID + f))
+    return out
+
+
+def test_contact_chain_fixture():
+    with open(os.path.join(GOLD, "contact_chain.json")) as fh:
+        g = json.load(fh)
+    sc = gen.Scene(lo=np.array(g["box_lo"]), hi=np.array(g["box_hi"]), x=np.array(g["positions"]),
+                   v=np.zeros((5, 3)), w=np.zeros((5, 3)), r=gen.f32(g["radii"]),
+                   mat=np.zeros(5, np.uint16), materials=[gen.Material.make()], walls=g["walls"])
+    want = set()
+    for a, b in g["expected_pairs"]:
+        want.add((a, oracle.FACE_ID + int(b[4:]) if isinstance(b, str) else b))
+    for mode in (0, 1):
+        i, j = oracle.contacts(sc, mode=mode)
+        assert set(zip(i.tolist(), j.tolist())) == want
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_brute_force_matches_kdtree(seed):
+    sc = gen.scene_random(seed=seed, n=800, phi=0.22, p_touch=0.6)
+    i, j = oracle.contacts(sc, mode=0)
+    got = set(zip(i.tolist(), j.tolist()))
+    assert got == _pairs_from_kdtree(sc.x, sc.r, sc.walls, sc.lo, sc.hi)
+    assert len(got) > 400
+
+
+@pytest.mark.parametrize("periodic,shear", [(0, 0.0), (7, 0.0), (5, 0.0), (7, 100.0)])
+def test_cells_match_brute_force(periodic, shear):
+    walls = 0 if periodic == 7 else (gen.WALL_ALL & ~(3 | 48) if periodic == 5 else gen.WALL_ALL)
+    sc = gen.scene_random(seed=17, n=600, phi=0.25, p_touch=0.6, walls=walls, periodic=periodic,
+                          shear_rate=shear)
+    for t in (0.0, 1.234e-3, 7.7e-2):
+        a = oracle.contacts(sc, mode=0, time=t)
+        b = oracle.contacts(sc, mode=1, time=t)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        assert len(a[0]) > 300
+
+
+def test_lees_edwards_image_contact_and_velocity():
+    # Two spheres across the y boundary: j's image at y_j - Ly sits at
+    # x_j - D(t) and moves with v_j - shear Ly along x.
+    L = 60e-6
+    shear = 1000.0
+    r = float(gen.f32([4e-6])[0])
+    t = 2.5e-4
+    D = (shear * L * t) % L
+    dn0 = 1e-9
+    d = np.array([1e-6, -math.sqrt((2 * r - dn0) ** 2 - 1e-12), 0.0])  # image minus i
+    xi = np.array([10e-6, 1e-6, 30e-6])
+    xj = np.array([(xi[0] + D + d[0]) % L, L + xi[1] + d[1], 30e-6])
+    sc = gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([xi, xj]), v=np.zeros((2, 3)),
+                   w=np.zeros((2, 3)), r=gen.f32([r, r]), mat=np.zeros(2, np.uint16),
+                   materials=[gen.Material.make(restitution=0.5, mu=0.0)], walls=0, periodic=7,
+                   gravity=(0, 0, 0), shear_rate=shear)
+    i, j = oracle.contacts(sc, mode=0, time=t)
+    assert set(zip(i.tolist(), j.tolist())) == {(0, 1), (1, 0)}
+    i2, j2 = oracle.contacts(sc, mode=1, time=t)
+    assert np.array_equal(i, i2) and np.array_equal(j, j2)
+    # frictionless, both at rest: the image moves at -shear*L along x, so
+    # v = v_i - v_image = +shear*L e_x and the damping term is -eta (v.n) n
+    s = oracle.Sim(sc, dt=1e-10, mode=0)
+    s.time = t
+    s.step(keep_contact_forces=True)
+    dd = (sc.x[1] - sc.x[0]) + np.array([-D, -L, 0.0])
+    dist = np.linalg.norm(dd)
+    n = dd / dist
+    F = s.cF[0]
+    m = 1200 * 4 / 3 * np.pi * r ** 3
+    P = oracle.params(sc, dt=1.0)
+    kn = oracle.kn(P, 0, 0, r, r)
+    dn = 2 * r - dist
+    eta = oracle.alpha(0.5) * np.sqrt(m / 2 * kn * np.sqrt(dn))
+    v = np.array([shear * L, 0, 0])
+    want = -kn * dn ** 1.5 * n - eta * (v @ n) * n
+    np.testing.assert_allclose(F, want, rtol=1e-5)
+    assert abs(eta * (v @ n)) > 0.05 * kn * dn ** 1.5  # the image velocity matters
+    np.testing.assert_array_equal(s.cF[1], -s.cF[0])
+
+
+def test_history_forgotten_and_restarted():
+    mat = gen.Material.make(restitution=0.9, mu=0.5)
+    sc = gen.scene_pair(gap=-2e-9, v1=(0.0, 0.05, 0), v2=(0.0, -0.05, 0), material=mat)
+    s = oracle.Sim(sc, dt=1e-9, mode=0)
+    s.step()
+    assert len(s.hist) == 2 and np.abs(s.hist.dt).max() > 0
+    s.x[1, 0] += 1e-6  # pull apart: the contact ends and its history is dropped
+    s.step()
+    assert len(s.hist) == 0
+    s.x[1, 0] -= 1e-6
+    s.v[:] = 0
+    s.w[:] = 0
+    s.step()
+    # restarted history: only this step's v_t dt with zero velocity -> zero
+    assert len(s.hist) == 2 and np.abs(s.hist.dt).max() == 0.0
+
+
+def test_dt_rule_closed_form():
+    sc = gen.scene_pair()
+    mat = sc.materials[0]
+    r = float(sc.r[0])
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    kn = textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, r, r) * 0.91 / 1.91
+    want = hertz_time_constant() * (m / 2 / kn) ** 0.4 * 0.1 ** -0.2 / 50
+    assert abs(oracle.dt_rule(sc) - want) / want < 1e-9
