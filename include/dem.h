@@ -1,0 +1,198 @@
+/*
+ * dem.h -- C ABI of the MI355X DEM force-step library (libdem.so).
+ *
+ * The library advances spheres under the contact law of Nakahara &
+ * Washizawa, "Accelerating DEM simulations on GPUs by reducing the impact of
+ * warp divergences" (arXiv:1503.03553), section 2: Hertz normal force
+ * k_n dn^(3/2), Mindlin tangential stiffness k_t(dn), damping
+ * eta = alpha(eps) sqrt(m* k_n sqrt(dn)), tangential displacement history
+ * (Eq. 3) carried across steps, sliding cap (Eq. 4) and torque r (n x F).
+ * Its calls follow the paper's problem statement (section 4.2, kernel list):
+ * the host creates the initial configuration, sends it to the GPU once, and
+ * then only asks the GPU to advance it.
+ *
+ * Conventions common to every call
+ *  - Units are SI.  Arrays are interleaved xyz ((n,3) row-major) unless
+ *    stated otherwise.
+ *  - Particle identity: the input index is the particle id (pid).  Every
+ *    output is returned in pid order, although the device keeps particles in
+ *    cell order internally.
+ *  - Ownership: the caller owns every host buffer; the library copies what it
+ *    needs and never keeps a caller pointer after a call returns.  A
+ *    dem_sim owns its device memory and frees it in dem_destroy.
+ *  - Errors: every call returns a dem_status; nothing is thrown across the
+ *    ABI.  dem_step only enqueues work; a condition found on the device
+ *    (contact capacity, non-finite state) is reported by the next blocking
+ *    call (dem_sync, dem_get_*), after which the state is that of the last
+ *    step that completed.  Capacity overflow is handled inside the library
+ *    (it grows the contact table and redoes the step) and only surfaces as
+ *    DEM_ECAPACITY when memory cannot be grown.
+ *  - Threading: one host thread at a time per handle.  Calls on different
+ *    handles are independent.
+ *  - Box faces ("walls") are the six faces of the box [lo, hi) as planes,
+ *    with the contact law of a sphere of infinite radius and mass made of the
+ *    particle's own material (section 3.3: forces between a particle and a
+ *    wall are computed like those between particles).  In contact lists a
+ *    face f is partner id DEM_FACE_ID + f, f = 2 * axis + (0 low, 1 high).
+ */
+#ifndef DEM_H
+#define DEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dem_sim dem_sim; /* opaque, owned by the library */
+
+typedef enum {
+    DEM_OK = 0,
+    DEM_EINVAL = -1,      /* a bad argument; nothing was changed */
+    DEM_ENOMEM = -2,      /* device or host allocation failed */
+    DEM_ECAPACITY = -3,   /* contact table could not be grown */
+    DEM_ENONFINITE = -4,  /* a force or state component became NaN/Inf */
+    DEM_EDEVICE = -5,     /* a HIP runtime error */
+    DEM_EBUSY = -6        /* reserved */
+} dem_status;
+
+typedef enum {
+    DEM_PREC_FP64 = 0,  /* every operation in FP64 */
+    DEM_PREC_MIXED = 1  /* contact normal, velocities, stiffnesses and forces in
+                           FP32; overlap, tangential displacement history,
+                           positions, velocities and angular velocities in FP64 */
+} dem_precision;
+
+#define DEM_MAX_MATERIALS 8
+#define DEM_FACE_ID 0xFFFFFFF0u
+
+/* One material (section 2: E Young's modulus, sigma Poisson ratio, G shear
+ * modulus, eps restitution coefficient, mu_D sliding friction coefficient).
+ * A pair of materials uses the means of their restitution and friction. */
+typedef struct {
+    double E, poisson, G, density, restitution, mu;
+} dem_material;
+
+typedef struct {
+    double lo[3], hi[3]; /* box [m] */
+    uint32_t walls;      /* bit 2a: low face of axis a is a wall; bit 2a+1: high face */
+    uint32_t periodic;   /* bit a: axis a periodic (no wall on it) */
+    double gravity[3];   /* [m/s^2], added as m g ("ForceGravity") */
+    double shear_rate;   /* Lees-Edwards shear d(v_x)/dy [1/s]; needs x and y periodic; 0 = off */
+    double dt;           /* time step [s]; 0 = t_c/50, t_c the undamped head-on contact
+                            time of two spheres of the smallest radius at 0.1 m/s */
+    double time;         /* simulation time of the initial state [s] (shear offset) */
+    int32_t precision;   /* dem_precision */
+    int32_t kn_form;     /* 0: k_n with (2 - sigma^2)/E as printed in section 2;
+                            1: textbook Hertz (1 - sigma^2)/E */
+    double cell_size;    /* [m]; 0 = the largest contact distance 2 r_max.  Must be
+                            >= 2 r_max. */
+    uint64_t max_contacts; /* initial contact-table capacity; 0 = automatic */
+    uint32_t flags;        /* DEM_FLAG_* */
+    uint32_t reserved;
+} dem_params;
+
+#define DEM_FLAG_NO_FORCE_OUTPUT 1u /* do not store per-particle F, T each step */
+
+/* Diagnostics of a simulation (dem_get_info). */
+typedef struct {
+    uint64_t n;             /* particles */
+    uint64_t steps_done;    /* completed steps since dem_create */
+    double dt, time;        /* time step and current simulation time */
+    uint64_t contacts;      /* directed contacts (including faces) in the last step */
+    uint64_t capacity;      /* contact-table capacity */
+    uint64_t regrows;       /* capacity regrowths so far */
+    uint64_t sum_contacts;  /* sums over completed steps: contacts, */
+    uint64_t sum_matched;   /*   contacts that carried history from the step before, */
+    uint64_t sum_old;       /*   contacts of the step before */
+    uint32_t cells[3];      /* cell grid */
+    uint32_t key_bits;      /* bits of the cell key sorted each step */
+    uint64_t device_bytes;  /* device memory held */
+} dem_info;
+
+/*
+ * Create a simulation and upload its initial state (section 4.2: the CPU
+ * creates the initial configuration and sends it to the GPU).
+ *   params, mats[n_mats]   box, walls, gravity, time step, precision, materials
+ *   n                      particles (0 allowed)
+ *   x, v, w                (n,3) positions, velocities, angular velocities
+ *   radius                 (n) radii; FP32 so that sums of two radii are exact in FP64
+ *   mat_id                 (n) material index < n_mats, or NULL for all 0
+ *   stream                 hipStream_t to enqueue on, or NULL for the null stream
+ * On success *out receives the handle.  Returns DEM_EINVAL for a bad box,
+ * materials, radius, a particle id space over 2^32 - 16, fewer than 3 cells
+ * along a periodic axis, or a wall on a periodic axis.
+ */
+dem_status dem_create(const dem_params *params, const dem_material *mats, uint32_t n_mats,
+                      uint64_t n, const double *x, const double *v, const double *w,
+                      const float *radius, const uint16_t *mat_id, void *stream, dem_sim **out);
+
+/*
+ * Enqueue nsteps time steps on the simulation's stream and return.  One step
+ * is: contact detection over the 27 cells around each particle, contact
+ * history match, contact law (Eq. 1-4, torque), per-particle sums with
+ * gravity, semi-implicit Euler integration of velocity, position and angular
+ * velocity, cell hashing, radix sort by cell key and reorder into cell order.
+ */
+dem_status dem_step(dem_sim *sim, uint32_t nsteps);
+
+/* Wait for enqueued steps; handles capacity regrowth; reports device errors. */
+dem_status dem_sync(dem_sim *sim);
+
+/*
+ * Copy the current state to host buffers in pid order (blocking).  Any
+ * pointer may be NULL to skip it.  F, T are the per-particle force (with
+ * gravity) and torque used by the last completed step (zero before the
+ * first step or with DEM_FLAG_NO_FORCE_OUTPUT).
+ */
+dem_status dem_get_state(dem_sim *sim, double *x, double *v, double *w, double *F, double *T);
+
+/*
+ * Copy the contact history to host buffers (blocking): for every directed
+ * contact (i, j) of the last completed step, sorted by (i, j), its tangential
+ * displacement dt_xyz (3 doubles).  j is a pid or DEM_FACE_ID + f.  At most
+ * cap entries are written; *m receives the total count (call with cap = 0 to
+ * size the buffers).
+ */
+dem_status dem_get_contacts(dem_sim *sim, uint64_t cap, uint32_t *i, uint32_t *j, double *dt_xyz,
+                            uint64_t *m);
+
+/*
+ * Replace the contact history used by the next step (tests and resume).
+ * Entries need not be sorted; duplicate (i, j) pairs are rejected.
+ */
+dem_status dem_set_contacts(dem_sim *sim, uint64_t m, const uint32_t *i, const uint32_t *j,
+                            const double *dt_xyz);
+
+/* Replace positions, velocities, angular velocities (pid order); the contact
+ * history is kept. */
+dem_status dem_set_state(dem_sim *sim, const double *x, const double *v, const double *w);
+
+/* Diagnostics (blocking). */
+dem_status dem_get_info(dem_sim *sim, dem_info *info);
+
+/* Free the simulation and its device memory.  NULL is ignored. */
+void dem_destroy(dem_sim *sim);
+
+/* A static string for a status code. */
+const char *dem_status_str(dem_status s);
+
+/* Device bytes a simulation of n particles with these parameters needs at
+ * creation (contact table at its automatic initial capacity). */
+uint64_t dem_footprint(const dem_params *params, uint64_t n);
+
+/*
+ * Kernel timing.  dem_profile(sim, 1) makes every following dem_step record
+ * HIP events around each phase on the simulation's stream; dem_profile_read
+ * waits and returns, per phase, the summed milliseconds and the launch count
+ * since the last read (then resets).  Phases: 0 detect, 1 force (history
+ * match, contact law, sums, integration, hashing), 2 sort, 3 reorder.
+ */
+#define DEM_NPHASE 4
+dem_status dem_profile(dem_sim *sim, int enable);
+dem_status dem_profile_read(dem_sim *sim, double *ms, uint64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEM_H */

@@ -614,8 +614,8 @@ int orc_step(const orc_params *P, long n, double *x, double *v, double *w, const
         }
         for (int a = 0; a < 3; a += 2) {
             if (!(P->periodic & (1u << a))) continue;
-            while (x[3 * i + a] >= P->hi[a]) x[3 * i + a] -= L[a];
-            while (x[3 * i + a] < P->lo[a]) x[3 * i + a] += L[a];
+            for (int k = 0; k < 4 && x[3 * i + a] >= P->hi[a]; ++k) x[3 * i + a] -= L[a];
+            for (int k = 0; k < 4 && x[3 * i + a] < P->lo[a]; ++k) x[3 * i + a] += L[a];
         }
         if (F_out) for (int a = 0; a < 3; ++a) F_out[3 * i + a] = Fi[3 * i + a];
         if (T_out) for (int a = 0; a < 3; ++a) T_out[3 * i + a] = Ti[3 * i + a];

@@ -1,0 +1,12 @@
+"""MI355X DEM force step (Nakahara & Washizawa, arXiv:1503.03553) behind a C ABI.
+
+The compute path is libdem.so (HIP kernels for gfx950, see include/dem.h);
+this package only marshals arguments to it through ctypes.  There is no CPU
+fallback: importing works without the library, but creating a simulation
+raises if libdem.so is missing or no GPU is present.
+"""
+from .binding import (DEM_FACE_ID, DemError, Sim, lib, library_path, status_str,  # noqa: F401
+                      footprint, PREC_FP64, PREC_MIXED, FLAG_NO_FORCE_OUTPUT)
+
+__all__ = ["Sim", "DemError", "lib", "library_path", "status_str", "footprint", "DEM_FACE_ID",
+           "PREC_FP64", "PREC_MIXED", "FLAG_NO_FORCE_OUTPUT"]

@@ -1,0 +1,284 @@
+"""ctypes binding of libdem.so with the names of include/dem.h.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+library.  PyTorch is used, when given, only to supply the HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "libdem.so")
+
+DEM_FACE_ID = 0xFFFFFFF0
+MAX_MATERIALS = 8
+PREC_FP64 = 0
+PREC_MIXED = 1
+FLAG_NO_FORCE_OUTPUT = 1
+NPHASE = 4
+PHASES = ("detect", "force", "sort", "reorder")
+
+STATUS = {0: "DEM_OK", -1: "DEM_EINVAL", -2: "DEM_ENOMEM", -3: "DEM_ECAPACITY",
+          -4: "DEM_ENONFINITE", -5: "DEM_EDEVICE", -6: "DEM_EBUSY"}
+
+# every symbol include/dem.h declares
+EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state", "dem_get_contacts",
+           "dem_set_contacts", "dem_set_state", "dem_get_info", "dem_destroy", "dem_status_str",
+           "dem_footprint", "dem_profile", "dem_profile_read")
+
+
+class DemError(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, STATUS.get(code, "?"), code))
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("poisson", ctypes.c_double), ("G", ctypes.c_double),
+                ("density", ctypes.c_double), ("restitution", ctypes.c_double),
+                ("mu", ctypes.c_double)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("walls", ctypes.c_uint32), ("periodic", ctypes.c_uint32),
+                ("gravity", ctypes.c_double * 3), ("shear_rate", ctypes.c_double),
+                ("dt", ctypes.c_double), ("time", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("kn_form", ctypes.c_int32),
+                ("cell_size", ctypes.c_double), ("max_contacts", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("steps_done", ctypes.c_uint64), ("dt", ctypes.c_double),
+                ("time", ctypes.c_double), ("contacts", ctypes.c_uint64),
+                ("capacity", ctypes.c_uint64), ("regrows", ctypes.c_uint64),
+                ("sum_contacts", ctypes.c_uint64), ("sum_matched", ctypes.c_uint64),
+                ("sum_old", ctypes.c_uint64), ("cells", ctypes.c_uint32 * 3),
+                ("key_bits", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+
+
+_LIB = None
+_vp = ctypes.c_void_p
+
+
+def library_path() -> str:
+    return _SO
+
+
+def lib():
+    """Load libdem.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_SO):
+            raise RuntimeError("libdem.so not found at %s; run __graft_entry__.build() or "
+                               "python paper_1503_03553_amd/build.py" % _SO)
+        L = ctypes.CDLL(_SO)
+        P = ctypes.POINTER(Params)
+        L.dem_create.restype = ctypes.c_int
+        L.dem_create.argtypes = [P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp,
+                                 _vp, ctypes.POINTER(_vp)]
+        L.dem_step.restype = ctypes.c_int
+        L.dem_step.argtypes = [_vp, ctypes.c_uint32]
+        L.dem_sync.restype = ctypes.c_int
+        L.dem_sync.argtypes = [_vp]
+        L.dem_get_state.restype = ctypes.c_int
+        L.dem_get_state.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+        L.dem_get_contacts.restype = ctypes.c_int
+        L.dem_get_contacts.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, _vp,
+                                       ctypes.POINTER(ctypes.c_uint64)]
+        L.dem_set_contacts.restype = ctypes.c_int
+        L.dem_set_contacts.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, _vp]
+        L.dem_set_state.restype = ctypes.c_int
+        L.dem_set_state.argtypes = [_vp, _vp, _vp, _vp]
+        L.dem_get_info.restype = ctypes.c_int
+        L.dem_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
+        L.dem_destroy.restype = None
+        L.dem_destroy.argtypes = [_vp]
+        L.dem_status_str.restype = ctypes.c_char_p
+        L.dem_status_str.argtypes = [ctypes.c_int]
+        L.dem_footprint.restype = ctypes.c_uint64
+        L.dem_footprint.argtypes = [P, ctypes.c_uint64]
+        L.dem_profile.restype = ctypes.c_int
+        L.dem_profile.argtypes = [_vp, ctypes.c_int]
+        L.dem_profile_read.restype = ctypes.c_int
+        L.dem_profile_read.argtypes = [_vp, _vp, _vp]
+        _LIB = L
+    return _LIB
+
+
+def status_str(code: int) -> str:
+    return lib().dem_status_str(code).decode()
+
+
+def _check(code, what):
+    if code != 0:
+        raise DemError(code, what)
+
+
+def _c(a, dtype, shape=None):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+def make_params(lo, hi, walls=0x3F, periodic=0, gravity=(0.0, 0.0, -9.81), shear_rate=0.0,
+                dt=0.0, time=0.0, precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0,
+                flags=0) -> Params:
+    P = Params()
+    for a in range(3):
+        P.lo[a] = float(lo[a])
+        P.hi[a] = float(hi[a])
+        P.gravity[a] = float(gravity[a])
+    P.walls = int(walls)
+    P.periodic = int(periodic)
+    P.shear_rate = float(shear_rate)
+    P.dt = float(dt)
+    P.time = float(time)
+    P.precision = int(precision)
+    P.kn_form = int(kn_form)
+    P.cell_size = float(cell_size)
+    P.max_contacts = int(max_contacts)
+    P.flags = int(flags)
+    return P
+
+
+def footprint(params: Params, n: int) -> int:
+    return int(lib().dem_footprint(ctypes.byref(params), int(n)))
+
+
+class Sim:
+    """One simulation on the GPU (dem_create ... dem_destroy)."""
+
+    def __init__(self, lo, hi, x, v, w, r, materials, mat=None, walls=0x3F, periodic=0,
+                 gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
+                 precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0, flags=0,
+                 stream=None):
+        L = lib()
+        self.params = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time,
+                                  precision, kn_form, cell_size, max_contacts, flags)
+        x = _c(x, np.float64, (-1, 3))
+        n = x.shape[0]
+        v = _c(v, np.float64, (n, 3))
+        w = _c(w, np.float64, (n, 3))
+        r32 = _c(r, np.float32, (n,))
+        mats = (Material * len(materials))()
+        for k, m in enumerate(materials):
+            mats[k] = Material(m.E, m.poisson, m.G, m.density, m.restitution, m.mu)
+        mat16 = None if mat is None else _c(mat, np.uint16, (n,))
+        self.n = n
+        self._h = _vp()
+        self._keep = (x, v, w, r32, mats, mat16)
+        code = L.dem_create(ctypes.byref(self.params), ctypes.cast(mats, _vp), len(materials), n,
+                            x.ctypes.data, v.ctypes.data, w.ctypes.data, r32.ctypes.data,
+                            None if mat16 is None else mat16.ctypes.data,
+                            _stream_handle(stream), ctypes.byref(self._h))
+        self._keep = None
+        _check(code, "dem_create")
+
+    @classmethod
+    def from_scene(cls, sc, precision=PREC_FP64, **kw):
+        """Build from any object with the attributes of gen.Scene."""
+        args = dict(lo=sc.lo, hi=sc.hi, x=sc.x, v=sc.v, w=sc.w, r=sc.r, materials=sc.materials,
+                    mat=sc.mat if len(sc.materials) > 1 else None, walls=sc.walls,
+                    periodic=sc.periodic, gravity=sc.gravity, shear_rate=sc.shear_rate, dt=sc.dt,
+                    kn_form=sc.kn_form, precision=precision)
+        args.update(kw)
+        return cls(**args)
+
+    # -------------------------------------------------------------- calls
+    def _handle(self):
+        if not self._h:
+            raise RuntimeError("simulation destroyed")
+        return self._h
+
+    def step(self, k=1):
+        _check(lib().dem_step(self._handle(), int(k)), "dem_step")
+        return self
+
+    def sync(self):
+        _check(lib().dem_sync(self._handle()), "dem_sync")
+        return self
+
+    def get_state(self, forces=True):
+        n = self.n
+        x, v, w = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+        F = np.zeros((n, 3)) if forces else None
+        T = np.zeros((n, 3)) if forces else None
+        code = lib().dem_get_state(self._handle(), x.ctypes.data, v.ctypes.data, w.ctypes.data,
+                                   None if F is None else F.ctypes.data,
+                                   None if T is None else T.ctypes.data)
+        _check(code, "dem_get_state")
+        return dict(x=x, v=v, w=w, F=F, T=T)
+
+    def get_contacts(self):
+        m = ctypes.c_uint64()
+        _check(lib().dem_get_contacts(self._handle(), 0, None, None, None, ctypes.byref(m)),
+               "dem_get_contacts")
+        k = m.value
+        i = np.zeros(max(k, 1), np.uint32)
+        j = np.zeros(max(k, 1), np.uint32)
+        dt = np.zeros((max(k, 1), 3))
+        _check(lib().dem_get_contacts(self._handle(), k, i.ctypes.data, j.ctypes.data,
+                                      dt.ctypes.data, ctypes.byref(m)), "dem_get_contacts")
+        return i[:k], j[:k], dt[:k]
+
+    def set_contacts(self, i, j, dt):
+        i = _c(i, np.uint32)
+        j = _c(j, np.uint32)
+        dt = _c(dt, np.float64, (-1, 3))
+        _check(lib().dem_set_contacts(self._handle(), i.shape[0], i.ctypes.data, j.ctypes.data,
+                                      dt.ctypes.data), "dem_set_contacts")
+
+    def set_state(self, x, v, w):
+        x = _c(x, np.float64, (self.n, 3))
+        v = _c(v, np.float64, (self.n, 3))
+        w = _c(w, np.float64, (self.n, 3))
+        _check(lib().dem_set_state(self._handle(), x.ctypes.data, v.ctypes.data, w.ctypes.data),
+               "dem_set_state")
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(lib().dem_get_info(self._handle(), ctypes.byref(inf)), "dem_get_info")
+        out = {f: getattr(inf, f) for f, _ in Info._fields_}
+        out["cells"] = tuple(inf.cells)
+        return out
+
+    def profile(self, enable=True):
+        _check(lib().dem_profile(self._handle(), 1 if enable else 0), "dem_profile")
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(NPHASE)
+        cnt = np.zeros(NPHASE, np.uint64)
+        _check(lib().dem_profile_read(self._handle(), ms.ctypes.data, cnt.ctypes.data),
+               "dem_profile_read")
+        return {p: (float(ms[k]), int(cnt[k])) for k, p in enumerate(PHASES)}
+
+    def close(self):
+        if self._h:
+            lib().dem_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,100 @@
+// Internal definitions shared by the HIP kernels and the host runtime of libdem.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dem {
+
+constexpr int TILE = 128;                 // particles per detect / force workgroup (2 waves)
+constexpr uint32_t FACE = 0xFFFFFFF0u;    // partner code of box face f is FACE + f
+constexpr int MAXMAT = 8;
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 8;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+
+// device error bits
+constexpr uint32_t ERR_CAPACITY = 1u;     // contact table too small for this step
+constexpr uint32_t ERR_ROW = 2u;          // a particle has more contacts than the row buffer
+constexpr uint32_t ERR_NONFINITE = 4u;    // NaN / Inf in a force or the new state
+
+// Per material-pair constants of the contact law (section 2), computed on the
+// host in FP64 and kept in device memory.
+struct MatTable {
+    double kn_pref[MAXMAT * MAXMAT];  // k_n = kn_pref sqrt(r*)
+    double kt_pref[MAXMAT * MAXMAT];  // k_t = kt_pref sqrt(r* dn)
+    double alpha[MAXMAT * MAXMAT];    // damping prefactor alpha(eps_ij)
+    double mu[MAXMAT * MAXMAT];       // sliding friction mu_ij
+    double mass_pref[MAXMAT];         // m = mass_pref r^3  (rho 4/3 pi)
+};
+
+// Box, grid and step constants, passed by value to every kernel.
+struct Geo {
+    double lo[3], hi[3], L[3];
+    double inv_cell[3];
+    int nc[3];
+    uint32_t walls, periodic;
+    int le;                 // Lees-Edwards shear active
+    int key_bits;
+    double g[3];
+    double dt;
+    double le_shift;        // image offset along x at the start of the step
+    double le_shift_next;   // at the end of the step (used when wrapping)
+    double le_dv;           // shear_rate * L_y: image velocity along x
+};
+
+// Device-side status word (one per simulation).
+struct Status {
+    uint32_t err;
+    uint32_t need;          // largest tile contact count seen when a tile overflowed
+    unsigned long long steps_done;
+};
+
+// Running counters of one workgroup (one slot per tile, so no two
+// workgroups ever update the same word): contacts written, contacts that found
+// their history, contacts of the step before.
+struct TileStats {
+    unsigned long long m, matched, old;
+};
+
+// Sorted particle state: position + (radius bits | pid << 32) in one 32-byte
+// record, velocity and angular velocity in three 16-byte planes
+// (vx,vy) (vz,wx) (wy,wz), and a material byte.
+struct State {
+    double4* xr;
+    double2* vw;   // 3 planes of n
+    uint8_t* mat;  // may be null (one material)
+};
+
+__host__ __device__ inline uint64_t pack_meta(float r, uint32_t pid) {
+    union { float f; uint32_t u; } c;
+    c.f = r;
+    return (uint64_t)c.u | ((uint64_t)pid << 32);
+}
+
+}  // namespace dem
+
+// Launch wrappers (dem_kernels.hip)
+namespace dem {
+// The contact list is cut into one region of TILE * slots entries per tile of
+// TILE particles; a tile's contacts are compacted into its own region.
+void launch_detect(int kmax, const State& A, const uint2* cells, uint32_t n, const Geo& G,
+                   uint2* rows, uint32_t* col_j, uint32_t slots, TileStats* ts, Status* st,
+                   hipStream_t s);
+void launch_force(bool fp64, const State& A, const State& B, const uint2* rows,
+                  const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
+                  const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
+                  double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
+                  void* fo, const MatTable* mt, uint32_t n, const Geo& G, TileStats* ts,
+                  Status* st, hipStream_t s);
+void launch_hash(const State& B, uint32_t n, const Geo& G, uint32_t* keys, uint32_t* vals,
+                 hipStream_t s);
+// Sorts (keys, vals) by the low `bits` bits of keys; the result ends in
+// (keys_out, vals_out).  tmp buffers are the ping-pong partners.
+void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                       uint32_t n, int bits, uint32_t* tile_hist, uint32_t* digit_tot,
+                       uint32_t** keys_out, uint32_t** vals_out, const Status* st, hipStream_t s);
+void launch_reorder(const uint32_t* keys_s, const uint32_t* vals_s, const State& B, const State& A,
+                    uint32_t* prev, uint2* cells, uint32_t n, const Geo& G, Status* st,
+                    int count_step, hipStream_t s);
+size_t sort_hist_words(uint32_t n);
+}  // namespace dem
