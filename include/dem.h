@@ -53,7 +53,8 @@ typedef enum {
     DEM_ECAPACITY = -3,   /* contact table could not be grown */
     DEM_ENONFINITE = -4,  /* a force or state component became NaN/Inf */
     DEM_EDEVICE = -5,     /* a HIP runtime error */
-    DEM_EBUSY = -6        /* reserved */
+    DEM_EBUSY = -6        /* a pool has no room (particles, cells, job slots or key
+                             bits) for this job now; nothing was changed */
 } dem_status;
 
 typedef enum {
@@ -191,6 +192,94 @@ uint64_t dem_footprint(const dem_params *params, uint64_t n);
 #define DEM_NPHASE 4
 dem_status dem_profile(dem_sim *sim, int enable);
 dem_status dem_profile_read(dem_sim *sim, double *ms, uint64_t *launches);
+
+/* ===================================================================== pool
+ *
+ * A pool advances many independent simulations ("jobs") of uneven sizes with
+ * one set of kernel launches per step: the data-parallel decomposition of
+ * section 4.2 (one thread per particle, one workgroup per tile of particles)
+ * applied across jobs instead of within one.  Each job occupies whole
+ * 128-particle tiles, has its own box, walls, gravity, shear, time step,
+ * materials and contact history, and is bitwise independent of its
+ * neighbours: a job gives the same results alone (dem_create) as in any mix.
+ * All jobs of a pool share one precision.  Jobs run for a fixed number of
+ * steps; a finished or failed job stays frozen in the pool until removed.
+ * Admission (dem_pool_add) and removal happen between steps, so new jobs can
+ * join while others run (continuous batching).
+ */
+typedef struct dem_pool dem_pool; /* opaque, owned by the library */
+
+typedef struct {
+    uint64_t max_particles;  /* particle positions (rounded up to 128-particle tiles) */
+    uint64_t max_cells;      /* cell-table entries shared by all jobs' grids */
+    uint32_t max_jobs;       /* job slots */
+    int32_t precision;       /* dem_precision of every job */
+    uint32_t contact_slots;  /* initial contact slots per particle position; 0 = 8 */
+    uint32_t flags;          /* DEM_FLAG_* */
+} dem_pool_params;
+
+typedef enum { DEM_JOB_RUNNING = 0, DEM_JOB_DONE = 1, DEM_JOB_FAILED = 2 } dem_job_status;
+
+typedef struct {
+    int32_t status;       /* dem_job_status; FAILED = a non-finite force or state */
+    uint32_t reserved;
+    uint64_t n;           /* particles */
+    uint64_t steps_done;  /* completed steps */
+    uint64_t steps_left;  /* steps still to run */
+    double time, dt;      /* simulation time and time step */
+} dem_job_info;
+
+/* Device bytes dem_pool_create allocates for these parameters. */
+uint64_t dem_pool_footprint(const dem_pool_params *pp);
+
+/* Create an empty pool with all its device memory (no allocation happens in
+ * later calls unless the contact table must grow).  stream as in dem_create. */
+dem_status dem_pool_create(const dem_pool_params *pp, void *stream, dem_pool **out);
+
+/*
+ * Admit one job that will run `steps` steps (1 .. 2^32 - 2).  Arguments are
+ * those of dem_create; params->precision must equal the pool's,
+ * params->max_contacts and params->flags are ignored (the pool's apply).  The
+ * upload is enqueued on the pool's stream.  On success *job receives an id
+ * unique within the pool.  DEM_EBUSY: not enough contiguous free tiles,
+ * cells or slots, or the pool's sort key would exceed 32 bits.
+ */
+dem_status dem_pool_add(dem_pool *pool, const dem_params *params, const dem_material *mats,
+                        uint32_t n_mats, uint64_t n, const double *x, const double *v,
+                        const double *w, const float *radius, const uint16_t *mat_id,
+                        uint32_t steps, uint64_t *job);
+
+/* Enqueue nsteps steps of every running job (finished jobs are skipped). */
+dem_status dem_pool_step(dem_pool *pool, uint32_t nsteps);
+
+/* Wait for enqueued steps; capacity regrowth as in dem_sync.  A job's
+ * non-finite failure is not a pool error: it shows as DEM_JOB_FAILED. */
+dem_status dem_pool_sync(dem_pool *pool);
+
+/* Wait, then write up to cap ids of jobs that finished or failed since the
+ * last poll; *n_done receives the count written. */
+dem_status dem_pool_poll(dem_pool *pool, uint64_t *done, uint32_t cap, uint32_t *n_done);
+
+/* Status, step counts and time of a job (blocking). */
+dem_status dem_pool_job_info(dem_pool *pool, uint64_t job, dem_job_info *info);
+
+/* A job's state in pid order, as dem_get_state (blocking); NULL skips. */
+dem_status dem_pool_get_state(dem_pool *pool, uint64_t job, double *x, double *v, double *w);
+
+/* Free a job's tiles, cells and slot (between steps; enqueued in order). */
+dem_status dem_pool_remove(dem_pool *pool, uint64_t job);
+
+/* Room for the next job: the largest contiguous run of free particle
+ * positions and of free cells, and the free job slots.  NULL skips. */
+dem_status dem_pool_capacity(dem_pool *pool, uint64_t *free_particles, uint64_t *free_cells,
+                             uint32_t *free_jobs);
+
+/* Kernel timing of the pool's steps, as dem_profile / dem_profile_read. */
+dem_status dem_pool_profile(dem_pool *pool, int enable);
+dem_status dem_pool_profile_read(dem_pool *pool, double *ms, uint64_t *launches);
+
+/* Free the pool and its device memory.  NULL is ignored. */
+void dem_pool_destroy(dem_pool *pool);
 
 #ifdef __cplusplus
 }

@@ -27,7 +27,13 @@ STATUS = {0: "DEM_OK", -1: "DEM_EINVAL", -2: "DEM_ENOMEM", -3: "DEM_ECAPACITY",
 # every symbol include/dem.h declares
 EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state", "dem_get_contacts",
            "dem_set_contacts", "dem_set_state", "dem_get_info", "dem_destroy", "dem_status_str",
-           "dem_footprint", "dem_profile", "dem_profile_read")
+           "dem_footprint", "dem_profile", "dem_profile_read", "dem_pool_footprint",
+           "dem_pool_create", "dem_pool_add", "dem_pool_step", "dem_pool_sync", "dem_pool_poll",
+           "dem_pool_job_info", "dem_pool_get_state", "dem_pool_remove", "dem_pool_capacity",
+           "dem_pool_profile", "dem_pool_profile_read", "dem_pool_destroy")
+
+JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2
+JOB_STATUS = {JOB_RUNNING: "running", JOB_DONE: "done", JOB_FAILED: "failed"}
 
 
 class DemError(RuntimeError):
@@ -59,6 +65,18 @@ class Info(ctypes.Structure):
                 ("sum_contacts", ctypes.c_uint64), ("sum_matched", ctypes.c_uint64),
                 ("sum_old", ctypes.c_uint64), ("cells", ctypes.c_uint32 * 3),
                 ("key_bits", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+
+
+class PoolParams(ctypes.Structure):
+    _fields_ = [("max_particles", ctypes.c_uint64), ("max_cells", ctypes.c_uint64),
+                ("max_jobs", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("contact_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_uint32), ("n", ctypes.c_uint64),
+                ("steps_done", ctypes.c_uint64), ("steps_left", ctypes.c_uint64),
+                ("time", ctypes.c_double), ("dt", ctypes.c_double)]
 
 
 _LIB = None
@@ -106,6 +124,36 @@ def lib():
         L.dem_profile.argtypes = [_vp, ctypes.c_int]
         L.dem_profile_read.restype = ctypes.c_int
         L.dem_profile_read.argtypes = [_vp, _vp, _vp]
+        PP = ctypes.POINTER(PoolParams)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.dem_pool_footprint.restype = ctypes.c_uint64
+        L.dem_pool_footprint.argtypes = [PP]
+        L.dem_pool_create.restype = ctypes.c_int
+        L.dem_pool_create.argtypes = [PP, _vp, ctypes.POINTER(_vp)]
+        L.dem_pool_add.restype = ctypes.c_int
+        L.dem_pool_add.argtypes = [_vp, P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp,
+                                   _vp, _vp, ctypes.c_uint32, u64p]
+        L.dem_pool_step.restype = ctypes.c_int
+        L.dem_pool_step.argtypes = [_vp, ctypes.c_uint32]
+        L.dem_pool_sync.restype = ctypes.c_int
+        L.dem_pool_sync.argtypes = [_vp]
+        L.dem_pool_poll.restype = ctypes.c_int
+        L.dem_pool_poll.argtypes = [_vp, _vp, ctypes.c_uint32, u32p]
+        L.dem_pool_job_info.restype = ctypes.c_int
+        L.dem_pool_job_info.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(JobInfo)]
+        L.dem_pool_get_state.restype = ctypes.c_int
+        L.dem_pool_get_state.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, _vp]
+        L.dem_pool_remove.restype = ctypes.c_int
+        L.dem_pool_remove.argtypes = [_vp, ctypes.c_uint64]
+        L.dem_pool_capacity.restype = ctypes.c_int
+        L.dem_pool_capacity.argtypes = [_vp, u64p, u64p, u32p]
+        L.dem_pool_profile.restype = ctypes.c_int
+        L.dem_pool_profile.argtypes = [_vp, ctypes.c_int]
+        L.dem_pool_profile_read.restype = ctypes.c_int
+        L.dem_pool_profile_read.argtypes = [_vp, _vp, _vp]
+        L.dem_pool_destroy.restype = None
+        L.dem_pool_destroy.argtypes = [_vp]
         _LIB = L
     return _LIB
 
@@ -269,6 +317,140 @@ class Sim:
     def close(self):
         if self._h:
             lib().dem_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def make_pool_params(max_particles, max_cells, max_jobs, precision=PREC_MIXED, contact_slots=0,
+                     flags=0) -> PoolParams:
+    pp = PoolParams()
+    pp.max_particles = int(max_particles)
+    pp.max_cells = int(max_cells)
+    pp.max_jobs = int(max_jobs)
+    pp.precision = int(precision)
+    pp.contact_slots = int(contact_slots)
+    pp.flags = int(flags)
+    return pp
+
+
+def pool_footprint(pp: PoolParams) -> int:
+    return int(lib().dem_pool_footprint(ctypes.byref(pp)))
+
+
+class Pool:
+    """Many simulations advanced by shared launches (dem_pool_*)."""
+
+    def __init__(self, max_particles, max_cells, max_jobs, precision=PREC_MIXED, contact_slots=0,
+                 flags=0, stream=None):
+        self.params = make_pool_params(max_particles, max_cells, max_jobs, precision,
+                                       contact_slots, flags)
+        self.precision = int(precision)
+        self._h = _vp()
+        self._n = {}
+        _check(lib().dem_pool_create(ctypes.byref(self.params), _stream_handle(stream),
+                                     ctypes.byref(self._h)), "dem_pool_create")
+
+    def _handle(self):
+        if not self._h:
+            raise RuntimeError("pool destroyed")
+        return self._h
+
+    def add(self, lo, hi, x, v, w, r, materials, steps, mat=None, walls=0x3F, periodic=0,
+            gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0, kn_form=0,
+            cell_size=0.0) -> int:
+        P = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time, self.precision,
+                        kn_form, cell_size)
+        x = _c(x, np.float64, (-1, 3))
+        n = x.shape[0]
+        v = _c(v, np.float64, (n, 3))
+        w = _c(w, np.float64, (n, 3))
+        r32 = _c(r, np.float32, (n,))
+        mats = (Material * len(materials))()
+        for k, m in enumerate(materials):
+            mats[k] = Material(m.E, m.poisson, m.G, m.density, m.restitution, m.mu)
+        mat16 = None if mat is None else _c(mat, np.uint16, (n,))
+        job = ctypes.c_uint64()
+        _check(lib().dem_pool_add(self._handle(), ctypes.byref(P), ctypes.cast(mats, _vp),
+                                  len(materials), n, x.ctypes.data, v.ctypes.data, w.ctypes.data,
+                                  r32.ctypes.data, None if mat16 is None else mat16.ctypes.data,
+                                  int(steps), ctypes.byref(job)), "dem_pool_add")
+        self._n[job.value] = n
+        return job.value
+
+    def add_scene(self, sc, steps, **kw) -> int:
+        args = dict(lo=sc.lo, hi=sc.hi, x=sc.x, v=sc.v, w=sc.w, r=sc.r, materials=sc.materials,
+                    mat=sc.mat if len(sc.materials) > 1 else None, walls=sc.walls,
+                    periodic=sc.periodic, gravity=sc.gravity, shear_rate=sc.shear_rate, dt=sc.dt,
+                    kn_form=sc.kn_form)
+        args.update(kw)
+        return self.add(steps=steps, **args)
+
+    def step(self, k=1):
+        _check(lib().dem_pool_step(self._handle(), int(k)), "dem_pool_step")
+        return self
+
+    def sync(self):
+        _check(lib().dem_pool_sync(self._handle()), "dem_pool_sync")
+        return self
+
+    def poll(self, cap=None):
+        cap = len(self._n) if cap is None else int(cap)
+        out = np.zeros(max(cap, 1), np.uint64)
+        k = ctypes.c_uint32()
+        _check(lib().dem_pool_poll(self._handle(), out.ctypes.data, cap, ctypes.byref(k)),
+               "dem_pool_poll")
+        return [int(j) for j in out[:k.value]]
+
+    def job_info(self, job) -> dict:
+        inf = JobInfo()
+        _check(lib().dem_pool_job_info(self._handle(), int(job), ctypes.byref(inf)),
+               "dem_pool_job_info")
+        out = {f: getattr(inf, f) for f, _ in JobInfo._fields_ if f != "reserved"}
+        out["status"] = JOB_STATUS.get(inf.status, inf.status)
+        return out
+
+    def get_state(self, job):
+        n = self._n[int(job)]
+        x, v, w = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 3))
+        _check(lib().dem_pool_get_state(self._handle(), int(job), x.ctypes.data, v.ctypes.data,
+                                        w.ctypes.data), "dem_pool_get_state")
+        return dict(x=x, v=v, w=w)
+
+    def remove(self, job):
+        _check(lib().dem_pool_remove(self._handle(), int(job)), "dem_pool_remove")
+        self._n.pop(int(job), None)
+
+    def capacity(self) -> dict:
+        p, c = ctypes.c_uint64(), ctypes.c_uint64()
+        j = ctypes.c_uint32()
+        _check(lib().dem_pool_capacity(self._handle(), ctypes.byref(p), ctypes.byref(c),
+                                       ctypes.byref(j)), "dem_pool_capacity")
+        return dict(particles=p.value, cells=c.value, jobs=j.value)
+
+    def profile(self, enable=True):
+        _check(lib().dem_pool_profile(self._handle(), 1 if enable else 0), "dem_pool_profile")
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(NPHASE)
+        cnt = np.zeros(NPHASE, np.uint64)
+        _check(lib().dem_pool_profile_read(self._handle(), ms.ctypes.data, cnt.ctypes.data),
+               "dem_pool_profile_read")
+        return {p: (float(ms[k]), int(cnt[k])) for k, p in enumerate(PHASES)}
+
+    def close(self):
+        if self._h:
+            lib().dem_pool_destroy(self._h)
             self._h = _vp()
 
     def __del__(self):

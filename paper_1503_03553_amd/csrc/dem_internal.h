@@ -5,7 +5,9 @@
 
 namespace dem {
 
-constexpr int TILE = 128;                 // particles per detect / force workgroup (2 waves)
+constexpr int TILE = 128;                 // particles per force workgroup (2 waves)
+constexpr int DTILE = TILE;               // particles per detect workgroup; also the unit of
+                                          // the contact list's regions
 constexpr uint32_t FACE = 0xFFFFFFF0u;    // partner code of box face f is FACE + f
 constexpr int MAXMAT = 8;
 constexpr int SORT_THREADS = 256;
@@ -31,18 +33,42 @@ struct MatTable {
 struct Geo {
     double lo[3], hi[3], L[3];
     double inv_cell[3];
+    double inv_L[3];        // 1 / L, for the minimum-image choice
     int nc[3];
     uint32_t walls, periodic;
     int le;                 // Lees-Edwards shear active
-    int key_bits;
+    int key_bits;           // bits of the cell key
+    int xbits;              // bits of its x part (the fastest-varying index)
     double g[3];
     double dt;
-    double le_shift;        // image offset along x at the start of the step
-    double le_shift_next;   // at the end of the step (used when wrapping)
+    double le_shift;        // image offset along x at the start of the next step
+    double le_shift_next;   // at its end (used when wrapping); both advanced by the
+                            // end-of-step kernel
     double le_dv;           // shear_rate * L_y: image velocity along x
 };
 
-// Device-side status word (one per simulation).
+// One simulation of a pool (device-resident).  Its particles occupy the
+// tile-aligned positions [p0, p0 + n) (the rest of its last tile are inactive
+// "ghost" slots), its cell bounds start at cell_base, its materials are
+// MatTable number `mat`.  Time, remaining steps, shear offsets and status
+// advance on the device, in the end-of-step kernel only: within the other
+// kernels of a step the descriptor is read-only.
+constexpr uint32_t NO_JOB = 0xFFFFFFFFu;
+constexpr uint32_t JOB_ACTIVE = 0u, JOB_DONE = 1u, JOB_FAILED = 2u;
+struct Job {
+    Geo g;
+    double t;                      // simulation time at the start of the next step
+    float margin;                  // FP32 pre-filter margin of the contact search
+    uint32_t p0, n;
+    uint32_t cell_base;
+    uint32_t mat;
+    uint32_t status;               // JOB_*
+    uint32_t steps_left;
+    uint32_t pad;
+    unsigned long long steps_done;
+};
+
+// Device-side status word (one per pool).
 struct Status {
     uint32_t err;
     uint32_t need;          // largest tile contact count seen when a tile overflowed
@@ -63,6 +89,8 @@ struct State {
     double4* xr;
     double2* vw;   // 3 planes of n
     uint8_t* mat;  // may be null (one material)
+    float4* xf;    // sorted state only: (x - lo, y - lo, z - lo) in FP32 and the radius,
+                   // the compact record the contact search pre-filters on
 };
 
 __host__ __device__ inline uint64_t pack_meta(float r, uint32_t pid) {
@@ -73,28 +101,42 @@ __host__ __device__ inline uint64_t pack_meta(float r, uint32_t pid) {
 
 }  // namespace dem
 
-// Launch wrappers (dem_kernels.hip)
+// Launch wrappers (dem_kernels.hip).  `ntiles` tiles of TILE positions are
+// processed; tile T belongs to job tile_job[T] (NO_JOB for a free tile) and
+// carries the high key bits tile_key[T] of its segment; `ns` is the position
+// capacity (the plane stride of the velocity and force arrays).
 namespace dem {
-// The contact list is cut into one region of TILE * slots entries per tile of
-// TILE particles; a tile's contacts are compacted into its own region.
-void launch_detect(int kmax, const State& A, const uint2* cells, uint32_t n, const Geo& G,
-                   uint2* rows, uint32_t* col_j, uint32_t slots, TileStats* ts, Status* st,
-                   hipStream_t s);
-void launch_force(bool fp64, const State& A, const State& B, const uint2* rows,
+struct PoolView {
+    const Job* jobs;
+    uint32_t* job_fail;            // per job: set on a non-finite force or state
+    const uint32_t* tile_job;
+    const uint32_t* tile_key;
+    uint32_t ntiles;
+    uint32_t ns;
+    uint32_t lmask;                // local key bits: (1 << local bits) - 1
+    const MatTable* mats;
+    TileStats* ts;
+    Status* st;
+    bool any_periodic;
+};
+// FP32 pre-filter margin of the contact search for a box of this geometry.
+float detect_margin(const Geo& G);
+void launch_detect(const PoolView& P, int kmax, const State& A, const uint2* cells, uint2* rows,
+                   uint32_t* col_j, uint32_t slots, hipStream_t s);
+void launch_force(const PoolView& P, bool fp64, const State& A, const State& B, const uint2* rows,
                   const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
                   const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
                   double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
-                  void* fo, const MatTable* mt, uint32_t n, const Geo& G, TileStats* ts,
-                  Status* st, hipStream_t s);
-void launch_hash(const State& B, uint32_t n, const Geo& G, uint32_t* keys, uint32_t* vals,
-                 hipStream_t s);
+                  void* fo, hipStream_t s);
 // Sorts (keys, vals) by the low `bits` bits of keys; the result ends in
 // (keys_out, vals_out).  tmp buffers are the ping-pong partners.
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                        uint32_t n, int bits, uint32_t* tile_hist, uint32_t* digit_tot,
                        uint32_t** keys_out, uint32_t** vals_out, const Status* st, hipStream_t s);
-void launch_reorder(const uint32_t* keys_s, const uint32_t* vals_s, const State& B, const State& A,
-                    uint32_t* prev, uint2* cells, uint32_t n, const Geo& G, Status* st,
-                    int count_step, hipStream_t s);
+void launch_reorder(const PoolView& P, const uint32_t* keys_s, const uint32_t* vals_s,
+                    const State& B, const State& A, uint32_t* prev, uint2* cells, hipStream_t s);
+void launch_tick(const PoolView& P, Job* jobs, uint32_t njobs, hipStream_t s);
+// Shear offset of the image along x at time t: D(t) = (shear_rate L_y t) mod L_x.
+double le_offset(const Geo& G, double t);
 size_t sort_hist_words(uint32_t n);
 }  // namespace dem

@@ -22,6 +22,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <cmath>
+
 #include "dem_internal.h"
 
 namespace dem {
@@ -49,53 +52,71 @@ __device__ inline int cell_coord(const Geo& G, double x, int a) {
     return (int)f;
 }
 
-__device__ inline uint32_t spread3(uint32_t v) {
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
+// Cell key: Morton (bit-interleaved) order over the (y, z) rows of cells,
+// with the x index as the fastest-varying part.  Rows that are close in
+// (y, z) stay close in memory, and the three x-neighbouring cells of a row
+// are consecutive keys, so their particles form one contiguous range.
+__device__ inline uint32_t spread2(uint32_t v) {
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
     return v;
 }
-__device__ inline uint32_t compact3(uint32_t v) {
-    v &= 0x09249249u;
-    v = (v ^ (v >> 2)) & 0x030C30C3u;
-    v = (v ^ (v >> 4)) & 0x0300F00Fu;
-    v = (v ^ (v >> 8)) & 0xFF0000FFu;
-    v = (v ^ (v >> 16)) & 0x000003FFu;
+__device__ inline uint32_t compact2(uint32_t v) {
+    v &= 0x55555555u;
+    v = (v ^ (v >> 1)) & 0x33333333u;
+    v = (v ^ (v >> 2)) & 0x0F0F0F0Fu;
+    v = (v ^ (v >> 4)) & 0x00FF00FFu;
+    v = (v ^ (v >> 8)) & 0x0000FFFFu;
     return v;
-}
-__device__ inline uint32_t morton(int cx, int cy, int cz) {
-    return spread3((uint32_t)cx) | (spread3((uint32_t)cy) << 1) | (spread3((uint32_t)cz) << 2);
 }
 __device__ inline uint32_t cell_key(const Geo& G, double x, double y, double z) {
-    return morton(cell_coord(G, x, 0), cell_coord(G, y, 1), cell_coord(G, z, 2));
+    const uint32_t cx = (uint32_t)cell_coord(G, x, 0), cy = (uint32_t)cell_coord(G, y, 1),
+                   cz = (uint32_t)cell_coord(G, z, 2);
+    return ((spread2(cy) | (spread2(cz) << 1)) << G.xbits) | cx;
 }
 __device__ inline uint32_t key_lin(const Geo& G, uint32_t key) {
-    uint32_t cx = compact3(key), cy = compact3(key >> 1), cz = compact3(key >> 2);
+    const uint32_t cx = key & ((1u << G.xbits) - 1u), m = key >> G.xbits;
+    const uint32_t cy = compact2(m), cz = compact2(m >> 1);
     return (cz * (uint32_t)G.nc[1] + cy) * (uint32_t)G.nc[0] + cx;
 }
 
 // Image of partner j that can touch i: periodic copies by minimum image, the
 // Lees-Edwards copy across y carrying the shear offset along x.  Returns the
-// shift S added to the raw difference x_j - x_i and the y-image index.
+// shift S added to the raw difference x_j - x_i and the y-image index.  For a
+// touching pair |d + k L| < L / 3, so rounding d / L (here d times 1 / L) to
+// the nearest integer picks the same image however it is rounded.
 __device__ inline void image_shift(const Geo& G, double dx, double dy, double dz, double& Sx,
                                    double& Sy, double& Sz, int& ky) {
     ky = 0;
     Sx = Sy = Sz = 0.0;
     if (G.periodic & 2u) {
-        ky = -(int)rint(dy / G.L[1]);
+        ky = -(int)rint(dy * G.inv_L[1]);
         Sy = (double)ky * G.L[1];
     }
     if (G.periodic & 1u) {
         double dxp = dx + (double)ky * G.le_shift;
-        int kx = -(int)rint(dxp / G.L[0]);
+        int kx = -(int)rint(dxp * G.inv_L[0]);
         Sx = (double)kx * G.L[0] + (double)ky * G.le_shift;
     }
     if (G.periodic & 4u) {
-        int kz = -(int)rint(dz / G.L[2]);
+        int kz = -(int)rint(dz * G.inv_L[2]);
         Sz = (double)kz * G.L[2];
     }
+}
+
+// The FP32 record of the contact search: position relative to the box corner
+// and radius.  Within 3 box lengths of the corner the float rounding error is
+// bounded (see detect_margin); a particle further out gets NaN coordinates,
+// which make every pre-filter comparison involving it pass.
+__device__ inline float4 far_record(const Geo& G, const double4& p) {
+    const double rx = p.x - G.lo[0], ry = p.y - G.lo[1], rz = p.z - G.lo[2];
+    const bool near = fabs(rx) <= 3.0 * G.L[0] && fabs(ry) <= 3.0 * G.L[1] && fabs(rz) <= 3.0 * G.L[2];
+    const float q = __int_as_float(0x7fc00000);
+    return near ? make_float4((float)rx, (float)ry, (float)rz, meta_r(p.w))
+                : make_float4(q, q, q, meta_r(p.w));
 }
 
 // The contact predicate on FP64 positions, written out with no fused
@@ -113,7 +134,20 @@ __device__ inline uint32_t skip_if_error(const Status* st, uint32_t* s_flag) {
     return *s_flag;
 }
 
-// Exclusive scan of v over the workgroup (blockDim = TILE = 2 waves).
+// The running job of a tile, or null for a free tile or a job that is
+// finished or failed.  The descriptor is read through a restrict-qualified
+// kernel argument at a workgroup-uniform address, so its fields come in
+// through scalar loads and stay in registers.
+__device__ inline const Job* tile_job(const Job* __restrict__ jobs, const PoolView& P,
+                                      uint32_t tile, uint32_t& jb) {
+    jb = P.tile_job[tile];
+    if (jb == NO_JOB) return nullptr;
+    const Job* J = jobs + jb;
+    return J->status == JOB_ACTIVE ? J : nullptr;
+}
+
+// Exclusive scan of v over a workgroup of NW waves.
+template <int NW>
 __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t& total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t x = v;
@@ -124,14 +158,20 @@ __device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* s_w, uint32_t& 
     }
     if (lane == 63) s_w[w] = x;
     __syncthreads();
-    uint32_t off = (w == 1) ? s_w[0] : 0u;
-    total = s_w[0] + s_w[1];
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        off += (k < w) ? s_w[k] : 0u;
+        tot += s_w[k];
+    }
+    total = tot;
     return x - v + off;
 }
 
-// Largest o in [0, TILE) with e[o] <= q, for e non-decreasing with e[0] = 0.
+// Largest o in [0, NT) with e[o] <= q, for e non-decreasing with e[0] = 0.
+template <int NT = TILE>
 __device__ inline int owner_of(const uint32_t* e, uint32_t q) {
-    int lo = 0, hi = TILE;
+    int lo = 0, hi = NT;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
         if (e[mid] <= q) lo = mid;
@@ -141,99 +181,243 @@ __device__ inline int owner_of(const uint32_t* e, uint32_t q) {
 }
 
 // ------------------------------------------------------------------ detect
-template <int KMAX>
-__global__ __launch_bounds__(TILE) void k_detect(const double4* __restrict__ xr,
-                                                 const uint2* __restrict__ cells, uint32_t n,
-                                                 Geo G, uint2* __restrict__ rows,
-                                                 uint32_t* __restrict__ col_j, uint32_t slots,
-                                                 TileStats* __restrict__ ts, Status* st) {
-    __shared__ uint32_t s_pid[KMAX * TILE];
-    __shared__ uint32_t s_j[KMAX * TILE];
-    __shared__ uint32_t s_excl[TILE + 1];
-    __shared__ uint32_t s_w[2];
+// Particles [lo, hi) of the non-empty cells among up to three consecutive
+// cells of a row (consecutive keys, hence one contiguous range).
+__device__ inline void merge_range(uint2 c, uint32_t& lo, uint32_t& hi) {
+    if (c.y > c.x) {
+        lo = c.x < lo ? c.x : lo;
+        hi = c.y > hi ? c.y : hi;
+    }
+}
+
+// One lane per particle, DTILE consecutive particles (cell order) per
+// workgroup.  The lane scans the 27 cells around its particle as 9 contiguous
+// ranges: in each (y, z) row the three x-neighbouring cells are consecutive
+// cell keys (plus, across a periodic x boundary, one wrapped cell).  All 27
+// cell bounds are loaded before any is used.
+//
+// Candidates are read as one 16-byte FP32 record each (position relative to
+// the box corner, radius) and pre-filtered with a margin that covers the
+// float rounding, so the pre-filter never rejects a pair that touches in FP64.
+// The survivors (the contacts plus rare near misses) are kept in LDS and then
+// take the exact FP64 test on the original positions, four loads in flight,
+// which keeps the contact set exactly the FP64 one.  Hits go into the lane's
+// LDS row in partner-id order; box faces come last; the workgroup compacts its
+// rows into its own region of the contact list.
+template <int KMAX, bool PER>
+__global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restrict__ jobs,
+                                                  const double4* __restrict__ xr,
+                                                  const float4* __restrict__ xf,
+                                                  const uint2* __restrict__ cells,
+                                                  uint2* __restrict__ rows,
+                                                  uint32_t* __restrict__ col_j, uint32_t slots) {
+    constexpr int NW = DTILE / 64;
+    __shared__ uint32_t s_pid[KMAX * DTILE];
+    __shared__ uint32_t s_j[KMAX * DTILE];
+    __shared__ uint2 s_win[18 * DTILE];  // this lane's non-empty candidate ranges
+    __shared__ uint32_t s_excl[DTILE + 1];
+    __shared__ uint32_t s_w[NW];
     __shared__ uint32_t s_base, s_flag;
+    Status* st = P.st;
     if (skip_if_error(st, &s_flag)) return;
 
     const int t = threadIdx.x;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t i = tile * TILE + t;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) return;
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const float margin = J.margin;
+    cells += J.cell_base;
+    const uint32_t i = tile * DTILE + t;
+    const bool act = i < J.p0 + J.n;
+    const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+    const bool px = G.periodic & 1u, py = G.periodic & 2u, pz = G.periodic & 4u;
+
     uint32_t cnt = 0;
-    if (i < n) {
+    if (act) {
         const double4 a = xr[i];
         const double ri = (double)meta_r(a.w);
         const int cx = cell_coord(G, a.x, 0), cy = cell_coord(G, a.y, 1), cz = cell_coord(G, a.z, 2);
-        for (int oz = -1; oz <= 1; ++oz) {
-            int qz = cz + oz;
-            if (qz < 0 || qz >= G.nc[2]) {
-                if (!(G.periodic & 4u)) continue;
-                qz = qz < 0 ? qz + G.nc[2] : qz - G.nc[2];
-            }
-            for (int oy = -1; oy <= 1; ++oy) {
-                int qy = cy + oy, kyc = 0;
-                if (qy < 0 || qy >= G.nc[1]) {
-                    if (!(G.periodic & 2u)) continue;
-                    kyc = qy < 0 ? -1 : 1;
-                    qy -= kyc * G.nc[1];
+        // the 9 rows: main range [wlo, whi) and wrapped cell [plo, phi)
+        uint32_t wlo[9], whi[9], plo[9], phi[9];
+        {
+            uint32_t il[9], im[9], ih[9];
+            bool okl[9], okm[9], okh[9], wrl[9], wrh[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int oz = k / 3 - 1, oy = k % 3 - 1;
+                int qz = cz + oz, qy = cy + oy, kyc = 0;
+                bool ok = true;
+                if (qz < 0 || qz >= nz) {
+                    if (!pz) ok = false;
+                    qz = qz < 0 ? qz + nz : qz - nz;
                 }
-                // across a sheared y boundary the partner row is offset along x
+                if (qy < 0 || qy >= ny) {
+                    if (!py) ok = false;
+                    kyc = qy < 0 ? -1 : 1;
+                    qy -= kyc * ny;
+                }
                 int cxq = cx;
                 if (G.le && kyc != 0) {
+                    // across a sheared y boundary the partner row is offset along x
                     double fx = floor((a.x - (double)kyc * G.le_shift - G.lo[0]) * G.inv_cell[0]);
-                    const double lim = 2.0 * (double)G.nc[0];
+                    const double lim = 2.0 * (double)nx;
                     if (!(fx >= -lim)) fx = -lim;  // also NaN
                     if (fx > lim) fx = lim;
-                    cxq = (int)fx;
+                    cxq = (int)fx % nx;
+                    if (cxq < 0) cxq += nx;
                 }
-                for (int ox = -1; ox <= 1; ++ox) {
-                    int qx = cxq + ox;
-                    if (qx < 0 || qx >= G.nc[0]) {
-                        if (!(G.periodic & 1u)) continue;
-                        qx %= G.nc[0];
-                        if (qx < 0) qx += G.nc[0];
+                int xl = cxq - 1, xh = cxq + 1;
+                okl[k] = okh[k] = okm[k] = ok;
+                wrl[k] = wrh[k] = false;
+                if (xl < 0) {
+                    if (px) { xl += nx; wrl[k] = true; } else okl[k] = false;
+                }
+                if (xh >= nx) {
+                    if (px) { xh -= nx; wrh[k] = true; } else okh[k] = false;
+                }
+                const uint32_t row = ok ? ((uint32_t)qz * (uint32_t)ny + (uint32_t)qy) * (uint32_t)nx : 0u;
+                il[k] = okl[k] ? row + (uint32_t)xl : 0u;
+                im[k] = ok ? row + (uint32_t)cxq : 0u;
+                ih[k] = okh[k] ? row + (uint32_t)xh : 0u;
+            }
+            uint2 cl[9], cm[9], cr[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                cl[k] = cells[il[k]];
+                cm[k] = cells[im[k]];
+                cr[k] = cells[ih[k]];
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const uint2 z = make_uint2(0, 0);
+                const uint2 l = okl[k] ? cl[k] : z, m = okm[k] ? cm[k] : z, h = okh[k] ? cr[k] : z;
+                uint32_t lo = 0xFFFFFFFFu, hi = 0u, lo2 = 0xFFFFFFFFu, hi2 = 0u;
+                merge_range(m, lo, hi);
+                if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
+                if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
+                wlo[k] = lo;
+                whi[k] = hi;
+                plo[k] = lo2;
+                phi[k] = hi2;
+            }
+        }
+
+        // non-empty ranges to LDS, so one flat loop walks all candidates
+        uint32_t nw = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            if (whi[k] > wlo[k]) s_win[(nw++) * DTILE + t] = make_uint2(wlo[k], whi[k]);
+            if (phi[k] > plo[k]) s_win[(nw++) * DTILE + t] = make_uint2(plo[k], phi[k]);
+        }
+
+        // FP32 pre-filter: never rejects a pair that touches in FP64 (NaN
+        // records of particles far from the box always pass)
+        const float4 me = far_record(G, a);
+        const float Lx = (float)G.L[0], Ly = (float)G.L[1], Lz = (float)G.L[2], Df = (float)G.le_shift;
+        const float iLx = (float)G.inv_L[0], iLy = (float)G.inv_L[1], iLz = (float)G.inv_L[2];
+        const float rm = me.w + margin;
+        auto pre = [&](const float4& b) {
+            float dx = b.x - me.x, dy = b.y - me.y, dz = b.z - me.z;
+            if (PER) {
+                int ky = 0;
+                if (G.periodic & 2u) {
+                    ky = -(int)rintf(dy * iLy);
+                    dy += (float)ky * Ly;
+                }
+                if (G.periodic & 1u) {
+                    const int kx = -(int)rintf((dx + (float)ky * Df) * iLx);
+                    dx += (float)kx * Lx + (float)ky * Df;
+                }
+                if (G.periodic & 4u) dz += (float)(-(int)rintf(dz * iLz)) * Lz;
+            }
+            const float sm = rm + b.w;
+            return !(dx * dx + dy * dy + dz * dz >= sm * sm);
+        };
+        // pass 1: one flat loop over all candidates of all ranges, the next
+        // candidate's record already in flight; survivors go unsorted into
+        // the row buffer
+        uint32_t sc = 0;
+        if (nw > 0) {
+            uint32_t w = 0;
+            uint2 rg = s_win[t];
+            uint32_t j = rg.x;
+            float4 bn = xf[j];
+            for (;;) {
+                const float4 b = bn;
+                const uint32_t jc = j;
+                bool more = true;
+                if (++j == rg.y) {
+                    if (++w < nw) {
+                        rg = s_win[w * DTILE + t];
+                        j = rg.x;
+                    } else {
+                        more = false;
                     }
-                    const uint2 rg = cells[(qz * G.nc[1] + qy) * G.nc[0] + qx];
-                    for (uint32_t j = rg.x; j < rg.y; ++j) {
-                        if (j == i) continue;
-                        const double4 b = xr[j];
-                        double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                        if (G.periodic) {
-                            double Sx, Sy, Sz;
-                            int ky;
-                            image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
-                            dx = dx + Sx;
-                            dy = dy + Sy;
-                            dz = dz + Sz;
+                }
+                if (more) bn = xf[j];
+                if (jc != i && pre(b)) {
+                    if (sc < KMAX) s_j[sc * DTILE + t] = jc;
+                    ++sc;
+                }
+                if (!more) break;
+            }
+        }
+        if (sc > KMAX) {
+            cnt = KMAX + 1;  // row buffer too small: reported below
+        } else {
+            // pass 2: exact FP64 test of the survivors, two loads in flight;
+            // a hit goes into the row in partner-id order (insertion only
+            // writes slots below the next survivors to be read)
+            for (uint32_t q0 = 0; q0 < sc; q0 += 2) {
+                uint32_t jj[2];
+                double4 bb[2];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) jj[m] = q0 + m < sc ? s_j[(q0 + m) * DTILE + t] : 0xFFFFFFFFu;
+#pragma unroll
+                for (int m = 0; m < 2; ++m) bb[m] = xr[jj[m] != 0xFFFFFFFFu ? jj[m] : i];
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    if (jj[m] == 0xFFFFFFFFu) continue;
+                    const double4 b = bb[m];
+                    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                    if (PER) {
+                        double Sx, Sy, Sz;
+                        int ky;
+                        image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                        dx = dx + Sx;
+                        dy = dy + Sy;
+                        dz = dz + Sz;
+                    }
+                    if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
+                        const uint32_t pj = meta_pid(b.w);
+                        int k = (int)cnt;
+                        while (k > 0 && s_pid[(k - 1) * DTILE + t] > pj) {
+                            s_pid[k * DTILE + t] = s_pid[(k - 1) * DTILE + t];
+                            s_j[k * DTILE + t] = s_j[(k - 1) * DTILE + t];
+                            --k;
                         }
-                        const double s = ri + (double)meta_r(b.w);
-                        if (touching(dx, dy, dz, s)) {
-                            if (cnt < KMAX) {
-                                const uint32_t pj = meta_pid(b.w);
-                                int k = (int)cnt;
-                                while (k > 0 && s_pid[(k - 1) * TILE + t] > pj) {
-                                    s_pid[k * TILE + t] = s_pid[(k - 1) * TILE + t];
-                                    s_j[k * TILE + t] = s_j[(k - 1) * TILE + t];
-                                    --k;
-                                }
-                                s_pid[k * TILE + t] = pj;
-                                s_j[k * TILE + t] = j;
-                            }
-                            ++cnt;
-                        }
+                        s_pid[k * DTILE + t] = pj;
+                        s_j[k * DTILE + t] = jj[m];
+                        ++cnt;
                     }
                 }
             }
         }
         // box faces last, in face order (their ids sort after every particle)
-        if (G.walls) {
-            const double p[3] = {a.x, a.y, a.z};
+        if (G.walls && cnt <= KMAX) {
+#pragma unroll
             for (int f = 0; f < 6; ++f) {
                 if (!(G.walls & (1u << f))) continue;
                 const int ax = f >> 1;
-                const double dist = (f & 1) ? G.hi[ax] - p[ax] : p[ax] - G.lo[ax];
+                const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+                const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
                 if (dist < ri) {
                     if (cnt < KMAX) {
-                        s_pid[cnt * TILE + t] = FACE + (uint32_t)f;
-                        s_j[cnt * TILE + t] = FACE + (uint32_t)f;
+                        s_pid[cnt * DTILE + t] = FACE + (uint32_t)f;
+                        s_j[cnt * DTILE + t] = FACE + (uint32_t)f;
                     }
                     ++cnt;
                 }
@@ -245,28 +429,28 @@ __global__ __launch_bounds__(TILE) void k_detect(const double4* __restrict__ xr,
         }
     }
     uint32_t total;
-    const uint32_t excl = block_excl_scan(cnt, s_w, total);
+    const uint32_t excl = block_excl_scan<NW>(cnt, s_w, total);
     s_excl[t] = excl;
     if (t == 0) {
-        // the tile's own region of the contact list: no device-wide counter
-        s_excl[TILE] = total;
-        uint32_t base = tile * (uint32_t)TILE * slots;
-        if (total > (uint32_t)TILE * slots) {
+        // the workgroup's own region of the contact list: no device-wide counter
+        s_excl[DTILE] = total;
+        uint32_t base = tile * (uint32_t)DTILE * slots;
+        if (total > (uint32_t)DTILE * slots) {
             atomicOr(&st->err, ERR_CAPACITY);
             atomicMax(&st->need, total);
             base = 0xFFFFFFFFu;
         } else {
-            ts[tile].m += total;
+            P.ts[tile].m += total;
         }
         s_base = base;
     }
     __syncthreads();
     const uint32_t base = s_base;
     if (base == 0xFFFFFFFFu) return;
-    if (i < n) rows[i] = make_uint2(base + excl, cnt);
-    for (uint32_t q = t; q < total; q += TILE) {
-        const int o = owner_of(s_excl, q);
-        col_j[base + q] = s_j[(q - s_excl[o]) * TILE + o];
+    if (act) rows[i] = make_uint2(base + excl, cnt);
+    for (uint32_t q = t; q < total; q += DTILE) {
+        const int o = owner_of<DTILE>(s_excl, q);
+        col_j[base + q] = s_j[(q - s_excl[o]) * DTILE + o];
     }
 }
 
@@ -327,8 +511,7 @@ __global__ __launch_bounds__(TILE) void k_force(
     const uint32_t* __restrict__ tab_pid_old, const double* __restrict__ tab_dt_old,
     uint32_t* __restrict__ tab_pid_new, double* __restrict__ tab_dt_new, uint64_t cap,
     uint2* __restrict__ cells, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    R* __restrict__ fo, const MatTable* __restrict__ mt, uint32_t n, Geo G,
-    TileStats* __restrict__ ts, Status* st) {
+    R* __restrict__ fo, PoolView P, const Job* __restrict__ jobs) {
     __shared__ double4 s_x[TILE];
     __shared__ double2 s_vw[3][TILE];
     __shared__ uint2 s_old[TILE];
@@ -337,12 +520,32 @@ __global__ __launch_bounds__(TILE) void k_force(
     __shared__ uint8_t s_mat[TILE];
     __shared__ uint32_t s_base, s_total, s_flag;
     __shared__ uint32_t s_red[4];
+    Status* st = P.st;
     if (skip_if_error(st, &s_flag)) return;
 
     const int t = threadIdx.x;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t p0 = tile * TILE;
+    const uint32_t ns = P.ns;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) {
+        // not running: keys that keep every position of the tile in place
+        keys[p0 + t] = P.tile_key[tile] | P.lmask;
+        vals[p0 + t] = p0 + t;
+        return;
+    }
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const MatTable* __restrict__ mt = P.mats + J.mat;
+    cells += J.cell_base;
     const uint32_t i = p0 + t;
+    const uint32_t n = J.p0 + J.n;  // end of the job's particles
+    if (i >= n) {
+        // ghost slot after the job's last particle: sorts last, stays in place
+        keys[i] = P.tile_key[tile] | P.lmask;
+        vals[i] = i;
+    }
     const uint32_t nt = (n - p0) < (uint32_t)TILE ? (n - p0) : (uint32_t)TILE;
     uint2 row = make_uint2(0, 0);
     uint2 orow = make_uint2(0, 0);
@@ -351,8 +554,8 @@ __global__ __launch_bounds__(TILE) void k_force(
         orow = rows_old[prev[i]];
         s_x[t] = xr[i];
         s_vw[0][t] = vw[i];
-        s_vw[1][t] = vw[n + i];
-        s_vw[2][t] = vw[2 * (size_t)n + i];
+        s_vw[1][t] = vw[ns + i];
+        s_vw[2][t] = vw[2 * (size_t)ns + i];
         s_mat[t] = mat ? mat[i] : (uint8_t)0;
     }
     s_old[t] = orow;
@@ -390,7 +593,7 @@ __global__ __launch_bounds__(TILE) void k_force(
             if (code < FACE) {
                 const uint32_t j = code;
                 const double4 b = xr[j];
-                const double2 b0 = vw[j], b1 = vw[n + j], b2 = vw[2 * (size_t)n + j];
+                const double2 b0 = vw[j], b1 = vw[ns + j], b2 = vw[2 * (size_t)ns + j];
                 mj = mat ? mat[j] : 0;
                 pid_j = meta_pid(b.w);
                 const double rjd = (double)meta_r(b.w);
@@ -505,8 +708,8 @@ __global__ __launch_bounds__(TILE) void k_force(
         }
         __syncthreads();
         if (t == 0) {
-            ts[tile].matched += s_red[0] + s_red[2];
-            ts[tile].old += s_red[1] + s_red[3];
+            P.ts[tile].matched += s_red[0] + s_red[2];
+            P.ts[tile].old += s_red[1] + s_red[3];
         }
     }
     if (i >= n) return;
@@ -553,36 +756,26 @@ __global__ __launch_bounds__(TILE) void k_force(
     const bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) &&
                         isfinite(vy) && isfinite(vz) && isfinite(wx) && isfinite(wy) &&
                         isfinite(wz);
-    if (!finite) atomicOr(&st->err, ERR_NONFINITE);
+    if (!finite) atomicOr(&P.job_fail[jb], 1u);
     xr_b[i] = make_double4(x, y, z, a.w);
     vw_b[i] = make_double2(vx, vy);
-    vw_b[n + i] = make_double2(vz, wx);
-    vw_b[2 * (size_t)n + i] = make_double2(wy, wz);
+    vw_b[ns + i] = make_double2(vz, wx);
+    vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
     if (mat_b) mat_b[i] = (uint8_t)mi;
-    keys[i] = cell_key(G, x, y, z);
+    keys[i] = P.tile_key[tile] | cell_key(G, x, y, z);
     vals[i] = i;
     if (fo) {
         fo[i] = (R)Fx;
-        fo[n + i] = (R)Fy;
-        fo[2 * (size_t)n + i] = (R)Fz;
-        fo[3 * (size_t)n + i] = acc[3];
-        fo[4 * (size_t)n + i] = acc[4];
-        fo[5 * (size_t)n + i] = acc[5];
+        fo[ns + i] = (R)Fy;
+        fo[2 * (size_t)ns + i] = (R)Fz;
+        fo[3 * (size_t)ns + i] = acc[3];
+        fo[4 * (size_t)ns + i] = acc[4];
+        fo[5 * (size_t)ns + i] = acc[5];
     }
     // the first particle of its (old) cell empties the cell's bounds; the
     // reorder kernel writes the bounds of the new order
     const uint32_t lin = key_lin(G, cell_key(G, a.x, a.y, a.z));
     if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
-}
-
-// ------------------------------------------------------------------ hash
-__global__ void k_hash(const double4* __restrict__ xr, uint32_t n, Geo G, uint32_t* keys,
-                       uint32_t* vals) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double4 a = xr[i];
-    keys[i] = cell_key(G, a.x, a.y, a.z);
-    vals[i] = i;
 }
 
 // ------------------------------------------------------------- radix sort
@@ -710,68 +903,114 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 }
 
 // ------------------------------------------------------------------ reorder
-__global__ void k_reorder(const uint32_t* __restrict__ keys_s, const uint32_t* __restrict__ vals_s,
-                          const double4* __restrict__ xr_b, const double2* __restrict__ vw_b,
-                          const uint8_t* __restrict__ mat_b, double4* __restrict__ xr,
-                          double2* __restrict__ vw, uint8_t* __restrict__ mat,
-                          uint32_t* __restrict__ prev, uint2* __restrict__ cells, uint32_t n, Geo G,
-                          Status* st, int count_step) {
+// One workgroup per tile.  Positions of free tiles, of jobs that are not
+// running and ghost slots kept their place in the sort and are left alone.
+__global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restrict__ jobs,
+                                                  const uint32_t* __restrict__ keys_s,
+                                                  const uint32_t* __restrict__ vals_s,
+                                                  const double4* __restrict__ xr_b,
+                                                  const double2* __restrict__ vw_b,
+                                                  const uint8_t* __restrict__ mat_b,
+                                                  double4* __restrict__ xr, float4* __restrict__ xf,
+                                                  double2* __restrict__ vw,
+                                                  uint8_t* __restrict__ mat,
+                                                  uint32_t* __restrict__ prev,
+                                                  uint2* __restrict__ cells) {
     __shared__ uint32_t s_flag;
-    if (skip_if_error(st, &s_flag)) return;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0 && count_step) st->steps_done += 1;
-    if (i >= n) return;
+    if (skip_if_error(P.st, &s_flag)) return;
+    const uint32_t tile = blockIdx.x;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) return;
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const uint32_t i = tile * TILE + threadIdx.x;
+    const uint32_t end = J.p0 + J.n;
+    if (i >= end) return;
+    const uint32_t ns = P.ns;
     const uint32_t src = vals_s[i];
-    xr[i] = xr_b[src];
+    const double4 p = xr_b[src];
+    xr[i] = p;
+    xf[i] = far_record(G, p);
     vw[i] = vw_b[src];
-    vw[n + i] = vw_b[n + src];
-    vw[2 * (size_t)n + i] = vw_b[2 * (size_t)n + src];
+    vw[ns + i] = vw_b[ns + src];
+    vw[2 * (size_t)ns + i] = vw_b[2 * (size_t)ns + src];
     if (mat) mat[i] = mat_b[src];
     prev[i] = src;
     const uint32_t key = keys_s[i];
-    const uint32_t lin = key_lin(G, key);
-    if (i == 0 || keys_s[i - 1] != key) cells[lin].x = i;
-    if (i == n - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
+    const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
+    if (i == J.p0 || keys_s[i - 1] != key) cells[lin].x = i;
+    if (i == end - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
+}
+
+// End of a step: the running jobs advance their time, step count and shear
+// offsets; a job that produced a non-finite state is marked failed.
+__global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
+    if (__atomic_load_n(&P.st->err, __ATOMIC_RELAXED)) return;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) P.st->steps_done += 1;
+    if (k >= njobs) return;
+    Job& J = jobs[k];
+    if (J.status != JOB_ACTIVE) return;
+    if (P.job_fail[k]) {
+        J.status = JOB_FAILED;
+        return;
+    }
+    const double t = J.t + J.g.dt;
+    J.t = t;
+    if (J.g.le) {
+        J.g.le_shift = fmod(J.g.le_dv * t, J.g.L[0]);
+        J.g.le_shift_next = fmod(J.g.le_dv * (t + J.g.dt), J.g.L[0]);
+    }
+    J.steps_done += 1;
+    if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
 }
 
 // ------------------------------------------------------------------ launch
-void launch_detect(int kmax, const State& A, const uint2* cells, uint32_t n, const Geo& G,
-                   uint2* rows, uint32_t* col_j, uint32_t slots, TileStats* ts, Status* st,
-                   hipStream_t s) {
-    if (n == 0) return;
-    const uint32_t nb = (n + TILE - 1) / TILE;
-    if (kmax <= 16)
-        hipLaunchKernelGGL(k_detect<16>, dim3(nb), dim3(TILE), 0, s, A.xr, cells, n, G, rows,
-                           col_j, slots, ts, st);
-    else
-        hipLaunchKernelGGL(k_detect<64>, dim3(nb), dim3(TILE), 0, s, A.xr, cells, n, G, rows,
-                           col_j, slots, ts, st);
+// The pre-filter compares float distances of positions within 3 box lengths
+// of the corner: every float coordinate, difference, image shift and sum is
+// off by at most a few 2^-24 of 3 L, so 48 such units plus 2^-20 of the
+// largest contact distance bound the error of the float distance with a wide
+// safety factor.
+float detect_margin(const Geo& G) {
+    const double Lm = std::max(G.L[0], std::max(G.L[1], G.L[2]));
+    const double dmax = 2.0 / std::min(G.inv_cell[0], std::min(G.inv_cell[1], G.inv_cell[2]));
+    return (float)(48.0 * 3.0 * Lm * 0x1p-24 + dmax * 0x1p-20);
 }
 
-void launch_force(bool fp64, const State& A, const State& B, const uint2* rows,
+void launch_detect(const PoolView& P, int kmax, const State& A, const uint2* cells, uint2* rows,
+                   uint32_t* col_j, uint32_t slots, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
+#define DEM_DETECT(K, PER)                                                                        \
+    hipLaunchKernelGGL((k_detect<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs, A.xr, A.xf,   \
+                       cells, rows, col_j, slots)
+    const bool per = P.any_periodic;
+    if (kmax <= 8) {
+        if (per) DEM_DETECT(8, true); else DEM_DETECT(8, false);
+    } else if (kmax <= 16) {
+        if (per) DEM_DETECT(16, true); else DEM_DETECT(16, false);
+    } else {
+        if (per) DEM_DETECT(32, true); else DEM_DETECT(32, false);
+    }
+#undef DEM_DETECT
+}
+
+void launch_force(const PoolView& P, bool fp64, const State& A, const State& B, const uint2* rows,
                   const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
                   const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
                   double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
-                  void* fo, const MatTable* mt, uint32_t n, const Geo& G, TileStats* ts,
-                  Status* st, hipStream_t s) {
-    if (n == 0) return;
-    const uint32_t nb = (n + TILE - 1) / TILE;
+                  void* fo, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
     if (fp64)
         hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, A.xr, A.vw, A.mat, B.xr,
                            B.vw, B.mat, rows, col_j, rows_old, prev, tab_pid_old, tab_dt_old,
-                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, mt, n, G,
-                           ts, st);
+                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, P, P.jobs);
     else
         hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, A.xr, A.vw, A.mat, B.xr,
                            B.vw, B.mat, rows, col_j, rows_old, prev, tab_pid_old, tab_dt_old,
-                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, mt, n, G,
-                           ts, st);
-}
-
-void launch_hash(const State& B, uint32_t n, const Geo& G, uint32_t* keys, uint32_t* vals,
-                 hipStream_t s) {
-    if (n == 0) return;
-    hipLaunchKernelGGL(k_hash, dim3((n + 255) / 256), dim3(256), 0, s, B.xr, n, G, keys, vals);
+                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs);
 }
 
 size_t sort_hist_words(uint32_t n) {
@@ -804,12 +1043,18 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
     *vals_out = vi;
 }
 
-void launch_reorder(const uint32_t* keys_s, const uint32_t* vals_s, const State& B, const State& A,
-                    uint32_t* prev, uint2* cells, uint32_t n, const Geo& G, Status* st,
-                    int count_step, hipStream_t s) {
-    const uint32_t nb = n ? (n + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_reorder, dim3(nb), dim3(256), 0, s, keys_s, vals_s, B.xr, B.vw, B.mat,
-                       A.xr, A.vw, A.mat, prev, cells, n, G, st, count_step);
+void launch_reorder(const PoolView& P, const uint32_t* keys_s, const uint32_t* vals_s,
+                    const State& B, const State& A, uint32_t* prev, uint2* cells, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    hipLaunchKernelGGL(k_reorder, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, keys_s, vals_s, B.xr, B.vw,
+                       B.mat, A.xr, A.xf, A.vw, A.mat, prev, cells);
 }
+
+void launch_tick(const PoolView& P, Job* jobs, uint32_t njobs, hipStream_t s) {
+    const uint32_t nb = (njobs + 255) / 256;
+    hipLaunchKernelGGL(k_tick, dim3(nb ? nb : 1), dim3(256), 0, s, P, jobs, njobs);
+}
+
+double le_offset(const Geo& G, double t) { return G.le ? std::fmod(G.le_dv * t, G.L[0]) : 0.0; }
 
 }  // namespace dem

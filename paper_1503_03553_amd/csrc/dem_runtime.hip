@@ -1,11 +1,14 @@
-// Host runtime of libdem: validation, device memory, the step pipeline,
-// capacity regrowth, state and contact-history transfer, and the C ABI
-// declared in include/dem.h.
+// Host runtime of libdem: validation, device memory, the job pool (several
+// independent simulations advanced by the same kernel launches), the step
+// pipeline with capacity regrowth, state and contact-history transfer, and
+// the C ABI declared in include/dem.h.  A single simulation (dem_sim) is a
+// pool holding one job.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -18,6 +21,7 @@ using namespace dem;
 namespace {
 
 constexpr double PI = 3.14159265358979323846;
+constexpr uint64_t MAX_ENTRIES = 0xFFFFFFF0ull;  // row starts and positions are 32-bit
 
 // Damping prefactor alpha(eps) (section 2 defines eta = alpha(eps) sqrt(m* k_n
 // sqrt(dn)) without giving alpha).  For the normal force k_n d^(3/2) + eta d',
@@ -38,6 +42,15 @@ double hertz_contact_time(double mstar, double kn, double v0) {
     return c * std::pow(mstar / kn, 0.4) * std::pow(v0, -0.2);
 }
 
+uint32_t spread2_host(uint32_t v) {
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
 struct Buf {
     void* p = nullptr;
     size_t bytes = 0;
@@ -47,32 +60,65 @@ struct ProfEv {
     hipEvent_t e[2 * DEM_NPHASE];
 };
 
-}  // namespace
+struct Layout {
+    int nc[3];
+    double cell[3];
+    int key_bits, xbits;
+};
 
-struct dem_sim {
+// One contiguous run of tiles (a job's segment or a free gap).
+struct Seg {
+    uint32_t start, len;
+    int slot;  // job slot, -1 when free
+};
+
+struct HostJob {
+    bool used = false;
+    uint64_t id = 0;
     dem_params P{};
     std::vector<dem_material> mats;
     uint64_t n = 0;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    bool fp64 = true;
-    int kmax = 16;
+    uint32_t tile0 = 0, ntiles = 0;
+    uint32_t cell_base = 0, ncells = 0;
+    Layout lay{};
     Geo geo{};
-    double dt = 0.0;
-    double time_done = 0.0;            // simulation time after the last confirmed step
-    uint64_t steps_confirmed = 0;      // steps known to have completed
-    uint64_t steps_enqueued = 0;
-    std::vector<double> t_pending;     // start time of each enqueued, unconfirmed step
-    uint32_t slots = 0;                // contact slots per particle of each tile's region
-    uint64_t cap = 0;                  // ntiles * TILE * slots
-    uint64_t regrows = 0;
-    bool table_by_pid = true;          // old table indexed by pid (after create / set_contacts)
-    dem_status failed = DEM_OK;
+    bool multi_mat = false;
+    bool hist_in_A = true;    // contact history indexed by the sorted order (else by the
+                              // order before the last reorder)
+    bool reported = false;    // finished/failed status already returned by poll
     std::vector<float> r;
     std::vector<uint16_t> mat;
-    size_t ncells = 0;
+};
+
+uint64_t tiles_of(uint64_t n) { return (n + TILE - 1) / TILE; }
+
+}  // namespace
+
+struct dem_pool {
+    hipStream_t stream = nullptr;
+    bool fp64 = false;
+    uint32_t flags = 0;
+    int kmax = 8;                     // row buffer of the detect kernel (8, 16 or 32)
+    uint32_t slots = 8;               // contact slots per position
+    uint64_t cap = 0;                 // max_tiles * TILE * slots
+    uint32_t max_tiles = 0, max_jobs = 0;
+    uint64_t max_cells = 0;
+    uint32_t hw_tiles = 0;            // tiles processed per step (high-water mark)
+    int lb = 1;                       // local key bits
+    bool any_periodic = false, any_multi_mat = false;
+    std::vector<Seg> segs;            // tile segments in memory order
+    std::vector<std::pair<uint64_t, uint64_t>> free_cells;  // (start, len)
+    std::vector<HostJob> jobs;        // by slot
+    uint64_t next_id = 1;
+    int cur = 0;                      // table/rows buffer read as "old" by the next step
+    std::deque<int> pending;          // buffer parity of each enqueued, unconfirmed step
+    uint64_t steps_confirmed = 0;
+    uint64_t regrows = 0;
+    dem_status failed = DEM_OK;
+    std::vector<std::vector<char>> staging;  // host buffers of uploads in flight
     // device memory
     std::vector<Buf> bufs;
+    size_t device_bytes = 0;
     State A{}, B{};
     uint2* cells = nullptr;
     uint2* rows[2] = {nullptr, nullptr};
@@ -84,15 +130,22 @@ struct dem_sim {
     uint32_t* tile_hist = nullptr;
     uint32_t* digit_tot = nullptr;
     void* fo = nullptr;
-    MatTable* mt = nullptr;
-    Status* st = nullptr;
+    MatTable* mats = nullptr;
+    Job* jobs_d = nullptr;
+    uint32_t* job_fail = nullptr;
+    uint32_t* tile_job = nullptr;
+    uint32_t* tile_key = nullptr;
     TileStats* ts = nullptr;
-    uint32_t ntiles = 0;
-    size_t device_bytes = 0;
+    Status* st = nullptr;
     // profiling
     bool prof = false;
     std::vector<ProfEv> prof_ev;
     size_t prof_used = 0;
+};
+
+struct dem_sim {
+    dem_pool* pool = nullptr;
+    int slot = 0;
 };
 
 namespace {
@@ -103,13 +156,13 @@ dem_status hip_status(hipError_t e) {
     return DEM_EDEVICE;
 }
 
-#define HIPCHK(x)                                   \
-    do {                                            \
-        hipError_t e_ = (x);                        \
+#define HIPCHK(x)                                    \
+    do {                                             \
+        hipError_t e_ = (x);                         \
         if (e_ != hipSuccess) return hip_status(e_); \
     } while (0)
 
-dem_status dalloc(dem_sim* s, size_t bytes, void** out) {
+dem_status dalloc(dem_pool* s, size_t bytes, void** out) {
     void* p = nullptr;
     if (bytes == 0) bytes = 256;
     hipError_t e = hipMalloc(&p, bytes);
@@ -123,7 +176,7 @@ dem_status dalloc(dem_sim* s, size_t bytes, void** out) {
     return DEM_OK;
 }
 
-void dfree(dem_sim* s, void* p) {
+void dfree(dem_pool* s, void* p) {
     if (!p) return;
     for (size_t k = 0; k < s->bufs.size(); ++k)
         if (s->bufs[k].p == p) {
@@ -135,18 +188,19 @@ void dfree(dem_sim* s, void* p) {
 }
 
 template <typename T>
-dem_status dalloc_t(dem_sim* s, size_t count, T** out) {
+dem_status dalloc_t(dem_pool* s, size_t count, T** out) {
     void* p;
     dem_status r = dalloc(s, count * sizeof(T), &p);
     if (r == DEM_OK) *out = (T*)p;
     return r;
 }
 
-double le_offset(const dem_sim* s, double t) {
-    if (s->P.shear_rate == 0.0) return 0.0;
-    const double Lx = s->P.hi[0] - s->P.lo[0], Ly = s->P.hi[1] - s->P.lo[1];
-    const double u = s->P.shear_rate * Ly;
-    return std::fmod(u * t, Lx);
+// Asynchronous upload whose host copy stays alive until the next sync.
+dem_status upload(dem_pool* s, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return DEM_OK;
+    s->staging.emplace_back((const char*)src, (const char*)src + bytes);
+    HIPCHK(hipMemcpyAsync(dst, s->staging.back().data(), bytes, hipMemcpyHostToDevice, s->stream));
+    return DEM_OK;
 }
 
 // Per-pair constants of the contact law.
@@ -168,12 +222,6 @@ void fill_mat_table(const dem_params& P, const std::vector<dem_material>& m, Mat
     }
 }
 
-struct Layout {
-    int nc[3];
-    double cell[3];
-    int key_bits;
-};
-
 // Uniform grid whose cells are at least the largest contact distance wide
 // along every axis, so that the 27 cells around a particle hold all its
 // possible partners.  At most max(4 n, 4096) cells: in dilute boxes the cells
@@ -185,7 +233,6 @@ dem_status plan_grid(const dem_params& P, double rmax, uint64_t n, Layout& out) 
     const uint64_t limit = std::max<uint64_t>(4 * n, 4096);
     for (int iter = 0; iter < 2000; ++iter) {
         uint64_t prod = 1;
-        int maxc = 1;
         for (int a = 0; a < 3; ++a) {
             const double L = P.hi[a] - P.lo[a];
             double c = std::floor(L / (want * 1.000001));
@@ -194,7 +241,6 @@ dem_status plan_grid(const dem_params& P, double rmax, uint64_t n, Layout& out) 
             out.nc[a] = (int)c;
             out.cell[a] = L / c;
             prod *= (uint64_t)c;
-            maxc = std::max(maxc, (int)c);
         }
         if (prod > limit) {
             want *= 1.02;
@@ -202,341 +248,19 @@ dem_status plan_grid(const dem_params& P, double rmax, uint64_t n, Layout& out) 
         }
         for (int a = 0; a < 3; ++a)
             if (((P.periodic >> a) & 1u) && out.nc[a] < 3) return DEM_EINVAL;
-        int b = 0;
-        while ((1 << b) < maxc) ++b;
-        out.key_bits = 3 * b;
+        auto bits = [](int c) {
+            int b = 0;
+            while ((1 << b) < c) ++b;
+            return b;
+        };
+        out.xbits = bits(out.nc[0]);
+        out.key_bits = out.xbits + 2 * std::max(bits(out.nc[1]), bits(out.nc[2]));
         return DEM_OK;
     }
     return DEM_EINVAL;
 }
 
-constexpr uint64_t MAX_ENTRIES = 0xFFFFFFF0ull;  // row starts are 32-bit
-
-uint64_t tiles_of(uint64_t n) { return n ? (n + TILE - 1) / TILE : 1; }
-
-dem_status alloc_contacts(dem_sim* s, uint32_t slots) {
-    const uint64_t cap = tiles_of(s->n) * TILE * (uint64_t)slots;
-    if (cap > MAX_ENTRIES) return DEM_ECAPACITY;
-    dem_status r;
-    if ((r = dalloc_t(s, cap, &s->col_j)) != DEM_OK) return r;
-    for (int k = 0; k < 2; ++k) {
-        if ((r = dalloc_t(s, cap, &s->tab_pid[k])) != DEM_OK) return r;
-        if ((r = dalloc_t(s, 3 * (size_t)cap, &s->tab_dt[k])) != DEM_OK) return r;
-    }
-    s->cap = cap;
-    s->slots = slots;
-    return DEM_OK;
-}
-
-// Contact slots per particle: from max_contacts when given, else 8.
-uint32_t initial_slots(const dem_params& P, uint64_t n) {
-    if (P.max_contacts) {
-        uint64_t sl = (P.max_contacts + tiles_of(n) * TILE - 1) / (tiles_of(n) * TILE);
-        return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(sl, 1024));
-    }
-    return 8;
-}
-
-State state_view(void* xr, void* vw, void* mat) {
-    State S;
-    S.xr = (double4*)xr;
-    S.vw = (double2*)vw;
-    S.mat = (uint8_t*)mat;
-    return S;
-}
-
-void set_step_geo(dem_sim* s, double t) {
-    s->geo.le_shift = le_offset(s, t);
-    s->geo.le_shift_next = le_offset(s, t + s->dt);
-}
-
-// Upload B (state in pid order), then hash, sort and reorder it into A.
-dem_status upload_and_sort(dem_sim* s, const double* x, const double* v, const double* w) {
-    const uint64_t n = s->n;
-    if (n == 0) return DEM_OK;
-    std::vector<double4> xr(n);
-    std::vector<double2> vw(3 * n);
-    for (uint64_t i = 0; i < n; ++i) {
-        uint64_t meta = pack_meta(s->r[i], (uint32_t)i);
-        double mw;
-        std::memcpy(&mw, &meta, 8);
-        xr[i] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], mw);
-        vw[i] = make_double2(v[3 * i], v[3 * i + 1]);
-        vw[n + i] = make_double2(v[3 * i + 2], w[3 * i]);
-        vw[2 * n + i] = make_double2(w[3 * i + 1], w[3 * i + 2]);
-    }
-    HIPCHK(hipMemcpyAsync(s->B.xr, xr.data(), n * sizeof(double4), hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->B.vw, vw.data(), 3 * n * sizeof(double2), hipMemcpyHostToDevice, s->stream));
-    if (s->B.mat) {
-        std::vector<uint8_t> m8(n);
-        for (uint64_t i = 0; i < n; ++i) m8[i] = (uint8_t)s->mat[i];
-        HIPCHK(hipMemcpyAsync(s->B.mat, m8.data(), n, hipMemcpyHostToDevice, s->stream));
-    }
-    HIPCHK(hipMemsetAsync(s->cells, 0, s->ncells * sizeof(uint2), s->stream));
-    launch_hash(s->B, (uint32_t)n, s->geo, s->keys, s->vals, s->stream);
-    uint32_t *ko, *vo;
-    launch_radix_sort(s->keys, s->vals, s->keys_t, s->vals_t, (uint32_t)n, s->geo.key_bits,
-                      s->tile_hist, s->digit_tot, &ko, &vo, s->st, s->stream);
-    launch_reorder(ko, vo, s->B, s->A, s->prev, s->cells, (uint32_t)n, s->geo, s->st, 0, s->stream);
-    HIPCHK(hipGetLastError());
-    // B now mirrors A's source order (pid order); keep F/T readable as zeros
-    if (s->fo) HIPCHK(hipMemsetAsync(s->fo, 0, 6 * n * (s->fp64 ? 8 : 4), s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    return DEM_OK;
-}
-
-void prof_record(dem_sim* s, size_t step_slot, int ev) {
-    if (!s->prof) return;
-    (void)hipEventRecord(s->prof_ev[step_slot].e[ev], s->stream);
-}
-
-dem_status enqueue_step(dem_sim* s, uint64_t k, double t) {
-    const uint32_t n = (uint32_t)s->n;
-    set_step_geo(s, t);
-    const int o = (int)(k & 1), w = 1 - o;
-    size_t slot = 0;
-    if (s->prof) {
-        if (s->prof_used == s->prof_ev.size()) {
-            ProfEv pe;
-            for (int q = 0; q < 2 * DEM_NPHASE; ++q) HIPCHK(hipEventCreate(&pe.e[q]));
-            s->prof_ev.push_back(pe);
-        }
-        slot = s->prof_used++;
-    }
-    prof_record(s, slot, 0);
-    launch_detect(s->kmax, s->A, s->cells, n, s->geo, s->rows[w], s->col_j, s->slots, s->ts,
-                  s->st, s->stream);
-    prof_record(s, slot, 1);
-    prof_record(s, slot, 2);
-    launch_force(s->fp64, s->A, s->B, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
-                 s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals,
-                 (s->P.flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo, s->mt, n, s->geo,
-                 s->ts, s->st, s->stream);
-    prof_record(s, slot, 3);
-    prof_record(s, slot, 4);
-    uint32_t *ko, *vo;
-    launch_radix_sort(s->keys, s->vals, s->keys_t, s->vals_t, n, s->geo.key_bits, s->tile_hist,
-                      s->digit_tot, &ko, &vo, s->st, s->stream);
-    prof_record(s, slot, 5);
-    prof_record(s, slot, 6);
-    launch_reorder(ko, vo, s->B, s->A, s->prev, s->cells, n, s->geo, s->st, 1, s->stream);
-    prof_record(s, slot, 7);
-    HIPCHK(hipGetLastError());
-    return DEM_OK;
-}
-
-dem_status read_status(dem_sim* s, Status& h) {
-    HIPCHK(hipStreamSynchronize(s->stream));
-    HIPCHK(hipMemcpy(&h, s->st, sizeof(Status), hipMemcpyDeviceToHost));
-    return DEM_OK;
-}
-
-// Grow every tile's region of the contact table to hold `need` contacts per
-// tile, keeping the old table of the step that is to be (re)run at the same
-// positions (its rows hold absolute indices).
-dem_status regrow(dem_sim* s, uint64_t need_per_tile, uint64_t step) {
-    const uint64_t nt = tiles_of(s->n);
-    uint64_t ns = std::max<uint64_t>((uint64_t)s->slots * 2, (need_per_tile + TILE - 1) / TILE + 2);
-    if (nt * TILE * ns > MAX_ENTRIES) ns = MAX_ENTRIES / (nt * TILE);
-    if (ns <= s->slots) return DEM_ECAPACITY;
-    const uint64_t nc = nt * TILE * ns, oc = s->cap;
-    uint32_t *col = nullptr, *pid[2] = {nullptr, nullptr};
-    double* dt[2] = {nullptr, nullptr};
-    bool ok = dalloc_t(s, nc, &col) == DEM_OK;
-    for (int k = 0; k < 2 && ok; ++k)
-        ok = dalloc_t(s, nc, &pid[k]) == DEM_OK && dalloc_t(s, 3 * nc, &dt[k]) == DEM_OK;
-    if (!ok) {
-        dfree(s, col);
-        for (int k = 0; k < 2; ++k) {
-            dfree(s, pid[k]);
-            dfree(s, dt[k]);
-        }
-        return DEM_ECAPACITY;
-    }
-    const int o = (int)(step & 1);
-    HIPCHK(hipMemcpyAsync(pid[o], s->tab_pid[o], oc * 4, hipMemcpyDeviceToDevice, s->stream));
-    for (int c = 0; c < 3; ++c)
-        HIPCHK(hipMemcpyAsync(dt[o] + (size_t)c * nc, s->tab_dt[o] + (size_t)c * oc, oc * 8,
-                              hipMemcpyDeviceToDevice, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    dfree(s, s->col_j);
-    for (int k = 0; k < 2; ++k) {
-        dfree(s, s->tab_pid[k]);
-        dfree(s, s->tab_dt[k]);
-    }
-    s->col_j = col;
-    for (int k = 0; k < 2; ++k) {
-        s->tab_pid[k] = pid[k];
-        s->tab_dt[k] = dt[k];
-    }
-    s->cap = nc;
-    s->slots = (uint32_t)ns;
-    s->regrows++;
-    return DEM_OK;
-}
-
-dem_status sync_impl(dem_sim* s) {
-    if (s->failed != DEM_OK) return s->failed;
-    for (;;) {
-        Status h;
-        dem_status r = read_status(s, h);
-        if (r != DEM_OK) return r;
-        const uint64_t done = h.steps_done;
-        // confirm completed steps
-        while (s->steps_confirmed < done) {
-            s->time_done = s->t_pending.front() + s->dt;
-            s->t_pending.erase(s->t_pending.begin());
-            s->steps_confirmed++;
-        }
-        if (h.err == 0) return DEM_OK;
-        if (h.err & ERR_NONFINITE) {
-            s->failed = DEM_ENONFINITE;
-            return DEM_ENONFINITE;
-        }
-        if (h.err & ERR_ROW) {
-            if (s->kmax >= 64) {
-                s->failed = DEM_ECAPACITY;
-                return DEM_ECAPACITY;
-            }
-            s->kmax = 64;
-        }
-        if (h.err & ERR_CAPACITY) {
-            r = regrow(s, h.need, done);
-            if (r != DEM_OK) {
-                s->failed = r;
-                return r;
-            }
-        }
-        // clear the error and the reservation counter, then redo the remaining steps
-        Status z = h;
-        z.err = 0;
-        z.need = 0;
-        HIPCHK(hipMemcpy(s->st, &z, sizeof(Status), hipMemcpyHostToDevice));
-        s->prof_used = 0;
-        std::vector<double> ts = s->t_pending;
-        for (size_t q = 0; q < ts.size(); ++q) {
-            r = enqueue_step(s, done + q, ts[q]);
-            if (r != DEM_OK) return r;
-        }
-    }
-}
-
-void destroy_impl(dem_sim* s) {
-    if (!s) return;
-    (void)hipStreamSynchronize(s->stream);
-    for (auto& b : s->bufs) (void)hipFree(b.p);
-    s->bufs.clear();
-    for (auto& pe : s->prof_ev)
-        for (int q = 0; q < 2 * DEM_NPHASE; ++q) (void)hipEventDestroy(pe.e[q]);
-    delete s;
-}
-
 bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
-
-// pid of the particle at each position of B (the order of the last step's rows)
-dem_status pids_of_B(dem_sim* s, std::vector<uint32_t>& pid) {
-    const uint64_t n = s->n;
-    std::vector<double4> xr(n);
-    pid.resize(n);
-    if (n) HIPCHK(hipMemcpy(xr.data(), s->B.xr, n * sizeof(double4), hipMemcpyDeviceToHost));
-    for (uint64_t i = 0; i < n; ++i) {
-        uint64_t m;
-        std::memcpy(&m, &xr[i].w, 8);
-        pid[i] = (uint32_t)(m >> 32);
-    }
-    return DEM_OK;
-}
-
-struct Contact {
-    uint32_t i, j;
-    double dt[3];
-};
-
-dem_status read_contacts(dem_sim* s, std::vector<Contact>& out) {
-    out.clear();
-    const uint64_t n = s->n;
-    if (n == 0) return DEM_OK;
-    const int o = (int)(s->steps_confirmed & 1);
-    std::vector<uint2> rows(n);
-    HIPCHK(hipMemcpy(rows.data(), s->rows[o], n * sizeof(uint2), hipMemcpyDeviceToHost));
-    uint64_t m = 0;
-    for (auto& r : rows) m = std::max<uint64_t>(m, (uint64_t)r.x + r.y);
-    std::vector<uint32_t> tp(m);
-    std::vector<double> td(3 * m);
-    if (m) {
-        HIPCHK(hipMemcpy(tp.data(), s->tab_pid[o], m * 4, hipMemcpyDeviceToHost));
-        for (int c = 0; c < 3; ++c)
-            HIPCHK(hipMemcpy(td.data() + c * m, s->tab_dt[o] + (size_t)c * s->cap, m * 8,
-                             hipMemcpyDeviceToHost));
-    }
-    std::vector<uint32_t> pid;
-    if (s->table_by_pid) {
-        pid.resize(n);
-        std::iota(pid.begin(), pid.end(), 0u);
-    } else {
-        dem_status r = pids_of_B(s, pid);
-        if (r != DEM_OK) return r;
-    }
-    for (uint64_t p = 0; p < n; ++p)
-        for (uint32_t k = rows[p].x; k < rows[p].x + rows[p].y; ++k)
-            out.push_back({pid[p], tp[k], {td[k], td[m + k], td[2 * m + k]}});
-    std::sort(out.begin(), out.end(), [](const Contact& a, const Contact& b) {
-        return a.i < b.i || (a.i == b.i && a.j < b.j);
-    });
-    return DEM_OK;
-}
-
-// Install a history indexed by pid as the old table of the next step.
-dem_status write_contacts(dem_sim* s, std::vector<Contact>& c) {
-    const uint64_t n = s->n;
-    std::sort(c.begin(), c.end(), [](const Contact& a, const Contact& b) {
-        return a.i < b.i || (a.i == b.i && a.j < b.j);
-    });
-    for (size_t k = 0; k < c.size(); ++k) {
-        if (c[k].i >= n) return DEM_EINVAL;
-        if (c[k].j >= n && c[k].j < FACE) return DEM_EINVAL;
-        if (c[k].j >= FACE + 6) return DEM_EINVAL;
-        if (c[k].j == c[k].i) return DEM_EINVAL;
-        if (k && c[k].i == c[k - 1].i && c[k].j == c[k - 1].j) return DEM_EINVAL;
-        if (!finite3(c[k].dt)) return DEM_EINVAL;
-    }
-    while (c.size() > s->cap) {
-        dem_status r = regrow(s, (c.size() + tiles_of(n) - 1) / tiles_of(n), s->steps_confirmed);
-        if (r != DEM_OK) return r;
-    }
-    const int o = (int)(s->steps_confirmed & 1);
-    const size_t m = c.size();
-    std::vector<uint2> rows(n, make_uint2(0, 0));
-    std::vector<uint32_t> tp(m);
-    std::vector<double> td(3 * std::max<size_t>(m, 1));
-    for (size_t k = 0; k < m; ++k) {
-        if (rows[c[k].i].y == 0) rows[c[k].i].x = (uint32_t)k;
-        rows[c[k].i].y++;
-        tp[k] = c[k].j;
-        for (int a = 0; a < 3; ++a) td[a * m + k] = c[k].dt[a];
-    }
-    if (n) HIPCHK(hipMemcpy(s->rows[o], rows.data(), n * sizeof(uint2), hipMemcpyHostToDevice));
-    if (m) {
-        HIPCHK(hipMemcpy(s->tab_pid[o], tp.data(), m * 4, hipMemcpyHostToDevice));
-        for (int a = 0; a < 3; ++a)
-            HIPCHK(hipMemcpy(s->tab_dt[o] + (size_t)a * s->cap, td.data() + a * m, m * 8,
-                             hipMemcpyHostToDevice));
-    }
-    // prev[i] = pid of the particle now at sorted position i
-    if (n) {
-        std::vector<double4> xr(n);
-        HIPCHK(hipMemcpy(xr.data(), s->A.xr, n * sizeof(double4), hipMemcpyDeviceToHost));
-        std::vector<uint32_t> pv(n);
-        for (uint64_t i = 0; i < n; ++i) {
-            uint64_t mm;
-            std::memcpy(&mm, &xr[i].w, 8);
-            pv[i] = (uint32_t)(mm >> 32);
-        }
-        HIPCHK(hipMemcpy(s->prev, pv.data(), n * 4, hipMemcpyHostToDevice));
-    }
-    s->table_by_pid = true;
-    return DEM_OK;
-}
 
 dem_status validate(const dem_params* P, const dem_material* mats, uint32_t n_mats) {
     if (!P || !mats || n_mats < 1 || n_mats > DEM_MAX_MATERIALS) return DEM_EINVAL;
@@ -566,6 +290,827 @@ dem_status validate(const dem_params* P, const dem_material* mats, uint32_t n_ma
     return DEM_OK;
 }
 
+// ------------------------------------------------------------- pool memory
+dem_status alloc_contacts(dem_pool* s, uint32_t slots, uint32_t** col, uint32_t** pid0,
+                          uint32_t** pid1, double** dt0, double** dt1) {
+    const uint64_t cap = (uint64_t)s->max_tiles * TILE * slots;
+    *col = nullptr;
+    *pid0 = *pid1 = nullptr;
+    *dt0 = *dt1 = nullptr;
+    if (cap > MAX_ENTRIES) return DEM_ECAPACITY;
+    bool ok = dalloc_t(s, cap, col) == DEM_OK && dalloc_t(s, cap, pid0) == DEM_OK &&
+              dalloc_t(s, cap, pid1) == DEM_OK && dalloc_t(s, 3 * cap, dt0) == DEM_OK &&
+              dalloc_t(s, 3 * cap, dt1) == DEM_OK;
+    if (!ok) {
+        dfree(s, *col);
+        dfree(s, *pid0);
+        dfree(s, *pid1);
+        dfree(s, *dt0);
+        dfree(s, *dt1);
+        return DEM_ENOMEM;
+    }
+    return DEM_OK;
+}
+
+uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, bool fp64,
+                    uint64_t slots) {
+    const uint64_t np = max_tiles * TILE;
+    uint64_t b = 0;
+    b += np * (32 + 48 + 1 + 16);      // sorted state and its FP32 record
+    b += np * (32 + 48 + 1);           // integrated state
+    b += np * 2 * 8;                   // contact rows, two steps
+    b += np * 5 * 4;                   // prev, keys and values (two buffers)
+    b += np * 6 * (fp64 ? 8 : 4);      // per-particle F, T
+    b += max_cells * 8;                // cell bounds
+    b += np * slots * (4 + 2 * 28);    // partner list and two history tables
+    b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
+    b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4);
+    b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
+    return b;
+}
+
+void destroy_pool(dem_pool* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (auto& b : s->bufs) (void)hipFree(b.p);
+    s->bufs.clear();
+    for (auto& pe : s->prof_ev)
+        for (int q = 0; q < 2 * DEM_NPHASE; ++q) (void)hipEventDestroy(pe.e[q]);
+    delete s;
+}
+
+dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_jobs, bool fp64,
+                       uint32_t slots, uint32_t flags, void* stream, dem_pool** out) {
+    *out = nullptr;
+    if (max_jobs < 1 || slots < 1) return DEM_EINVAL;
+    const uint64_t mt = std::max<uint64_t>(1, tiles_of(max_particles));
+    if (mt * TILE > MAX_ENTRIES || mt * TILE * slots > MAX_ENTRIES) return DEM_EINVAL;
+    dem_pool* s = new (std::nothrow) dem_pool();
+    if (!s) return DEM_ENOMEM;
+    s->stream = (hipStream_t)stream;
+    s->fp64 = fp64;
+    s->flags = flags;
+    s->slots = slots;
+    s->max_tiles = (uint32_t)mt;
+    s->max_cells = std::max<uint64_t>(max_cells, 1);
+    s->max_jobs = max_jobs;
+    s->jobs.resize(max_jobs);
+    s->segs.push_back({0, s->max_tiles, -1});
+    s->free_cells.push_back({0, s->max_cells});
+    const size_t np = (size_t)mt * TILE;
+    dem_status r = DEM_OK;
+    void *xa, *va, *ma, *xfa, *xb, *vb, *mb;
+#define ALLOC_OR_FAIL(call)   \
+    do {                      \
+        r = (call);           \
+        if (r != DEM_OK) {    \
+            destroy_pool(s);  \
+            return r;         \
+        }                     \
+    } while (0)
+    ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xa));
+    ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &va));
+    ALLOC_OR_FAIL(dalloc(s, np, &ma));
+    ALLOC_OR_FAIL(dalloc(s, np * sizeof(float4), &xfa));
+    ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xb));
+    ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &vb));
+    ALLOC_OR_FAIL(dalloc(s, np, &mb));
+    s->A.xr = (double4*)xa;
+    s->A.vw = (double2*)va;
+    s->A.mat = (uint8_t*)ma;
+    s->A.xf = (float4*)xfa;
+    s->B.xr = (double4*)xb;
+    s->B.vw = (double2*)vb;
+    s->B.mat = (uint8_t*)mb;
+    s->B.xf = nullptr;
+    ALLOC_OR_FAIL(dalloc_t(s, s->max_cells, &s->cells));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[0]));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[1]));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->prev));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->keys));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->vals));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->keys_t));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->vals_t));
+    ALLOC_OR_FAIL(dalloc_t(s, sort_hist_words((uint32_t)np), &s->tile_hist));
+    ALLOC_OR_FAIL(dalloc_t(s, 256, &s->digit_tot));
+    ALLOC_OR_FAIL(dalloc(s, 6 * np * (fp64 ? 8 : 4), &s->fo));
+    ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->mats));
+    ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->jobs_d));
+    ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->job_fail));
+    ALLOC_OR_FAIL(dalloc_t(s, mt, &s->tile_job));
+    ALLOC_OR_FAIL(dalloc_t(s, mt, &s->tile_key));
+    ALLOC_OR_FAIL(dalloc_t(s, mt, &s->ts));
+    ALLOC_OR_FAIL(dalloc_t(s, 1, &s->st));
+    ALLOC_OR_FAIL(alloc_contacts(s, slots, &s->col_j, &s->tab_pid[0], &s->tab_pid[1],
+                                 &s->tab_dt[0], &s->tab_dt[1]));
+#undef ALLOC_OR_FAIL
+    s->cap = (uint64_t)mt * TILE * slots;
+    hipError_t e = hipMemset(s->st, 0, sizeof(Status));
+    if (e == hipSuccess) e = hipMemset(s->ts, 0, mt * sizeof(TileStats));
+    if (e == hipSuccess) e = hipMemset(s->cells, 0, s->max_cells * sizeof(uint2));
+    if (e == hipSuccess) e = hipMemset(s->rows[0], 0, np * sizeof(uint2));
+    if (e == hipSuccess) e = hipMemset(s->rows[1], 0, np * sizeof(uint2));
+    if (e == hipSuccess) e = hipMemset(s->fo, 0, 6 * np * (fp64 ? 8 : 4));
+    if (e == hipSuccess) e = hipMemset(s->jobs_d, 0, max_jobs * sizeof(Job));
+    if (e == hipSuccess) e = hipMemset(s->job_fail, 0, max_jobs * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(s->A.mat, 0, np);
+    if (e == hipSuccess) e = hipMemset(s->B.mat, 0, np);
+    std::vector<uint32_t> tj(mt, NO_JOB);
+    if (e == hipSuccess) e = hipMemcpy(s->tile_job, tj.data(), mt * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(s->tile_key, 0, mt * 4);
+    if (e != hipSuccess) {
+        destroy_pool(s);
+        return hip_status(e);
+    }
+    *out = s;
+    return DEM_OK;
+}
+
+int seg_bits(size_t nsegs) {
+    int jb = 0;
+    while ((size_t(1) << jb) < nsegs) ++jb;
+    return jb;
+}
+
+// Ranks of the segments in memory order are the high bits of the sort key,
+// so one sort keeps every job (and every free gap) inside its segment.
+dem_status upload_layout(dem_pool* s) {
+    int lb = 1;
+    bool per = false, mm = false;
+    for (const HostJob& j : s->jobs)
+        if (j.used) {
+            lb = std::max(lb, j.lay.key_bits);
+            per = per || j.P.periodic != 0;
+            mm = mm || j.multi_mat;
+        }
+    const int jb = seg_bits(s->segs.size());
+    if (lb + jb > 32) return DEM_EBUSY;
+    s->lb = lb;
+    s->any_periodic = per;
+    s->any_multi_mat = mm;
+    std::vector<uint32_t> tj(s->max_tiles, NO_JOB), tk(s->max_tiles, 0u);
+    uint32_t hw = 0;
+    for (size_t q = 0; q < s->segs.size(); ++q) {
+        const Seg& g = s->segs[q];
+        const uint32_t key = lb >= 32 ? 0u : (uint32_t)((uint64_t)q << lb);
+        for (uint32_t t = g.start; t < g.start + g.len; ++t) {
+            tj[t] = g.slot < 0 ? NO_JOB : (uint32_t)g.slot;
+            tk[t] = key;
+        }
+        if (g.slot >= 0) hw = std::max(hw, g.start + g.len);
+    }
+    s->hw_tiles = hw;
+    dem_status r = upload(s, s->tile_job, tj.data(), s->max_tiles * 4);
+    if (r == DEM_OK) r = upload(s, s->tile_key, tk.data(), s->max_tiles * 4);
+    return r;
+}
+
+int take_tiles(dem_pool* s, uint32_t need, int slot) {
+    for (size_t q = 0; q < s->segs.size(); ++q) {
+        Seg& g = s->segs[q];
+        if (g.slot >= 0 || g.len < need) continue;
+        const uint32_t start = g.start;
+        if (g.len == need) {
+            g.slot = slot;
+        } else {
+            Seg rest{start + need, g.len - need, -1};
+            g.len = need;
+            g.slot = slot;
+            s->segs.insert(s->segs.begin() + q + 1, rest);
+        }
+        return (int)start;
+    }
+    return -1;
+}
+
+void release_tiles(dem_pool* s, int slot) {
+    for (Seg& g : s->segs)
+        if (g.slot == slot) g.slot = -1;
+    std::vector<Seg> m;
+    for (const Seg& g : s->segs) {
+        if (g.len == 0 && g.slot < 0) continue;
+        if (!m.empty() && m.back().slot < 0 && g.slot < 0) m.back().len += g.len;
+        else m.push_back(g);
+    }
+    if (m.empty()) m.push_back({0, s->max_tiles, -1});
+    s->segs = m;
+}
+
+long long take_cells(dem_pool* s, uint64_t need) {
+    for (auto& f : s->free_cells)
+        if (f.second >= need) {
+            const uint64_t start = f.first;
+            f.first += need;
+            f.second -= need;
+            return (long long)start;
+        }
+    return -1;
+}
+
+void release_cells(dem_pool* s, uint64_t start, uint64_t len) {
+    s->free_cells.push_back({start, len});
+    std::sort(s->free_cells.begin(), s->free_cells.end());
+    std::vector<std::pair<uint64_t, uint64_t>> m;
+    for (auto& f : s->free_cells) {
+        if (!f.second) continue;
+        if (!m.empty() && m.back().first + m.back().second == f.first) m.back().second += f.second;
+        else m.push_back(f);
+    }
+    s->free_cells = m;
+}
+
+// Host-side placement of a job's particles in cell order (stable by particle
+// id) with its cell bounds: the device only ever re-sorts jobs it already has.
+struct Placed {
+    std::vector<double4> xr;
+    std::vector<float4> xf;
+    std::vector<double2> vw0, vw1, vw2;
+    std::vector<uint8_t> mat;
+    std::vector<uint2> cells;
+};
+
+uint32_t host_cell_coord(const Geo& G, double x, int a) {
+    double f = std::floor((x - G.lo[a]) * G.inv_cell[a]);
+    if (!(f >= 0.0)) return 0;
+    if (f >= (double)G.nc[a]) return (uint32_t)G.nc[a] - 1;
+    return (uint32_t)f;
+}
+
+void place_job(const HostJob& J, uint32_t p0, const double* x, const double* v, const double* w,
+               Placed& out) {
+    const uint64_t n = J.n;
+    const Geo& G = J.geo;
+    std::vector<uint32_t> key(n), lin(n);
+    for (uint64_t i = 0; i < n; ++i) {
+        const uint32_t cx = host_cell_coord(G, x[3 * i], 0), cy = host_cell_coord(G, x[3 * i + 1], 1),
+                       cz = host_cell_coord(G, x[3 * i + 2], 2);
+        key[i] = ((spread2_host(cy) | (spread2_host(cz) << 1)) << G.xbits) | cx;
+        lin[i] = (cz * (uint32_t)G.nc[1] + cy) * (uint32_t)G.nc[0] + cx;
+    }
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key[a] < key[b]; });
+    out.xr.resize(n);
+    out.xf.resize(n);
+    out.vw0.resize(n);
+    out.vw1.resize(n);
+    out.vw2.resize(n);
+    out.mat.resize(n);
+    out.cells.assign(J.ncells, make_uint2(0, 0));
+    const float qnan = std::nanf("");
+    for (uint64_t q = 0; q < n; ++q) {
+        const uint32_t i = order[q];
+        uint64_t meta = pack_meta(J.r[i], i);
+        double mw;
+        std::memcpy(&mw, &meta, 8);
+        out.xr[q] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], mw);
+        const double rx = x[3 * i] - G.lo[0], ry = x[3 * i + 1] - G.lo[1], rz = x[3 * i + 2] - G.lo[2];
+        const bool near = std::fabs(rx) <= 3.0 * G.L[0] && std::fabs(ry) <= 3.0 * G.L[1] &&
+                          std::fabs(rz) <= 3.0 * G.L[2];
+        out.xf[q] = near ? make_float4((float)rx, (float)ry, (float)rz, J.r[i])
+                         : make_float4(qnan, qnan, qnan, J.r[i]);
+        out.vw0[q] = make_double2(v[3 * i], v[3 * i + 1]);
+        out.vw1[q] = make_double2(v[3 * i + 2], w[3 * i]);
+        out.vw2[q] = make_double2(w[3 * i + 1], w[3 * i + 2]);
+        out.mat[q] = (uint8_t)J.mat[i];
+        const uint32_t k = key[i];
+        if (q == 0 || key[order[q - 1]] != k) out.cells[lin[i]].x = p0 + (uint32_t)q;
+        if (q + 1 == n || key[order[q + 1]] != k) out.cells[lin[i]].y = p0 + (uint32_t)q + 1;
+    }
+}
+
+// Upload a job's state (sorted on the host), its cells, an empty history and
+// identity map, its descriptor and materials.
+dem_status upload_job(dem_pool* s, int slot, const double* x, const double* v, const double* w,
+                      double t0, uint32_t steps) {
+    HostJob& J = s->jobs[slot];
+    const uint32_t p0 = J.tile0 * TILE;
+    Placed pl;
+    place_job(J, p0, x, v, w, pl);
+    const uint64_t n = J.n, np = (uint64_t)s->max_tiles * TILE;
+    dem_status r = DEM_OK;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (r == DEM_OK) r = upload(s, dst, src, bytes);
+    };
+    up(s->A.xr + p0, pl.xr.data(), n * sizeof(double4));
+    up(s->A.xf + p0, pl.xf.data(), n * sizeof(float4));
+    up(s->A.vw + p0, pl.vw0.data(), n * sizeof(double2));
+    up(s->A.vw + np + p0, pl.vw1.data(), n * sizeof(double2));
+    up(s->A.vw + 2 * np + p0, pl.vw2.data(), n * sizeof(double2));
+    up(s->A.mat + p0, pl.mat.data(), n);
+    up(s->cells + J.cell_base, pl.cells.data(), (size_t)J.ncells * sizeof(uint2));
+    const uint64_t span = (uint64_t)J.ntiles * TILE;
+    std::vector<uint2> zr(span, make_uint2(0, 0));
+    std::vector<uint32_t> idp(span);
+    std::iota(idp.begin(), idp.end(), p0);
+    up(s->rows[s->cur] + p0, zr.data(), span * sizeof(uint2));
+    up(s->prev + p0, idp.data(), span * 4);
+    std::vector<TileStats> z(J.ntiles);
+    if (J.ntiles) std::memset(z.data(), 0, z.size() * sizeof(TileStats));
+    up(s->ts + J.tile0, z.data(), J.ntiles * sizeof(TileStats));
+    // F, T of a new job read as zero until its first step
+    const size_t fs = s->fp64 ? 8 : 4;
+    if (span) {
+        std::vector<char> zf(span * fs, 0);
+        for (int c = 0; c < 6; ++c) up((char*)s->fo + ((size_t)c * np + p0) * fs, zf.data(), span * fs);
+    }
+    MatTable mt;
+    fill_mat_table(J.P, J.mats, mt);
+    up(s->mats + slot, &mt, sizeof(MatTable));
+    Job jd;
+    std::memset(&jd, 0, sizeof(jd));
+    jd.g = J.geo;
+    jd.g.le_shift = le_offset(J.geo, t0);
+    jd.g.le_shift_next = le_offset(J.geo, t0 + J.geo.dt);
+    jd.t = t0;
+    jd.margin = detect_margin(J.geo);
+    jd.p0 = p0;
+    jd.n = (uint32_t)n;
+    jd.cell_base = J.cell_base;
+    jd.mat = (uint32_t)slot;
+    jd.status = JOB_ACTIVE;
+    jd.steps_left = steps;
+    up(s->jobs_d + slot, &jd, sizeof(Job));
+    const uint32_t zero = 0;
+    up(s->job_fail + slot, &zero, sizeof(zero));
+    J.hist_in_A = true;
+    return r;
+}
+
+// A job's constants and memory: validates, plans the grid, takes tiles and cells.
+dem_status add_job(dem_pool* s, const dem_params* params, const dem_material* mats, uint32_t n_mats,
+                   uint64_t n, const double* x, const double* v, const double* w,
+                   const float* radius, const uint16_t* mat_id, uint32_t steps, int* slot_out) {
+    dem_status r = validate(params, mats, n_mats);
+    if (r != DEM_OK) return r;
+    if ((params->precision == DEM_PREC_FP64) != s->fp64) return DEM_EINVAL;
+    if (n >= (uint64_t)FACE) return DEM_EINVAL;
+    if (n > (uint64_t)s->max_tiles * TILE) return DEM_EBUSY;
+    if (n && (!x || !v || !w || !radius)) return DEM_EINVAL;
+    double rmax = 0.0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (!(radius[i] > 0.0f) || !std::isfinite(radius[i])) return DEM_EINVAL;
+        if (!finite3(x + 3 * i) || !finite3(v + 3 * i) || !finite3(w + 3 * i)) return DEM_EINVAL;
+        if (mat_id && mat_id[i] >= n_mats) return DEM_EINVAL;
+        rmax = std::max(rmax, (double)radius[i]);
+    }
+    if (n == 0) {
+        double lmin = INFINITY;
+        for (int a = 0; a < 3; ++a) lmin = std::min(lmin, params->hi[a] - params->lo[a]);
+        rmax = lmin / 6.1;
+    }
+    Layout lay;
+    r = plan_grid(*params, rmax, n, lay);
+    if (r != DEM_OK) return r;
+    int slot = -1;
+    for (uint32_t k = 0; k < s->max_jobs; ++k)
+        if (!s->jobs[k].used) {
+            slot = (int)k;
+            break;
+        }
+    if (slot < 0) return DEM_EBUSY;
+    const uint64_t ncells = (uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2];
+    const uint32_t ntiles = (uint32_t)tiles_of(n);
+    const long long cb = take_cells(s, ncells);
+    if (cb < 0) return DEM_EBUSY;
+    const int t0 = take_tiles(s, ntiles, slot);
+    if (t0 < 0) {
+        release_cells(s, (uint64_t)cb, ncells);
+        return DEM_EBUSY;
+    }
+    HostJob& J = s->jobs[slot];
+    J = HostJob();
+    J.used = true;
+    J.id = s->next_id++;
+    J.P = *params;
+    J.mats.assign(mats, mats + n_mats);
+    J.n = n;
+    J.tile0 = (uint32_t)t0;
+    J.ntiles = ntiles;
+    J.cell_base = (uint32_t)cb;
+    J.ncells = (uint32_t)ncells;
+    J.lay = lay;
+    J.multi_mat = n_mats > 1;
+    J.r.assign(radius, radius + n);
+    J.mat.assign(n, 0);
+    if (mat_id) J.mat.assign(mat_id, mat_id + n);
+    Geo& G = J.geo;
+    std::memset(&G, 0, sizeof(G));
+    for (int a = 0; a < 3; ++a) {
+        G.lo[a] = params->lo[a];
+        G.hi[a] = params->hi[a];
+        G.L[a] = params->hi[a] - params->lo[a];
+        G.inv_cell[a] = 1.0 / lay.cell[a];
+        G.inv_L[a] = 1.0 / G.L[a];
+        G.nc[a] = lay.nc[a];
+        G.g[a] = params->gravity[a];
+    }
+    G.walls = params->walls;
+    G.periodic = params->periodic;
+    G.le = params->shear_rate != 0.0;
+    G.key_bits = lay.key_bits;
+    G.xbits = lay.xbits;
+    G.le_dv = params->shear_rate * G.L[1];
+    // time step: t_c / 50 of two spheres of the smallest radius at 0.1 m/s
+    double dt = params->dt;
+    if (dt == 0.0) {
+        if (n == 0) {
+            dt = 1e-9;
+        } else {
+            uint64_t k = 0;
+            for (uint64_t i = 1; i < n; ++i)
+                if (radius[i] < radius[k]) k = i;
+            const int m = mat_id ? mat_id[k] : 0;
+            MatTable mt;
+            fill_mat_table(*params, J.mats, mt);
+            const double rk = (double)radius[k];
+            const double mk = mt.mass_pref[m] * rk * rk * rk;
+            const double kn = mt.kn_pref[m * MAXMAT + m] * std::sqrt(rk * rk / (rk + rk));
+            dt = hertz_contact_time(0.5 * mk, kn, 0.1) / 50.0;
+        }
+    }
+    G.dt = dt;
+    r = upload_layout(s);
+    if (r == DEM_OK) r = upload_job(s, slot, x, v, w, params->time, steps);
+    if (r != DEM_OK) {
+        release_tiles(s, slot);
+        release_cells(s, J.cell_base, J.ncells);
+        J = HostJob();
+        (void)upload_layout(s);
+        return r;
+    }
+    *slot_out = slot;
+    return DEM_OK;
+}
+
+dem_status remove_job(dem_pool* s, int slot) {
+    HostJob& J = s->jobs[slot];
+    if (!J.used) return DEM_EINVAL;
+    release_tiles(s, slot);
+    release_cells(s, J.cell_base, J.ncells);
+    J = HostJob();
+    return upload_layout(s);
+}
+
+// ------------------------------------------------------------ step pipeline
+PoolView view(dem_pool* s) {
+    PoolView P;
+    P.jobs = s->jobs_d;
+    P.job_fail = s->job_fail;
+    P.tile_job = s->tile_job;
+    P.tile_key = s->tile_key;
+    P.ntiles = s->hw_tiles;
+    P.ns = s->max_tiles * TILE;
+    P.lmask = s->lb >= 32 ? 0xFFFFFFFFu : ((1u << s->lb) - 1u);
+    P.mats = s->mats;
+    P.ts = s->ts;
+    P.st = s->st;
+    P.any_periodic = s->any_periodic;
+    return P;
+}
+
+void prof_record(dem_pool* s, size_t slot, int ev) {
+    if (!s->prof) return;
+    (void)hipEventRecord(s->prof_ev[slot].e[ev], s->stream);
+}
+
+// One step of every running job; `o` is the buffer holding the old table.
+dem_status enqueue_step(dem_pool* s, int o) {
+    const int w = 1 - o;
+    PoolView P = view(s);
+    State A = s->A, B = s->B;
+    if (!s->any_multi_mat) A.mat = B.mat = nullptr;
+    size_t slot = 0;
+    if (s->prof) {
+        if (s->prof_used == s->prof_ev.size()) {
+            ProfEv pe;
+            for (int q = 0; q < 2 * DEM_NPHASE; ++q) HIPCHK(hipEventCreate(&pe.e[q]));
+            s->prof_ev.push_back(pe);
+        }
+        slot = s->prof_used++;
+    }
+    prof_record(s, slot, 0);
+    launch_detect(P, s->kmax, A, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
+    prof_record(s, slot, 1);
+    prof_record(s, slot, 2);
+    launch_force(P, s->fp64, A, B, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
+                 s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals,
+                 (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo, s->stream);
+    prof_record(s, slot, 3);
+    prof_record(s, slot, 4);
+    uint32_t *ko, *vo;
+    launch_radix_sort(s->keys, s->vals, s->keys_t, s->vals_t, s->hw_tiles * TILE,
+                      s->lb + seg_bits(s->segs.size()), s->tile_hist, s->digit_tot, &ko, &vo, s->st,
+                      s->stream);
+    prof_record(s, slot, 5);
+    prof_record(s, slot, 6);
+    launch_reorder(P, ko, vo, B, A, s->prev, s->cells, s->stream);
+    launch_tick(P, s->jobs_d, s->max_jobs, s->stream);
+    prof_record(s, slot, 7);
+    HIPCHK(hipGetLastError());
+    return DEM_OK;
+}
+
+dem_status step_impl(dem_pool* s, uint32_t nsteps) {
+    if (s->failed != DEM_OK) return s->failed;
+    for (uint32_t q = 0; q < nsteps; ++q) {
+        dem_status r = enqueue_step(s, s->cur);
+        if (r != DEM_OK) return r;
+        s->pending.push_back(s->cur);
+        s->cur = 1 - s->cur;
+    }
+    if (nsteps)
+        for (HostJob& j : s->jobs) j.hist_in_A = false;
+    return DEM_OK;
+}
+
+dem_status read_status(dem_pool* s, Status& h) {
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipMemcpy(&h, s->st, sizeof(Status), hipMemcpyDeviceToHost));
+    return DEM_OK;
+}
+
+// Grow every tile's region of the contact table to hold `need` contacts per
+// tile, keeping the old table of buffer `o` at the same positions (its rows
+// hold absolute indices).
+dem_status regrow(dem_pool* s, uint64_t need_per_tile, int o) {
+    const uint64_t nt = s->max_tiles;
+    uint64_t ns = std::max<uint64_t>((uint64_t)s->slots * 2, (need_per_tile + TILE - 1) / TILE + 2);
+    if (nt * TILE * ns > MAX_ENTRIES) ns = MAX_ENTRIES / (nt * TILE);
+    if (ns <= s->slots) return DEM_ECAPACITY;
+    const uint64_t oc = s->cap;
+    uint32_t *col, *p0, *p1;
+    double *d0, *d1;
+    if (alloc_contacts(s, (uint32_t)ns, &col, &p0, &p1, &d0, &d1) != DEM_OK) return DEM_ECAPACITY;
+    const uint64_t nc = nt * TILE * ns;
+    uint32_t* np_[2] = {p0, p1};
+    double* nd_[2] = {d0, d1};
+    HIPCHK(hipMemcpyAsync(np_[o], s->tab_pid[o], oc * 4, hipMemcpyDeviceToDevice, s->stream));
+    for (int c = 0; c < 3; ++c)
+        HIPCHK(hipMemcpyAsync(nd_[o] + (size_t)c * nc, s->tab_dt[o] + (size_t)c * oc, oc * 8,
+                              hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    dfree(s, s->col_j);
+    for (int k = 0; k < 2; ++k) {
+        dfree(s, s->tab_pid[k]);
+        dfree(s, s->tab_dt[k]);
+    }
+    s->col_j = col;
+    s->tab_pid[0] = p0;
+    s->tab_pid[1] = p1;
+    s->tab_dt[0] = d0;
+    s->tab_dt[1] = d1;
+    s->cap = nc;
+    s->slots = (uint32_t)ns;
+    s->regrows++;
+    return DEM_OK;
+}
+
+dem_status sync_impl(dem_pool* s) {
+    if (s->failed != DEM_OK) return s->failed;
+    for (;;) {
+        Status h;
+        dem_status r = read_status(s, h);
+        if (r != DEM_OK) return r;
+        s->staging.clear();
+        while (s->steps_confirmed < h.steps_done && !s->pending.empty()) {
+            s->pending.pop_front();
+            s->steps_confirmed++;
+        }
+        if (h.err == 0) return DEM_OK;
+        // a step failed pool-wide before changing any state: fix and redo
+        const int o = s->pending.empty() ? s->cur : s->pending.front();
+        if (h.err & ERR_ROW) {
+            if (s->kmax >= 32) {
+                s->failed = DEM_ECAPACITY;
+                return DEM_ECAPACITY;
+            }
+            s->kmax = s->kmax <= 8 ? 16 : 32;
+        }
+        if (h.err & ERR_CAPACITY) {
+            r = regrow(s, h.need, o);
+            if (r != DEM_OK) {
+                s->failed = r;
+                return r;
+            }
+        }
+        Status z = h;
+        z.err = 0;
+        z.need = 0;
+        HIPCHK(hipMemcpy(s->st, &z, sizeof(Status), hipMemcpyHostToDevice));
+        s->prof_used = 0;
+        const size_t k = s->pending.size();
+        s->pending.clear();
+        s->cur = o;
+        r = step_impl(s, (uint32_t)k);
+        if (r != DEM_OK) return r;
+    }
+}
+
+dem_status read_job(dem_pool* s, int slot, Job& jd) {
+    HIPCHK(hipMemcpy(&jd, s->jobs_d + slot, sizeof(Job), hipMemcpyDeviceToHost));
+    return DEM_OK;
+}
+
+// pids of a job's positions in A (current order) or B (order of the last
+// step's rows)
+dem_status job_pids(dem_pool* s, const HostJob& J, bool fromA, std::vector<uint32_t>& pid) {
+    const uint64_t n = J.n;
+    std::vector<double4> xr(n);
+    pid.resize(n);
+    const uint32_t p0 = J.tile0 * TILE;
+    if (n) HIPCHK(hipMemcpy(xr.data(), (fromA ? s->A.xr : s->B.xr) + p0, n * sizeof(double4),
+                            hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t m;
+        std::memcpy(&m, &xr[i].w, 8);
+        pid[i] = (uint32_t)(m >> 32);
+    }
+    return DEM_OK;
+}
+
+dem_status get_state_impl(dem_pool* s, int slot, double* x, double* v, double* w, double* F,
+                          double* T) {
+    const HostJob& J = s->jobs[slot];
+    const uint64_t n = J.n, np = (uint64_t)s->max_tiles * TILE;
+    const uint32_t p0 = J.tile0 * TILE;
+    if (n == 0) return DEM_OK;
+    std::vector<double4> xr(n);
+    std::vector<double2> v0(n), v1(n), v2(n);
+    HIPCHK(hipMemcpy(xr.data(), s->A.xr + p0, n * sizeof(double4), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v0.data(), s->A.vw + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v1.data(), s->A.vw + np + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v2.data(), s->A.vw + 2 * np + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t m;
+        std::memcpy(&m, &xr[i].w, 8);
+        const uint32_t p = (uint32_t)(m >> 32);
+        if (x) {
+            x[3 * p] = xr[i].x;
+            x[3 * p + 1] = xr[i].y;
+            x[3 * p + 2] = xr[i].z;
+        }
+        if (v) {
+            v[3 * p] = v0[i].x;
+            v[3 * p + 1] = v0[i].y;
+            v[3 * p + 2] = v1[i].x;
+        }
+        if (w) {
+            w[3 * p] = v1[i].y;
+            w[3 * p + 1] = v2[i].x;
+            w[3 * p + 2] = v2[i].y;
+        }
+    }
+    if (F || T) {
+        // F, T were written in the order before the last reorder (that of B);
+        // before any step they are zero at the positions of A
+        std::vector<uint32_t> pid;
+        dem_status r = job_pids(s, J, J.hist_in_A, pid);
+        if (r != DEM_OK) return r;
+        std::vector<double> f(6 * n);
+        for (int c = 0; c < 6; ++c) {
+            if (s->fp64) {
+                HIPCHK(hipMemcpy(f.data() + c * n, (double*)s->fo + (size_t)c * np + p0, n * 8,
+                                 hipMemcpyDeviceToHost));
+            } else {
+                std::vector<float> ff(n);
+                HIPCHK(hipMemcpy(ff.data(), (float*)s->fo + (size_t)c * np + p0, n * 4,
+                                 hipMemcpyDeviceToHost));
+                for (uint64_t k = 0; k < n; ++k) f[c * n + k] = ff[k];
+            }
+        }
+        for (uint64_t i = 0; i < n; ++i) {
+            const uint32_t p = pid[i];
+            for (int a = 0; a < 3; ++a) {
+                if (F) F[3 * p + a] = f[a * n + i];
+                if (T) T[3 * p + a] = f[(3 + a) * n + i];
+            }
+        }
+    }
+    return DEM_OK;
+}
+
+struct Contact {
+    uint32_t i, j;
+    double dt[3];
+};
+
+dem_status read_contacts(dem_pool* s, int slot, std::vector<Contact>& out) {
+    out.clear();
+    const HostJob& J = s->jobs[slot];
+    const uint64_t n = J.n;
+    if (n == 0) return DEM_OK;
+    const uint32_t p0 = J.tile0 * TILE;
+    const int o = s->cur;
+    std::vector<uint2> rows(n);
+    HIPCHK(hipMemcpy(rows.data(), s->rows[o] + p0, n * sizeof(uint2), hipMemcpyDeviceToHost));
+    uint64_t lo = ~0ull, hi = 0;
+    for (const uint2& q : rows)
+        if (q.y) {
+            lo = std::min<uint64_t>(lo, q.x);
+            hi = std::max<uint64_t>(hi, (uint64_t)q.x + q.y);
+        }
+    std::vector<uint32_t> pid;
+    dem_status r = job_pids(s, J, J.hist_in_A, pid);
+    if (r != DEM_OK) return r;
+    if (hi <= lo) return DEM_OK;
+    const uint64_t m = hi - lo;
+    std::vector<uint32_t> tp(m);
+    std::vector<double> td(3 * m);
+    HIPCHK(hipMemcpy(tp.data(), s->tab_pid[o] + lo, m * 4, hipMemcpyDeviceToHost));
+    for (int a = 0; a < 3; ++a)
+        HIPCHK(hipMemcpy(td.data() + a * m, s->tab_dt[o] + (size_t)a * s->cap + lo, m * 8,
+                         hipMemcpyDeviceToHost));
+    for (uint64_t p = 0; p < n; ++p)
+        for (uint32_t k = rows[p].x; k < rows[p].x + rows[p].y; ++k) {
+            const uint64_t q = k - lo;
+            out.push_back({pid[p], tp[q], {td[q], td[m + q], td[2 * m + q]}});
+        }
+    std::sort(out.begin(), out.end(), [](const Contact& a, const Contact& b) {
+        return a.i < b.i || (a.i == b.i && a.j < b.j);
+    });
+    return DEM_OK;
+}
+
+// Install a history (pid keyed) as the old table of the job's next step, in
+// the current sorted order, inside the job's own tile regions.
+dem_status write_contacts(dem_pool* s, int slot, std::vector<Contact>& c) {
+    HostJob& J = s->jobs[slot];
+    const uint64_t n = J.n;
+    std::sort(c.begin(), c.end(), [](const Contact& a, const Contact& b) {
+        return a.i < b.i || (a.i == b.i && a.j < b.j);
+    });
+    for (size_t k = 0; k < c.size(); ++k) {
+        if (c[k].i >= n) return DEM_EINVAL;
+        if (c[k].j >= n && c[k].j < FACE) return DEM_EINVAL;
+        if (c[k].j >= FACE + 6) return DEM_EINVAL;
+        if (c[k].j == c[k].i) return DEM_EINVAL;
+        if (k && c[k].i == c[k - 1].i && c[k].j == c[k - 1].j) return DEM_EINVAL;
+        if (!finite3(c[k].dt)) return DEM_EINVAL;
+    }
+    const uint64_t span = (uint64_t)J.ntiles * TILE;
+    while (c.size() > span * s->slots) {
+        dem_status r = regrow(s, (c.size() + J.ntiles - 1) / std::max<uint32_t>(J.ntiles, 1), s->cur);
+        if (r != DEM_OK) return r;
+    }
+    std::vector<uint32_t> pid;
+    dem_status r = job_pids(s, J, true, pid);
+    if (r != DEM_OK) return r;
+    std::vector<uint32_t> pos(n);
+    for (uint64_t q = 0; q < n; ++q) pos[pid[q]] = (uint32_t)q;
+    const uint32_t p0 = J.tile0 * TILE;
+    const uint64_t base = (uint64_t)p0 * s->slots;
+    // entries grouped by sorted position, each row in partner-id order
+    std::vector<size_t> idx(c.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return pos[c[a].i] < pos[c[b].i]; });
+    const size_t m = c.size();
+    std::vector<uint2> rows(n, make_uint2(0, 0));
+    std::vector<uint32_t> tp(m);
+    std::vector<double> td(3 * std::max<size_t>(m, 1));
+    for (size_t k = 0; k < m; ++k) {
+        const Contact& e = c[idx[k]];
+        uint2& rw = rows[pos[e.i]];
+        if (rw.y == 0) rw.x = (uint32_t)(base + k);
+        rw.y++;
+        tp[k] = e.j;
+        for (int a = 0; a < 3; ++a) td[a * m + k] = e.dt[a];
+    }
+    const int o = s->cur;
+    if (n) HIPCHK(hipMemcpy(s->rows[o] + p0, rows.data(), n * sizeof(uint2), hipMemcpyHostToDevice));
+    if (m) {
+        HIPCHK(hipMemcpy(s->tab_pid[o] + base, tp.data(), m * 4, hipMemcpyHostToDevice));
+        for (int a = 0; a < 3; ++a)
+            HIPCHK(hipMemcpy(s->tab_dt[o] + (size_t)a * s->cap + base, td.data() + a * m, m * 8,
+                             hipMemcpyHostToDevice));
+    }
+    std::vector<uint32_t> idp(n);
+    std::iota(idp.begin(), idp.end(), p0);
+    if (n) HIPCHK(hipMemcpy(s->prev + p0, idp.data(), n * 4, hipMemcpyHostToDevice));
+    J.hist_in_A = true;
+    return DEM_OK;
+}
+
+dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* v, const double* w) {
+    HostJob& J = s->jobs[slot];
+    for (uint64_t k = 0; k < J.n; ++k)
+        if (!finite3(x + 3 * k) || !finite3(v + 3 * k) || !finite3(w + 3 * k)) return DEM_EINVAL;
+    std::vector<Contact> c;
+    dem_status r = read_contacts(s, slot, c);
+    if (r != DEM_OK) return r;
+    Job jd;
+    r = read_job(s, slot, jd);
+    if (r != DEM_OK) return r;
+    r = upload_job(s, slot, x, v, w, jd.t, jd.steps_left);
+    if (r != DEM_OK) return r;
+    // keep the device time, step count and status
+    r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
+    if (r != DEM_OK) return r;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->staging.clear();
+    return write_contacts(s, slot, c);
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -579,27 +1124,18 @@ const char* dem_status_str(dem_status s) {
         case DEM_ECAPACITY: return "contact capacity exceeded";
         case DEM_ENONFINITE: return "non-finite force or state";
         case DEM_EDEVICE: return "HIP runtime error";
-        case DEM_EBUSY: return "busy";
+        case DEM_EBUSY: return "pool full";
     }
     return "unknown status";
 }
 
 uint64_t dem_footprint(const dem_params* P, uint64_t n) {
     if (!P) return 0;
-    const uint64_t cells = std::max<uint64_t>(4 * n, 4096);  // the grid's upper bound
-    const uint64_t cap = tiles_of(n) * TILE * (uint64_t)initial_slots(*P, n);
-    const bool f64 = P->precision == DEM_PREC_FP64;
-    const uint64_t nn = n ? n : 1;
-    uint64_t b = 0;
-    b += 2 * nn * (32 + 48 + 1);        // sorted state and integrated state
-    b += 2 * nn * 8;                    // contact rows, two steps
-    b += 5 * nn * 4;                    // prev, keys and values (two buffers)
-    b += 6 * nn * (f64 ? 8 : 4);        // per-particle F, T
-    b += cells * 8;                     // cell bounds
-    b += cap * (4 + 2 * 28);            // partner list and two history tables
-    b += sort_hist_words((uint32_t)nn) * 4 + 256 * 4 + sizeof(MatTable) + sizeof(Status);
-    b += tiles_of(n) * sizeof(TileStats);
-    return b;
+    const uint64_t cells = std::max<uint64_t>(4 * n, 4096);
+    const uint64_t np = std::max<uint64_t>(1, tiles_of(n)) * TILE;
+    uint64_t slots = 8;
+    if (P->max_contacts) slots = std::max<uint64_t>(1, (P->max_contacts + np - 1) / np);
+    return pool_bytes(np / TILE, cells, 1, P->precision == DEM_PREC_FP64, slots);
 }
 
 dem_status dem_create(const dem_params* params, const dem_material* mats, uint32_t n_mats,
@@ -611,211 +1147,79 @@ dem_status dem_create(const dem_params* params, const dem_material* mats, uint32
     if (r != DEM_OK) return r;
     if (n >= (uint64_t)FACE) return DEM_EINVAL;
     if (n && (!x || !v || !w || !radius)) return DEM_EINVAL;
+    // size the pool for exactly this job
     double rmax = 0.0;
-    for (uint64_t i = 0; i < n; ++i) {
-        if (!(radius[i] > 0.0f) || !std::isfinite(radius[i])) return DEM_EINVAL;
-        if (!finite3(x + 3 * i) || !finite3(v + 3 * i) || !finite3(w + 3 * i)) return DEM_EINVAL;
-        if (mat_id && mat_id[i] >= n_mats) return DEM_EINVAL;
-        rmax = std::max(rmax, (double)radius[i]);
-    }
-    dem_sim* s = new (std::nothrow) dem_sim();
-    if (!s) return DEM_ENOMEM;
-    s->P = *params;
-    s->mats.assign(mats, mats + n_mats);
-    s->n = n;
-    s->stream = (hipStream_t)stream;
-    (void)hipGetDevice(&s->device);
-    s->fp64 = params->precision == DEM_PREC_FP64;
-    s->r.assign(radius, radius + n);
-    s->mat.assign(n, 0);
-    if (mat_id) s->mat.assign(mat_id, mat_id + n);
-    const bool multi = n_mats > 1;
-
-    Layout lay;
-    if (n == 0) {
-        // no particles: any grid with 3 cells per axis will do
+    for (uint64_t i = 0; i < n; ++i)
+        if (radius[i] > rmax) rmax = radius[i];
+    if (n == 0 || !(rmax > 0.0) || !std::isfinite(rmax)) {
         double lmin = INFINITY;
         for (int a = 0; a < 3; ++a) lmin = std::min(lmin, params->hi[a] - params->lo[a]);
         rmax = lmin / 6.1;
     }
+    Layout lay;
     r = plan_grid(*params, rmax, n, lay);
+    if (r != DEM_OK) return r;
+    const uint64_t np = std::max<uint64_t>(1, tiles_of(n)) * TILE;
+    uint32_t slots = 8;
+    if (params->max_contacts)
+        slots = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((params->max_contacts + np - 1) / np, 1024));
+    dem_pool* p = nullptr;
+    r = create_pool(n, (uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2], 1,
+                    params->precision == DEM_PREC_FP64, slots, params->flags, stream, &p);
+    if (r != DEM_OK) return r;
+    int slot = 0;
+    r = add_job(p, params, mats, n_mats, n, x, v, w, radius, mat_id, 0xFFFFFFFFu, &slot);
+    if (r == DEM_OK) r = sync_impl(p);
     if (r != DEM_OK) {
-        delete s;
-        return r;
+        destroy_pool(p);
+        return r == DEM_EBUSY ? DEM_EINVAL : r;
     }
-    Geo& G = s->geo;
-    for (int a = 0; a < 3; ++a) {
-        G.lo[a] = params->lo[a];
-        G.hi[a] = params->hi[a];
-        G.L[a] = params->hi[a] - params->lo[a];
-        G.inv_cell[a] = 1.0 / lay.cell[a];
-        G.nc[a] = lay.nc[a];
-        G.g[a] = params->gravity[a];
+    dem_sim* s = new (std::nothrow) dem_sim();
+    if (!s) {
+        destroy_pool(p);
+        return DEM_ENOMEM;
     }
-    G.walls = params->walls;
-    G.periodic = params->periodic;
-    G.le = params->shear_rate != 0.0;
-    G.key_bits = lay.key_bits;
-    G.le_dv = params->shear_rate * G.L[1];
-    s->ncells = (size_t)lay.nc[0] * lay.nc[1] * lay.nc[2];
-
-    MatTable mt;
-    fill_mat_table(*params, s->mats, mt);
-    // time step: t_c / 50 of two spheres of the smallest radius at 0.1 m/s
-    double dt = params->dt;
-    if (dt == 0.0) {
-        if (n == 0) {
-            dt = 1e-9;
-        } else {
-            uint64_t k = 0;
-            for (uint64_t i = 1; i < n; ++i)
-                if (radius[i] < radius[k]) k = i;
-            const int m = mat_id ? mat_id[k] : 0;
-            const double rk = (double)radius[k];
-            const double mk = mt.mass_pref[m] * rk * rk * rk;
-            const double kn = mt.kn_pref[m * MAXMAT + m] * std::sqrt(rk * rk / (rk + rk));
-            dt = hertz_contact_time(0.5 * mk, kn, 0.1) / 50.0;
-        }
-    }
-    s->dt = dt;
-    G.dt = dt;
-    s->time_done = params->time;
-
-    const size_t nn = n ? n : 1;
-    void *xa, *va, *xb, *vb, *ma = nullptr, *mb = nullptr;
-#define ALLOC_OR_FAIL(call)      \
-    do {                         \
-        r = (call);              \
-        if (r != DEM_OK) {       \
-            destroy_impl(s);     \
-            return r;            \
-        }                        \
-    } while (0)
-    ALLOC_OR_FAIL(dalloc(s, nn * sizeof(double4), &xa));
-    ALLOC_OR_FAIL(dalloc(s, 3 * nn * sizeof(double2), &va));
-    ALLOC_OR_FAIL(dalloc(s, nn * sizeof(double4), &xb));
-    ALLOC_OR_FAIL(dalloc(s, 3 * nn * sizeof(double2), &vb));
-    if (multi) {
-        ALLOC_OR_FAIL(dalloc(s, nn, &ma));
-        ALLOC_OR_FAIL(dalloc(s, nn, &mb));
-    }
-    s->A = state_view(xa, va, ma);
-    s->B = state_view(xb, vb, mb);
-    ALLOC_OR_FAIL(dalloc_t(s, s->ncells, &s->cells));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->rows[0]));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->rows[1]));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->prev));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->keys));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->vals));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->keys_t));
-    ALLOC_OR_FAIL(dalloc_t(s, nn, &s->vals_t));
-    ALLOC_OR_FAIL(dalloc_t(s, sort_hist_words((uint32_t)nn), &s->tile_hist));
-    ALLOC_OR_FAIL(dalloc_t(s, 256, &s->digit_tot));
-    ALLOC_OR_FAIL(dalloc(s, 6 * nn * (s->fp64 ? 8 : 4), &s->fo));
-    ALLOC_OR_FAIL(dalloc_t(s, 1, &s->mt));
-    ALLOC_OR_FAIL(dalloc_t(s, 1, &s->st));
-    s->ntiles = (uint32_t)tiles_of(n);
-    ALLOC_OR_FAIL(dalloc_t(s, s->ntiles, &s->ts));
-    ALLOC_OR_FAIL(alloc_contacts(s, initial_slots(*params, n)));
-#undef ALLOC_OR_FAIL
-    hipError_t e = hipMemcpy(s->mt, &mt, sizeof(MatTable), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(s->st, 0, sizeof(Status));
-    if (e == hipSuccess) e = hipMemset(s->ts, 0, s->ntiles * sizeof(TileStats));
-    if (e == hipSuccess) e = hipMemset(s->rows[0], 0, nn * sizeof(uint2));
-    if (e == hipSuccess) e = hipMemset(s->rows[1], 0, nn * sizeof(uint2));
-    if (e != hipSuccess) {
-        destroy_impl(s);
-        return hip_status(e);
-    }
-    r = upload_and_sort(s, x, v, w);
-    if (r != DEM_OK) {
-        destroy_impl(s);
-        return r;
-    }
+    s->pool = p;
+    s->slot = slot;
     *out = s;
     return DEM_OK;
 }
 
 dem_status dem_step(dem_sim* s, uint32_t nsteps) {
     if (!s) return DEM_EINVAL;
-    if (s->failed != DEM_OK) return s->failed;
-    double t = s->t_pending.empty() ? s->time_done : s->t_pending.back() + s->dt;
-    for (uint32_t q = 0; q < nsteps; ++q) {
-        s->t_pending.push_back(t);
-        dem_status r = enqueue_step(s, s->steps_enqueued, t);
-        if (r != DEM_OK) return r;
-        s->steps_enqueued++;
-        t = t + s->dt;
-    }
-    if (nsteps) s->table_by_pid = false;
-    return DEM_OK;
+    return step_impl(s->pool, nsteps);
+}
+
+// A single simulation reports its job's non-finite failure as an error.
+static dem_status sim_sync(dem_sim* s) {
+    dem_status r = sync_impl(s->pool);
+    if (r != DEM_OK) return r;
+    Job jd;
+    r = read_job(s->pool, s->slot, jd);
+    if (r != DEM_OK) return r;
+    return jd.status == JOB_FAILED ? DEM_ENONFINITE : DEM_OK;
 }
 
 dem_status dem_sync(dem_sim* s) {
     if (!s) return DEM_EINVAL;
-    return sync_impl(s);
+    return sim_sync(s);
 }
 
 dem_status dem_get_state(dem_sim* s, double* x, double* v, double* w, double* F, double* T) {
     if (!s) return DEM_EINVAL;
-    dem_status r = sync_impl(s);
+    dem_status r = sim_sync(s);
     if (r != DEM_OK && r != DEM_ENONFINITE) return r;
-    const uint64_t n = s->n;
-    if (n == 0) return r;
-    std::vector<double4> xr(n);
-    std::vector<double2> vw(3 * n);
-    HIPCHK(hipMemcpy(xr.data(), s->A.xr, n * sizeof(double4), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(vw.data(), s->A.vw, 3 * n * sizeof(double2), hipMemcpyDeviceToHost));
-    for (uint64_t i = 0; i < n; ++i) {
-        uint64_t m;
-        std::memcpy(&m, &xr[i].w, 8);
-        const uint32_t p = (uint32_t)(m >> 32);
-        if (x) {
-            x[3 * p] = xr[i].x;
-            x[3 * p + 1] = xr[i].y;
-            x[3 * p + 2] = xr[i].z;
-        }
-        if (v) {
-            v[3 * p] = vw[i].x;
-            v[3 * p + 1] = vw[i].y;
-            v[3 * p + 2] = vw[n + i].x;
-        }
-        if (w) {
-            w[3 * p] = vw[n + i].y;
-            w[3 * p + 1] = vw[2 * n + i].x;
-            w[3 * p + 2] = vw[2 * n + i].y;
-        }
-    }
-    if (F || T) {
-        std::vector<uint32_t> pid;
-        dem_status r2 = pids_of_B(s, pid);
-        if (r2 != DEM_OK) return r2;
-        std::vector<double> f(6 * n);
-        if (s->fp64) {
-            HIPCHK(hipMemcpy(f.data(), s->fo, 6 * n * 8, hipMemcpyDeviceToHost));
-        } else {
-            std::vector<float> ff(6 * n);
-            HIPCHK(hipMemcpy(ff.data(), s->fo, 6 * n * 4, hipMemcpyDeviceToHost));
-            for (size_t k = 0; k < 6 * n; ++k) f[k] = ff[k];
-        }
-        for (uint64_t i = 0; i < n; ++i) {
-            const uint32_t p = pid[i];
-            for (int a = 0; a < 3; ++a) {
-                if (F) F[3 * p + a] = f[a * n + i];
-                if (T) T[3 * p + a] = f[(3 + a) * n + i];
-            }
-        }
-    }
-    return r;
+    dem_status r2 = get_state_impl(s->pool, s->slot, x, v, w, F, T);
+    return r2 != DEM_OK ? r2 : r;
 }
 
 dem_status dem_get_contacts(dem_sim* s, uint64_t cap, uint32_t* i, uint32_t* j, double* dt_xyz,
                             uint64_t* m) {
     if (!s || !m) return DEM_EINVAL;
-    dem_status r = sync_impl(s);
+    dem_status r = sim_sync(s);
     if (r != DEM_OK) return r;
     std::vector<Contact> c;
-    r = read_contacts(s, c);
+    r = read_contacts(s->pool, s->slot, c);
     if (r != DEM_OK) return r;
     *m = c.size();
     const uint64_t k = std::min<uint64_t>(cap, c.size());
@@ -832,7 +1236,7 @@ dem_status dem_set_contacts(dem_sim* s, uint64_t m, const uint32_t* i, const uin
                             const double* dt_xyz) {
     if (!s) return DEM_EINVAL;
     if (m && (!i || !j || !dt_xyz)) return DEM_EINVAL;
-    dem_status r = sync_impl(s);
+    dem_status r = sim_sync(s);
     if (r != DEM_OK) return r;
     std::vector<Contact> c(m);
     for (uint64_t q = 0; q < m; ++q) {
@@ -840,65 +1244,59 @@ dem_status dem_set_contacts(dem_sim* s, uint64_t m, const uint32_t* i, const uin
         c[q].j = j[q];
         for (int a = 0; a < 3; ++a) c[q].dt[a] = dt_xyz[3 * q + a];
     }
-    return write_contacts(s, c);
+    return write_contacts(s->pool, s->slot, c);
 }
 
 dem_status dem_set_state(dem_sim* s, const double* x, const double* v, const double* w) {
-    if (!s || (s->n && (!x || !v || !w))) return DEM_EINVAL;
-    dem_status r = sync_impl(s);
+    if (!s || (s->pool->jobs[s->slot].n && (!x || !v || !w))) return DEM_EINVAL;
+    dem_status r = sim_sync(s);
     if (r != DEM_OK) return r;
-    for (uint64_t k = 0; k < s->n; ++k)
-        if (!finite3(x + 3 * k) || !finite3(v + 3 * k) || !finite3(w + 3 * k)) return DEM_EINVAL;
-    std::vector<Contact> c;
-    r = read_contacts(s, c);
-    if (r != DEM_OK) return r;
-    r = upload_and_sort(s, x, v, w);
-    if (r != DEM_OK) return r;
-    return write_contacts(s, c);
+    return set_state_impl(s->pool, s->slot, x, v, w);
 }
 
 dem_status dem_get_info(dem_sim* s, dem_info* info) {
     if (!s || !info) return DEM_EINVAL;
-    dem_status r = sync_impl(s);
-    Status h;
-    dem_status r2 = read_status(s, h);
+    dem_pool* p = s->pool;
+    dem_status r = sim_sync(s);
+    if (r != DEM_OK && r != DEM_ENONFINITE) return r;
+    Job jd;
+    dem_status r2 = read_job(p, s->slot, jd);
     if (r2 != DEM_OK) return r2;
+    const HostJob& J = p->jobs[s->slot];
     std::memset(info, 0, sizeof(*info));
-    info->n = s->n;
-    info->steps_done = h.steps_done;
-    info->dt = s->dt;
-    info->time = s->time_done;
-    std::vector<TileStats> ts(s->ntiles);
-    HIPCHK(hipMemcpy(ts.data(), s->ts, s->ntiles * sizeof(TileStats), hipMemcpyDeviceToHost));
+    info->n = J.n;
+    info->steps_done = jd.steps_done;
+    info->dt = J.geo.dt;
+    info->time = jd.t;
+    info->capacity = (uint64_t)J.ntiles * TILE * p->slots;
+    info->regrows = p->regrows;
+    for (int a = 0; a < 3; ++a) info->cells[a] = (uint32_t)J.lay.nc[a];
+    info->key_bits = (uint32_t)J.lay.key_bits;
+    info->device_bytes = p->device_bytes;
+    std::vector<TileStats> ts(J.ntiles);
+    if (J.ntiles)
+        HIPCHK(hipMemcpy(ts.data(), p->ts + J.tile0, J.ntiles * sizeof(TileStats), hipMemcpyDeviceToHost));
     for (const TileStats& q : ts) {
         info->sum_contacts += q.m;
         info->sum_matched += q.matched;
         info->sum_old += q.old;
     }
-    if (s->n) {
-        std::vector<uint2> rows(s->n);
-        HIPCHK(hipMemcpy(rows.data(), s->rows[s->steps_confirmed & 1], s->n * sizeof(uint2),
+    if (J.n) {
+        std::vector<uint2> rows(J.n);
+        HIPCHK(hipMemcpy(rows.data(), p->rows[p->cur] + J.tile0 * TILE, J.n * sizeof(uint2),
                          hipMemcpyDeviceToHost));
         for (const uint2& q : rows) info->contacts += q.y;
     }
-    info->capacity = s->cap;
-    info->regrows = s->regrows;
-    for (int a = 0; a < 3; ++a) info->cells[a] = (uint32_t)s->geo.nc[a];
-    info->key_bits = (uint32_t)s->geo.key_bits;
-    info->device_bytes = s->device_bytes;
     return r;
 }
 
-void dem_destroy(dem_sim* s) { destroy_impl(s); }
-
-dem_status dem_profile(dem_sim* s, int enable) {
-    if (!s) return DEM_EINVAL;
-    s->prof = enable != 0;
-    return DEM_OK;
+void dem_destroy(dem_sim* s) {
+    if (!s) return;
+    destroy_pool(s->pool);
+    delete s;
 }
 
-dem_status dem_profile_read(dem_sim* s, double* ms, uint64_t* launches) {
-    if (!s || !ms || !launches) return DEM_EINVAL;
+static dem_status profile_read_impl(dem_pool* s, double* ms, uint64_t* launches) {
     HIPCHK(hipStreamSynchronize(s->stream));
     for (int p = 0; p < DEM_NPHASE; ++p) {
         ms[p] = 0.0;
@@ -916,5 +1314,151 @@ dem_status dem_profile_read(dem_sim* s, double* ms, uint64_t* launches) {
     s->prof_used = 0;
     return DEM_OK;
 }
+
+dem_status dem_profile(dem_sim* s, int enable) {
+    if (!s) return DEM_EINVAL;
+    s->pool->prof = enable != 0;
+    return DEM_OK;
+}
+
+dem_status dem_profile_read(dem_sim* s, double* ms, uint64_t* launches) {
+    if (!s || !ms || !launches) return DEM_EINVAL;
+    return profile_read_impl(s->pool, ms, launches);
+}
+
+// ------------------------------------------------------------------- pool
+uint64_t dem_pool_footprint(const dem_pool_params* pp) {
+    if (!pp) return 0;
+    return pool_bytes(std::max<uint64_t>(1, tiles_of(pp->max_particles)), pp->max_cells, pp->max_jobs,
+                      pp->precision == DEM_PREC_FP64, pp->contact_slots ? pp->contact_slots : 8);
+}
+
+dem_status dem_pool_create(const dem_pool_params* pp, void* stream, dem_pool** out) {
+    if (!pp || !out) return DEM_EINVAL;
+    *out = nullptr;
+    if (pp->precision != DEM_PREC_FP64 && pp->precision != DEM_PREC_MIXED) return DEM_EINVAL;
+    if (pp->max_jobs < 1 || pp->max_particles < 1 || pp->max_cells < 1) return DEM_EINVAL;
+    if (pp->contact_slots > 1024) return DEM_EINVAL;
+    const uint32_t slots = pp->contact_slots ? (uint32_t)pp->contact_slots : 8u;
+    return create_pool(pp->max_particles, pp->max_cells, pp->max_jobs,
+                       pp->precision == DEM_PREC_FP64, slots, pp->flags, stream, out);
+}
+
+dem_status dem_pool_add(dem_pool* s, const dem_params* params, const dem_material* mats,
+                        uint32_t n_mats, uint64_t n, const double* x, const double* v,
+                        const double* w, const float* radius, const uint16_t* mat_id,
+                        uint32_t steps, uint64_t* job) {
+    if (!s || !job) return DEM_EINVAL;
+    if (s->failed != DEM_OK) return s->failed;
+    if (steps == 0 || steps == 0xFFFFFFFFu) return DEM_EINVAL;
+    // admission happens between steps: enqueued steps complete first
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    int slot = 0;
+    r = add_job(s, params, mats, n_mats, n, x, v, w, radius, mat_id, steps, &slot);
+    if (r != DEM_OK) return r;
+    *job = s->jobs[slot].id;
+    return DEM_OK;
+}
+
+static int slot_of(dem_pool* s, uint64_t id) {
+    for (uint32_t k = 0; k < s->max_jobs; ++k)
+        if (s->jobs[k].used && s->jobs[k].id == id) return (int)k;
+    return -1;
+}
+
+dem_status dem_pool_step(dem_pool* s, uint32_t nsteps) {
+    if (!s) return DEM_EINVAL;
+    return step_impl(s, nsteps);
+}
+
+dem_status dem_pool_sync(dem_pool* s) {
+    if (!s) return DEM_EINVAL;
+    return sync_impl(s);
+}
+
+dem_status dem_pool_poll(dem_pool* s, uint64_t* done, uint32_t cap, uint32_t* n_done) {
+    if (!s || !n_done || (cap && !done)) return DEM_EINVAL;
+    *n_done = 0;
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    std::vector<Job> jd(s->max_jobs);
+    HIPCHK(hipMemcpy(jd.data(), s->jobs_d, s->max_jobs * sizeof(Job), hipMemcpyDeviceToHost));
+    uint32_t k = 0;
+    for (uint32_t q = 0; q < s->max_jobs && k < cap; ++q) {
+        HostJob& J = s->jobs[q];
+        if (!J.used || J.reported || jd[q].status == JOB_ACTIVE) continue;
+        done[k++] = J.id;
+        J.reported = true;
+    }
+    *n_done = k;
+    return DEM_OK;
+}
+
+dem_status dem_pool_job_info(dem_pool* s, uint64_t job, dem_job_info* info) {
+    if (!s || !info) return DEM_EINVAL;
+    const int slot = slot_of(s, job);
+    if (slot < 0) return DEM_EINVAL;
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    Job jd;
+    r = read_job(s, slot, jd);
+    if (r != DEM_OK) return r;
+    std::memset(info, 0, sizeof(*info));
+    info->status = jd.status == JOB_ACTIVE ? DEM_JOB_RUNNING
+                                           : (jd.status == JOB_DONE ? DEM_JOB_DONE : DEM_JOB_FAILED);
+    info->n = s->jobs[slot].n;
+    info->steps_done = jd.steps_done;
+    info->steps_left = jd.steps_left;
+    info->time = jd.t;
+    info->dt = s->jobs[slot].geo.dt;
+    return DEM_OK;
+}
+
+dem_status dem_pool_get_state(dem_pool* s, uint64_t job, double* x, double* v, double* w) {
+    if (!s) return DEM_EINVAL;
+    const int slot = slot_of(s, job);
+    if (slot < 0) return DEM_EINVAL;
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    return get_state_impl(s, slot, x, v, w, nullptr, nullptr);
+}
+
+dem_status dem_pool_remove(dem_pool* s, uint64_t job) {
+    if (!s) return DEM_EINVAL;
+    const int slot = slot_of(s, job);
+    if (slot < 0) return DEM_EINVAL;
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    return remove_job(s, slot);
+}
+
+dem_status dem_pool_capacity(dem_pool* s, uint64_t* free_particles, uint64_t* free_cells,
+                             uint32_t* free_jobs) {
+    if (!s) return DEM_EINVAL;
+    uint64_t best = 0, cells = 0;
+    for (const Seg& g : s->segs)
+        if (g.slot < 0) best = std::max<uint64_t>(best, (uint64_t)g.len * TILE);
+    for (auto& f : s->free_cells) cells = std::max<uint64_t>(cells, f.second);
+    uint32_t fj = 0;
+    for (const HostJob& j : s->jobs) fj += j.used ? 0 : 1;
+    if (free_particles) *free_particles = best;
+    if (free_cells) *free_cells = cells;
+    if (free_jobs) *free_jobs = fj;
+    return DEM_OK;
+}
+
+dem_status dem_pool_profile(dem_pool* s, int enable) {
+    if (!s) return DEM_EINVAL;
+    s->prof = enable != 0;
+    return DEM_OK;
+}
+
+dem_status dem_pool_profile_read(dem_pool* s, double* ms, uint64_t* launches) {
+    if (!s || !ms || !launches) return DEM_EINVAL;
+    return profile_read_impl(s, ms, launches);
+}
+
+void dem_pool_destroy(dem_pool* s) { destroy_pool(s); }
 
 }  // extern "C"

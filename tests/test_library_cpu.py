@@ -59,6 +59,35 @@ def test_ctypes_layouts_match_the_header(tmp_path):
     assert got == want
 
 
+def test_pool_ctypes_layouts_match_the_header(tmp_path):
+    prog = tmp_path / "psizes.c"
+    prog.write_text('#include "dem.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu\\n", sizeof(dem_pool_params),'
+                    ' sizeof(dem_job_info), offsetof(dem_pool_params, precision),'
+                    ' offsetof(dem_job_info, n), offsetof(dem_job_info, dt));return 0;}\n')
+    exe = tmp_path / "psizes"
+    subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(binding.PoolParams), ctypes.sizeof(binding.JobInfo),
+            binding.PoolParams.precision.offset, binding.JobInfo.n.offset,
+            binding.JobInfo.dt.offset]
+    assert got == want
+
+
+def test_pool_footprint_and_argument_checks_without_gpu():
+    L = binding.lib()
+    pp = binding.make_pool_params(100_000, 400_000, 64, binding.PREC_MIXED)
+    small = binding.make_pool_params(1_000, 4_096, 4, binding.PREC_MIXED)
+    assert 0 < binding.pool_footprint(small) < binding.pool_footprint(pp)
+    h = ctypes.c_void_p()
+    assert L.dem_pool_create(None, None, ctypes.byref(h)) == -1
+    bad = binding.make_pool_params(1000, 4096, 0, binding.PREC_MIXED)  # no job slots
+    assert L.dem_pool_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    bad = binding.make_pool_params(1000, 4096, 4, 7)  # unknown precision
+    assert L.dem_pool_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+    assert binding.status_str(-6) == "pool full"
+
+
 def test_binding_raises_without_gpu_instead_of_falling_back():
     import gen
     from paper_1503_03553_amd import DemError, Sim
