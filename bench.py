@@ -1,15 +1,24 @@
 #!/usr/bin/env python3
-"""Benchmark of the DEM force step on one MI355X.
+"""Benchmark of the DEM step on one MI355X.
 
-Workload (default): 1,000,000 polydisperse spheres (lognormal radii, median
-4 um, sigma_log 0.15, clipped to [2, 8] um) in a walled box at volume fraction
-0.1 under gravity, half of them seeded touching a neighbour; FP32 contact
-force arithmetic with FP64 overlap, history and integration; 200 steps.  The
-FP64 path on the same input is timed beside it.
+Headline workload (`value`): 1,000,000 polydisperse spheres (lognormal radii,
+median 4 um, sigma_log 0.15, clipped to [2, 8] um) in a walled box at volume
+fraction 0.1 under gravity, half of them seeded touching a neighbour; FP32
+contact force arithmetic with FP64 overlap, history and integration; 200
+steps, one simulation.  Beside it, on the same GPU and in the same run:
+  fp64_plain  the same input with every operation in FP64;
+  batched     256 independent jobs, N log-uniform in [1k, 200k], run in one
+              pool (one set of launches per step), cell factor and job layout
+              picked by the autotuner;
+  serving     a Poisson stream (20 jobs/s) of jobs of 1k-1M particles and
+              100-2000 steps served by continuous batching; p50/p99 latency
+              and aggregate throughput;
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline
+              workload, on the host's cores.
 
-Prints one JSON line: particle-steps/s (whole job), the roofline of the
-dominant kernel (algorithmic bytes / HIP-event-timed launch duration), and
-the FP64 CPU oracle timed on a bounded sample on the host.
+Prints one JSON line.  The roofline object is that of the dominant kernel of
+the headline run: algorithmic bytes per launch / its average duration from
+HIP events recorded on the stream the kernels run on.
 """
 from __future__ import annotations
 
@@ -29,7 +38,9 @@ METRIC = "particle-steps/s at 1M (FP32 batched vs FP64 plain); p50/p99 job laten
 def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False):
     """Algorithmic HBM bytes of one launch (each record counted once)."""
     if phase == "detect":
-        # own record 32, cell range 8, row write 8; partner index 4 per contact
+        # own FP32 record 16 + FP64 position 32, 9 cell-row bounds read as
+        # 27 cells x 8 (cache-resident, counted once per particle: 8), row
+        # write 8; partner index 4 per contact
         return 48 * n + 4 * m
     if phase == "force":
         # reads: state 80, rows 8, prev 4, old row 8, cell bound 4;
@@ -47,7 +58,32 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False):
     return 0
 
 
-def run_gpu(sc, precision, steps, warmup, stream):
+def phase_rows(prof, n, m, m_old, fp64, key_bits):
+    rows = {}
+    for ph, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_s = ms / cnt * 1e-3
+        b = kernel_bytes(ph, n, m, m_old, fp64, key_bits)
+        rows[ph] = dict(avg_us=avg_s * 1e6, bytes=b, gbs=b / avg_s / 1e9)
+    return rows
+
+
+def roofline_of(rows):
+    dom = max(rows, key=lambda p: rows[p]["avg_us"])
+    r = rows[dom]
+    return {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(r["gbs"], 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_launch": int(r["bytes"]),
+            "avg_launch_us": round(r["avg_us"], 2)}
+
+
+def kernels_of(rows):
+    return {k: {"avg_us": round(v["avg_us"], 2), "GBps": round(v["gbs"], 1)} for k, v in rows.items()}
+
+
+# ------------------------------------------------------------ single sim
+def run_single(sc, precision, steps, warmup, stream):
     import torch
     from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, Sim
     sim = Sim.from_scene(sc, precision=precision, stream=stream, flags=FLAG_NO_FORCE_OUTPUT)
@@ -65,37 +101,73 @@ def run_gpu(sc, precision, steps, warmup, stream):
     prof = sim.profile_read()
     info1 = sim.info()
     sim.close()
-    k = info1["steps_done"] - info0["steps_done"]
-    m = (info1["sum_contacts"] - info0["sum_contacts"]) / max(k, 1)
-    m_old = (info1["sum_old"] - info0["sum_old"]) / max(k, 1)
-    matched = (info1["sum_matched"] - info0["sum_matched"]) / max(k, 1)
-    return dict(seconds=t1 - t0, steps=steps, prof=prof, contacts=m, contacts_old=m_old,
-                matched=matched, info=info1)
+    k = max(info1["steps_done"] - info0["steps_done"], 1)
+    return dict(seconds=t1 - t0, steps=steps, prof=prof, info=info1,
+                contacts=(info1["sum_contacts"] - info0["sum_contacts"]) / k,
+                contacts_old=(info1["sum_old"] - info0["sum_old"]) / k,
+                matched=(info1["sum_matched"] - info0["sum_matched"]) / k)
 
 
-def roofline(res, n, fp64):
-    key_bits = res["info"]["key_bits"]
-    rows = {}
-    for ph, (ms, cnt) in res["prof"].items():
-        if cnt == 0:
-            continue
-        avg_s = ms / cnt * 1e-3
-        b = kernel_bytes(ph, n, res["contacts"], res["contacts_old"], fp64, key_bits)
-        rows[ph] = dict(avg_us=avg_s * 1e6, bytes=b, gbs=b / avg_s / 1e9)
-    dom = max(rows, key=lambda p: rows[p]["avg_us"])
-    r = rows[dom]
-    out = {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(r["gbs"], 1),
-           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
-           "traffic": None, "bytes_per_launch": int(r["bytes"]),
-           "avg_launch_us": round(r["avg_us"], 2)}
-    return out, rows
+# --------------------------------------------------------------- batched
+def pool_for(scenes, precision, stream, slack_jobs=0, flags=0):
+    from paper_1503_03553_amd import Pool
+    from paper_1503_03553_amd.binding import job_cells
+    parts = sum(((s.n + 127) // 128) * 128 for s in scenes)
+    cells = sum(job_cells(s) for s in scenes)
+    return Pool(max_particles=max(parts, 128), max_cells=max(cells, 1),
+                max_jobs=len(scenes) + slack_jobs, precision=precision, stream=stream, flags=flags)
 
 
-def cpu_baseline(sc, dt, budget_s):
+def run_batched(scenes, steps, warmup, stream, tune_steps, log):
+    import torch
+    from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, PREC_MIXED, tune
+    make = lambda c: pool_for(scenes, PREC_MIXED, stream, flags=FLAG_NO_FORCE_OUTPUT)
+    t = time.perf_counter()
+    best, table = tune.autotune(make, scenes, steps=tune_steps, warmup=2, log=log)
+    tune_s = time.perf_counter() - t
+    pool = make(best)
+    tune.fill_pool(pool, scenes, warmup + steps, best)
+    pool.step(warmup)
+    pool.sync()
+    pool.profile(True)
+    pool.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pool.step(steps)
+    pool.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = pool.profile_read()
+    done = pool.poll()
+    pool.close()
+    n = sum(s.n for s in scenes)
+    sec = t1 - t0
+    return dict(seconds=sec, n=n, prof=prof, finished=len(done), best=best, tune_s=tune_s,
+                table=[(c, round(s * 1e3, 4)) for c, s in table])
+
+
+# --------------------------------------------------------------- serving
+def run_serving(templates, arr, tmpl, steps, stream, budget_particles, superstep, log):
+    from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, PREC_MIXED, Pool
+    from paper_1503_03553_amd.serve import Request, Server
+    max_jobs = 256
+    pool = Pool(max_particles=budget_particles, max_cells=4 * budget_particles + 4096 * 64,
+                max_jobs=max_jobs, precision=PREC_MIXED, stream=stream, flags=FLAG_NO_FORCE_OUTPUT)
+    reqs = [Request(q, templates[int(tmpl[q])], int(steps[q]), float(arr[q]))
+            for q in range(len(arr))]
+    srv = Server(pool, superstep=superstep)
+    st = srv.run(reqs, deadline=600.0)
+    pool.close()
+    log("serving: %s" % json.dumps(st))
+    return st
+
+
+# ----------------------------------------------------------- cpu oracle
+def cpu_baseline(sc, budget_s):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     threads = min(threads, 16)
-    s = oracle.Sim(sc, dt=dt, mode=1, threads=threads)
+    s = oracle.Sim(sc, mode=1, threads=threads)
     t0 = time.perf_counter()
     s.step(1)
     t1 = time.perf_counter() - t0
@@ -117,6 +189,15 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batch-jobs", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--tune-steps", type=int, default=10)
+    ap.add_argument("--serve-horizon", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-budget", type=int, default=8_000_000)
+    ap.add_argument("--superstep", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args()
@@ -125,37 +206,47 @@ def main():
               "(got --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    import gen
-    from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-
     def log(*x):
         if a.verbose:
             print(*x, file=sys.stderr, flush=True)
 
+    import gen
+    # every input is drawn before anything touches the GPU (the generators
+    # fork worker processes)
     t = time.perf_counter()
     sc = gen.config_dilute(n=a.n)
-    log("generated %d spheres in %.1fs" % (sc.n, time.perf_counter() - t))
+    log("headline input: %d spheres in %.1fs" % (sc.n, time.perf_counter() - t))
+    batch = []
+    if not a.no_batch:
+        t = time.perf_counter()
+        sizes = gen.batch_sizes(0, a.batch_jobs)
+        batch = gen.generate_many(gen.config_batch_job,
+                                  [(0, m, int(sizes[m])) for m in range(a.batch_jobs)])
+        log("batched input: %d jobs, %d spheres in %.1fs" % (len(batch), sum(s.n for s in batch),
+                                                              time.perf_counter() - t))
+    serve_in = None
+    if not a.no_serve:
+        t = time.perf_counter()
+        arr, tmpl, steps, sizes = gen.serve_requests(gen.SEED_BASE + 9000, a.serve_horizon,
+                                                     rate=a.serve_rate)
+        templates = gen.generate_many(gen.config_batch_job,
+                                      [(1, m, int(sizes[m])) for m in range(len(sizes))])
+        serve_in = (templates, arr, tmpl, steps)
+        log("serving input: %d requests over %.0fs, %d templates in %.1fs" % (
+            len(arr), a.serve_horizon, len(templates), time.perf_counter() - t))
 
-    mixed = run_gpu(sc, PREC_MIXED, a.steps, a.warmup, stream)
+    import torch
+    from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    mixed = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream)
     n = sc.n
     value = n * a.steps / mixed["seconds"]
-    roof, rows = roofline(mixed, n, fp64=False)
+    rows = phase_rows(mixed["prof"], n, mixed["contacts"], mixed["contacts_old"], False,
+                      mixed["info"]["key_bits"])
     log("mixed", json.dumps(rows))
 
-    extra = {}
-    if not a.no_fp64:
-        f64 = run_gpu(sc, PREC_FP64, a.steps, a.warmup, stream)
-        roof64, rows64 = roofline(f64, n, fp64=True)
-        log("fp64", json.dumps(rows64))
-        extra["fp64_plain"] = {"value": round(n * a.steps / f64["seconds"], 1),
-                               "ms_per_step": round(f64["seconds"] / a.steps * 1e3, 4),
-                               "roofline": roof64}
-
-    step_bytes = sum(r["bytes"] for r in rows.values())
-    step_time = sum(r["avg_us"] for r in rows.values()) * 1e-6
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -170,19 +261,59 @@ def main():
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": "dilute-1m: %d polydisperse spheres, phi 0.1, walls, gravity, "
-                               "single simulation" % n,
+                               "one simulation, %d steps" % (n, a.steps),
                    "precision": "mixed: fp32 contact force, fp64 overlap/history/integration",
                    "contacts_per_particle": round(mixed["contacts"] / n, 4),
                    "history_matched_per_step": round(mixed["matched"], 1),
                    "cells": list(mixed["info"]["cells"]), "key_bits": mixed["info"]["key_bits"]},
-        "roofline": roof,
-        "kernels": {k: {"avg_us": round(v["avg_us"], 2), "GBps": round(v["gbs"], 1)}
-                    for k, v in rows.items()},
-        "step_roofline_frac": round(step_bytes / step_time / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline_of(rows),
+        "kernels": kernels_of(rows),
     }
-    out.update(extra)
+    step_bytes = sum(r["bytes"] for r in rows.values())
+    step_time = sum(r["avg_us"] for r in rows.values()) * 1e-6
+    out["step_roofline_frac"] = round(step_bytes / step_time / 1e9 / HBM_PEAK_GBS, 4)
+
+    if not a.no_fp64:
+        f64 = run_single(sc, PREC_FP64, a.steps, a.warmup, stream)
+        rows64 = phase_rows(f64["prof"], n, f64["contacts"], f64["contacts_old"], True,
+                            f64["info"]["key_bits"])
+        log("fp64", json.dumps(rows64))
+        out["fp64_plain"] = {"value": round(n * a.steps / f64["seconds"], 1),
+                             "unit": "particle-steps/s",
+                             "ms_per_step": round(f64["seconds"] / a.steps * 1e3, 4),
+                             "roofline": roofline_of(rows64), "kernels": kernels_of(rows64)}
+
+    if batch:
+        b = run_batched(batch, a.batch_steps, a.warmup, stream, a.tune_steps, log)
+        brows = phase_rows(b["prof"], b["n"], 0, 0, False, 24)
+        out["batched"] = {"value": round(b["n"] * a.batch_steps / b["seconds"], 1),
+                          "unit": "particle-steps/s",
+                          "jobs": len(batch), "particles": b["n"], "steps": a.batch_steps,
+                          "ms_per_step": round(b["seconds"] / a.batch_steps * 1e3, 4),
+                          "finished": b["finished"],
+                          "autotuned": b["best"], "tune_seconds": round(b["tune_s"], 2),
+                          "tune_table_ms_per_step": b["table"],
+                          "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in brows.items()}}
+        if "fp64_plain" in out:
+            out["batched"]["vs_fp64_plain"] = round(out["batched"]["value"] /
+                                                    out["fp64_plain"]["value"], 3)
+
+    if serve_in is not None:
+        templates, arr, tmpl, steps = serve_in
+        st = run_serving(templates, arr, tmpl, steps, stream, a.serve_budget, a.superstep, log)
+        out["serving"] = {"rate_jobs_per_s": a.serve_rate, "horizon_s": a.serve_horizon,
+                          "requests": int(len(arr)), "budget_particles": a.serve_budget,
+                          "superstep": a.superstep,
+                          "p50_latency_s": round(st["p50_s"], 4),
+                          "p99_latency_s": round(st["p99_s"], 4),
+                          "wait_p50_s": round(st["wait_p50_s"], 4),
+                          "wait_p99_s": round(st["wait_p99_s"], 4),
+                          "value": round(st["particle_steps_per_s"], 1),
+                          "unit": "particle-steps/s", "makespan_s": round(st["makespan_s"], 3),
+                          "failed": st["failed"]}
+
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sc, None, a.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(sc, a.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

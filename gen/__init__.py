@@ -104,8 +104,20 @@ def lognormal_radii(rng, n, median=4e-6, sigma=0.15, rmin=2e-6, rmax=8e-6):
     return f32(np.clip(r, rmin, rmax))
 
 
-def rsa(r, lo, hi, periodic=0, p_touch=0.0, touch_max=2e-3, seed=0, max_attempts=100000):
-    """Random sequential addition; returns (n,3) positions (raises if it jams)."""
+def rsa(r, lo, hi, periodic=0, p_touch=0.0, touch_max=2e-3, seed=0, max_attempts=100000,
+        big_first=False):
+    """Random sequential addition; returns (n,3) positions (raises if it jams).
+
+    big_first places the spheres in order of decreasing radius (stable), which
+    reaches higher volume fractions before jamming; positions are returned in
+    the order of r either way."""
+    if big_first:
+        r64 = np.asarray(r, dtype=np.float64)
+        order = np.argsort(-r64, kind="stable")
+        xs = rsa(r64[order], lo, hi, periodic, p_touch, touch_max, seed, max_attempts)
+        x = np.empty_like(xs)
+        x[order] = xs
+        return x
     r = np.ascontiguousarray(r, dtype=np.float64)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
     hi = np.ascontiguousarray(hi, dtype=np.float64)
@@ -166,22 +178,65 @@ def config_dilute(seed=None, n=1_000_000, p_touch=0.5, touch_max=2e-3):
 
 
 def config_batch_job(k, m, n=None):
-    """Job m of a batched workload: N log-uniform in [1k, 200k], phi ~ U[0.1, 0.3]
-    by RSA (touch-seeded), restitution ~ U[0.3, 0.9], mu ~ U[0.1, 0.5]."""
+    """Job m of a batched workload: N log-uniform in [1k, 200k], phi ~ U[0.1, 0.4]
+    by RSA (touch-seeded, largest spheres first; RSA jams before 0.5),
+    restitution ~ U[0.3, 0.9], mu ~ U[0.1, 0.5]."""
     seed = SEED_BASE + 1000 * k + m
     rng = np.random.Generator(np.random.PCG64(seed))
     if n is None:
         n = int(np.exp(rng.uniform(np.log(1e3), np.log(2e5))))
-    phi = float(rng.uniform(0.1, 0.3))
+    phi = float(rng.uniform(0.1, 0.4))
     eps = float(rng.uniform(0.3, 0.9))
     mu = float(rng.uniform(0.1, 0.5))
     r = lognormal_radii(rng, n)
     L = box_side(r, phi)
     lo, hi = np.zeros(3), np.full(3, L)
-    x = rsa(r, lo, hi, p_touch=0.5, seed=seed)
+    x = rsa(r, lo, hi, p_touch=0.5, seed=seed, big_first=True)
     mats = [Material.make(restitution=eps, mu=mu)]
     return _finish(rng, x, r, lo, hi, mats, steps=500, name="batch-job-%d" % m,
                    meta=dict(phi=phi))
+
+
+def batch_sizes(k, jobs, lo=1e3, hi=2e5):
+    """Particle counts of a batched workload: log-uniform in [lo, hi]."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7000 + k))
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), size=jobs)).astype(np.int64)
+
+
+def serve_requests(seed, horizon_s, rate=20.0, n_lo=1e3, n_hi=1e6, steps_lo=100,
+                   steps_hi=2000, templates=32):
+    """A Poisson arrival stream of simulation requests.
+
+    Returns (arrival times [s], template index, steps) for arrivals within
+    horizon_s at `rate` jobs/s, and the particle counts of the `templates`
+    scene templates (log-uniform in [n_lo, n_hi]); request q runs template
+    tmpl[q] for steps[q] steps (uniform integers in [steps_lo, steps_hi])."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sizes = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=templates)).astype(np.int64)
+    t, arr = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= horizon_s:
+            break
+        arr.append(t)
+    arr = np.array(arr)
+    tmpl = rng.integers(0, templates, size=arr.size)
+    steps = rng.integers(steps_lo, steps_hi + 1, size=arr.size)
+    return arr, tmpl, steps, sizes
+
+
+def generate_many(fn, args, workers=None):
+    """fn(*a) for every a in args in a pool of processes (CPU only: call it
+    before anything in the process has touched a GPU)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1 or len(args) <= 1:
+        return [fn(*a) for a in args]
+    build_helper()
+    with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        futs = [ex.submit(fn, *a) for a in args]
+        return [f.result() for f in futs]
 
 
 # ---------------------------------------------------------------- tiny scenes

@@ -274,6 +274,12 @@ dem_status dem_pool_remove(dem_pool *pool, uint64_t job);
 dem_status dem_pool_capacity(dem_pool *pool, uint64_t *free_particles, uint64_t *free_cells,
                              uint32_t *free_jobs);
 
+/* Cells of the grid a job of n particles with these parameters and largest
+ * radius rmax gets (what it takes of the pool's max_cells); 0 if the
+ * parameters are invalid.  With dem_pool_capacity this tells whether a job
+ * fits before its data is prepared. */
+uint64_t dem_job_cells(const dem_params *params, uint64_t n, double rmax);
+
 /* Kernel timing of the pool's steps, as dem_profile / dem_profile_read. */
 dem_status dem_pool_profile(dem_pool *pool, int enable);
 dem_status dem_pool_profile_read(dem_pool *pool, double *ms, uint64_t *launches);

@@ -30,6 +30,7 @@ EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state", "dem_get_conta
            "dem_footprint", "dem_profile", "dem_profile_read", "dem_pool_footprint",
            "dem_pool_create", "dem_pool_add", "dem_pool_step", "dem_pool_sync", "dem_pool_poll",
            "dem_pool_job_info", "dem_pool_get_state", "dem_pool_remove", "dem_pool_capacity",
+           "dem_job_cells",
            "dem_pool_profile", "dem_pool_profile_read", "dem_pool_destroy")
 
 JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2
@@ -148,6 +149,8 @@ def lib():
         L.dem_pool_remove.argtypes = [_vp, ctypes.c_uint64]
         L.dem_pool_capacity.restype = ctypes.c_int
         L.dem_pool_capacity.argtypes = [_vp, u64p, u64p, u32p]
+        L.dem_job_cells.restype = ctypes.c_uint64
+        L.dem_job_cells.argtypes = [P, ctypes.c_uint64, ctypes.c_double]
         L.dem_pool_profile.restype = ctypes.c_int
         L.dem_pool_profile.argtypes = [_vp, ctypes.c_int]
         L.dem_pool_profile_read.restype = ctypes.c_int
@@ -348,6 +351,24 @@ def pool_footprint(pp: PoolParams) -> int:
     return int(lib().dem_pool_footprint(ctypes.byref(pp)))
 
 
+def job_cells(sc, cell_size=0.0) -> int:
+    """Cells a job of this scene takes from a pool (dem_job_cells)."""
+    P = make_params(sc.lo, sc.hi, sc.walls, sc.periodic, sc.gravity, sc.shear_rate, sc.dt,
+                    0.0, PREC_MIXED, sc.kn_form, cell_size)
+    rmax = float(np.max(np.asarray(sc.r, np.float32))) if len(sc.r) else 0.0
+    if rmax <= 0.0:
+        rmax = float(np.min(np.asarray(sc.hi) - np.asarray(sc.lo))) / 6.1
+    return int(lib().dem_job_cells(ctypes.byref(P), int(len(sc.r)), rmax))
+
+
+def job_fits(sc, cap, cell_size=0.0) -> bool:
+    """Whether a scene fits the free capacity `cap` (dict of Pool.capacity)."""
+    n = int(len(sc.r))
+    tiles = (n + 127) // 128
+    c = job_cells(sc, cell_size)
+    return c > 0 and tiles * 128 <= cap["particles"] and c <= cap["cells"]
+
+
 class Pool:
     """Many simulations advanced by shared launches (dem_pool_*)."""
 
@@ -437,6 +458,11 @@ class Pool:
         _check(lib().dem_pool_capacity(self._handle(), ctypes.byref(p), ctypes.byref(c),
                                        ctypes.byref(j)), "dem_pool_capacity")
         return dict(particles=p.value, cells=c.value, jobs=j.value)
+
+    def fits(self, sc, cell_size=0.0) -> bool:
+        """Whether a job of this scene fits in the pool now."""
+        cap = self.capacity()
+        return cap["jobs"] >= 1 and job_fits(sc, cap, cell_size)
 
     def profile(self, enable=True):
         _check(lib().dem_pool_profile(self._handle(), 1 if enable else 0), "dem_pool_profile")

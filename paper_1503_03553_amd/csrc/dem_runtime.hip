@@ -520,13 +520,14 @@ void release_cells(dem_pool* s, uint64_t start, uint64_t len) {
 }
 
 // Host-side placement of a job's particles in cell order (stable by particle
-// id) with its cell bounds: the device only ever re-sorts jobs it already has.
+// id) with its cell bounds relative to the job's first position: the device
+// only ever re-sorts jobs it already has.
 struct Placed {
     std::vector<double4> xr;
     std::vector<float4> xf;
     std::vector<double2> vw0, vw1, vw2;
     std::vector<uint8_t> mat;
-    std::vector<uint2> cells;
+    std::vector<uint2> cells;  // (start, end) relative to the job; (0, 0) = empty
 };
 
 uint32_t host_cell_coord(const Geo& G, double x, int a) {
@@ -536,8 +537,7 @@ uint32_t host_cell_coord(const Geo& G, double x, int a) {
     return (uint32_t)f;
 }
 
-void place_job(const HostJob& J, uint32_t p0, const double* x, const double* v, const double* w,
-               Placed& out) {
+void place_job(const HostJob& J, const double* x, const double* v, const double* w, Placed& out) {
     const uint64_t n = J.n;
     const Geo& G = J.geo;
     std::vector<uint32_t> key(n), lin(n);
@@ -574,19 +574,21 @@ void place_job(const HostJob& J, uint32_t p0, const double* x, const double* v, 
         out.vw2[q] = make_double2(w[3 * i + 1], w[3 * i + 2]);
         out.mat[q] = (uint8_t)J.mat[i];
         const uint32_t k = key[i];
-        if (q == 0 || key[order[q - 1]] != k) out.cells[lin[i]].x = p0 + (uint32_t)q;
-        if (q + 1 == n || key[order[q + 1]] != k) out.cells[lin[i]].y = p0 + (uint32_t)q + 1;
+        if (q == 0 || key[order[q - 1]] != k) out.cells[lin[i]].x = (uint32_t)q;
+        if (q + 1 == n || key[order[q + 1]] != k) out.cells[lin[i]].y = (uint32_t)q + 1;
     }
 }
 
-// Upload a job's state (sorted on the host), its cells, an empty history and
-// identity map, its descriptor and materials.
-dem_status upload_job(dem_pool* s, int slot, const double* x, const double* v, const double* w,
-                      double t0, uint32_t steps) {
+// Upload a placed job (its state, cells, an empty history and identity map,
+// its descriptor and materials) at its tiles and cells.
+dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t steps) {
     HostJob& J = s->jobs[slot];
     const uint32_t p0 = J.tile0 * TILE;
-    Placed pl;
-    place_job(J, p0, x, v, w, pl);
+    for (uint2& c : pl.cells)
+        if (c.y > c.x) {
+            c.x += p0;
+            c.y += p0;
+        }
     const uint64_t n = J.n, np = (uint64_t)s->max_tiles * TILE;
     dem_status r = DEM_OK;
     auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -637,15 +639,19 @@ dem_status upload_job(dem_pool* s, int slot, const double* x, const double* v, c
     return r;
 }
 
-// A job's constants and memory: validates, plans the grid, takes tiles and cells.
-dem_status add_job(dem_pool* s, const dem_params* params, const dem_material* mats, uint32_t n_mats,
-                   uint64_t n, const double* x, const double* v, const double* w,
-                   const float* radius, const uint16_t* mat_id, uint32_t steps, int* slot_out) {
+// A job before it has a place in a pool: validated constants, grid, time
+// step and its particles in cell order.  Host work only.
+struct Prepared {
+    HostJob J;
+    Placed pl;
+};
+
+dem_status prepare_job(const dem_params* params, const dem_material* mats, uint32_t n_mats,
+                       uint64_t n, const double* x, const double* v, const double* w,
+                       const float* radius, const uint16_t* mat_id, Prepared& pj) {
     dem_status r = validate(params, mats, n_mats);
     if (r != DEM_OK) return r;
-    if ((params->precision == DEM_PREC_FP64) != s->fp64) return DEM_EINVAL;
     if (n >= (uint64_t)FACE) return DEM_EINVAL;
-    if (n > (uint64_t)s->max_tiles * TILE) return DEM_EBUSY;
     if (n && (!x || !v || !w || !radius)) return DEM_EINVAL;
     double rmax = 0.0;
     for (uint64_t i = 0; i < n; ++i) {
@@ -662,33 +668,13 @@ dem_status add_job(dem_pool* s, const dem_params* params, const dem_material* ma
     Layout lay;
     r = plan_grid(*params, rmax, n, lay);
     if (r != DEM_OK) return r;
-    int slot = -1;
-    for (uint32_t k = 0; k < s->max_jobs; ++k)
-        if (!s->jobs[k].used) {
-            slot = (int)k;
-            break;
-        }
-    if (slot < 0) return DEM_EBUSY;
-    const uint64_t ncells = (uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2];
-    const uint32_t ntiles = (uint32_t)tiles_of(n);
-    const long long cb = take_cells(s, ncells);
-    if (cb < 0) return DEM_EBUSY;
-    const int t0 = take_tiles(s, ntiles, slot);
-    if (t0 < 0) {
-        release_cells(s, (uint64_t)cb, ncells);
-        return DEM_EBUSY;
-    }
-    HostJob& J = s->jobs[slot];
+    HostJob& J = pj.J;
     J = HostJob();
-    J.used = true;
-    J.id = s->next_id++;
     J.P = *params;
     J.mats.assign(mats, mats + n_mats);
     J.n = n;
-    J.tile0 = (uint32_t)t0;
-    J.ntiles = ntiles;
-    J.cell_base = (uint32_t)cb;
-    J.ncells = (uint32_t)ncells;
+    J.ntiles = (uint32_t)tiles_of(n);
+    J.ncells = (uint32_t)((uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2]);
     J.lay = lay;
     J.multi_mat = n_mats > 1;
     J.r.assign(radius, radius + n);
@@ -730,8 +716,38 @@ dem_status add_job(dem_pool* s, const dem_params* params, const dem_material* ma
         }
     }
     G.dt = dt;
-    r = upload_layout(s);
-    if (r == DEM_OK) r = upload_job(s, slot, x, v, w, params->time, steps);
+    place_job(J, x, v, w, pj.pl);
+    return DEM_OK;
+}
+
+// Give a prepared job a slot, tiles and cells in the pool and upload it.
+// The pool must have no unconfirmed steps.
+dem_status commit_job(dem_pool* s, Prepared& pj, uint32_t steps, int* slot_out) {
+    const HostJob& P = pj.J;
+    if ((P.P.precision == DEM_PREC_FP64) != s->fp64) return DEM_EINVAL;
+    if (P.n > (uint64_t)s->max_tiles * TILE) return DEM_EBUSY;
+    int slot = -1;
+    for (uint32_t k = 0; k < s->max_jobs; ++k)
+        if (!s->jobs[k].used) {
+            slot = (int)k;
+            break;
+        }
+    if (slot < 0) return DEM_EBUSY;
+    const long long cb = take_cells(s, P.ncells);
+    if (cb < 0) return DEM_EBUSY;
+    const int t0 = take_tiles(s, P.ntiles, slot);
+    if (t0 < 0) {
+        release_cells(s, (uint64_t)cb, P.ncells);
+        return DEM_EBUSY;
+    }
+    HostJob& J = s->jobs[slot];
+    J = std::move(pj.J);
+    J.used = true;
+    J.id = s->next_id++;
+    J.tile0 = (uint32_t)t0;
+    J.cell_base = (uint32_t)cb;
+    dem_status r = upload_layout(s);
+    if (r == DEM_OK) r = upload_job(s, slot, pj.pl, J.P.time, steps);
     if (r != DEM_OK) {
         release_tiles(s, slot);
         release_cells(s, J.cell_base, J.ncells);
@@ -1101,7 +1117,9 @@ dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* 
     Job jd;
     r = read_job(s, slot, jd);
     if (r != DEM_OK) return r;
-    r = upload_job(s, slot, x, v, w, jd.t, jd.steps_left);
+    Placed pl;
+    place_job(J, x, v, w, pl);
+    r = upload_job(s, slot, pl, jd.t, jd.steps_left);
     if (r != DEM_OK) return r;
     // keep the device time, step count and status
     r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
@@ -1168,7 +1186,9 @@ dem_status dem_create(const dem_params* params, const dem_material* mats, uint32
                     params->precision == DEM_PREC_FP64, slots, params->flags, stream, &p);
     if (r != DEM_OK) return r;
     int slot = 0;
-    r = add_job(p, params, mats, n_mats, n, x, v, w, radius, mat_id, 0xFFFFFFFFu, &slot);
+    Prepared pj;
+    r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, pj);
+    if (r == DEM_OK) r = commit_job(p, pj, 0xFFFFFFFFu, &slot);
     if (r == DEM_OK) r = sync_impl(p);
     if (r != DEM_OK) {
         destroy_pool(p);
@@ -1351,11 +1371,16 @@ dem_status dem_pool_add(dem_pool* s, const dem_params* params, const dem_materia
     if (!s || !job) return DEM_EINVAL;
     if (s->failed != DEM_OK) return s->failed;
     if (steps == 0 || steps == 0xFFFFFFFFu) return DEM_EINVAL;
-    // admission happens between steps: enqueued steps complete first
-    dem_status r = sync_impl(s);
+    if (params && (params->precision == DEM_PREC_FP64) != s->fp64) return DEM_EINVAL;
+    // host work first, while enqueued steps run; then the job is placed
+    // between steps
+    Prepared pj;
+    dem_status r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, pj);
+    if (r != DEM_OK) return r;
+    r = sync_impl(s);
     if (r != DEM_OK) return r;
     int slot = 0;
-    r = add_job(s, params, mats, n_mats, n, x, v, w, radius, mat_id, steps, &slot);
+    r = commit_job(s, pj, steps, &slot);
     if (r != DEM_OK) return r;
     *job = s->jobs[slot].id;
     return DEM_OK;
@@ -1431,6 +1456,13 @@ dem_status dem_pool_remove(dem_pool* s, uint64_t job) {
     dem_status r = sync_impl(s);
     if (r != DEM_OK) return r;
     return remove_job(s, slot);
+}
+
+uint64_t dem_job_cells(const dem_params* params, uint64_t n, double rmax) {
+    if (!params || !(rmax > 0.0) || !std::isfinite(rmax)) return 0;
+    Layout lay;
+    if (plan_grid(*params, rmax, n, lay) != DEM_OK) return 0;
+    return (uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2];
 }
 
 dem_status dem_pool_capacity(dem_pool* s, uint64_t* free_particles, uint64_t* free_cells,

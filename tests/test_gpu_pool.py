@@ -157,3 +157,31 @@ def test_pool_argument_errors():
     assert pool.poll() == [j]
     assert pool.poll() == []
     pool.close()
+
+
+def test_served_requests_equal_requests_alone():
+    # continuous batching with real arrivals: requests join while others run,
+    # and each result is bitwise that of the request run alone
+    say("case serving")
+    from paper_1503_03553_amd.serve import Request, Server
+    scs = mixed_scenes()
+    dts = [oracle.Sim(s, mode=1).dt for s in scs]
+    for s, dt in zip(scs, dts):
+        s.dt = dt
+    steps = [60, 15, 30, 45, 25, 35, 50, 10]
+    reqs = [Request(k, scs[k], steps[k], 0.002 * k) for k in range(len(scs))]
+    got = {}
+
+    def keep(req, pool):
+        got[req.rid] = pool.get_state(req.job)
+
+    # room for about half of the jobs at a time
+    pool = Pool(max_particles=3800, max_cells=cells_bound(scs), max_jobs=4, precision=PREC_MIXED)
+    srv = Server(pool, superstep=7, on_done=keep)
+    st = srv.run(reqs, deadline=120.0)
+    pool.close()
+    say("  ", st)
+    assert st["jobs"] == len(scs) and st["failed"] == 0
+    assert srv.supersteps >= 2
+    for k, s in enumerate(scs):
+        assert_same(got[k], alone(s, PREC_MIXED, dts[k], steps[k]), "request %d" % k)
