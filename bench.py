@@ -199,8 +199,18 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=8_000_000)
     ap.add_argument("--superstep", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="first run a plain device-to-device copy of this many MiB 5 times "
+                         "(reference reads/writes for HBM traffic counters)")
+    ap.add_argument("--only", choices=("all", "single", "batch", "serve"), default="all",
+                    help="run one part only (for profiling); the JSON line then lacks the others")
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args()
+    if a.only != "all":
+        a.no_fp64 = a.no_fp64 or a.only != "single"
+        a.no_cpu = True
+        a.no_batch = a.only != "batch"
+        a.no_serve = a.only != "serve"
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(got --gpus %d)" % a.gpus, file=sys.stderr)
@@ -236,10 +246,25 @@ def main():
             len(arr), a.serve_horizon, len(templates), time.perf_counter() - t))
 
     import torch
-    from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if a.calibrate_copy_mb:
+        src = torch.ones(a.calibrate_copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
+    out = {}
+    if a.only in ("all", "single"):
+        out = headline(a, sc, stream, log)
+    run_others(a, out, sc, batch, serve_in, stream, log)
+    print(json.dumps(out), flush=True)
+
+
+def headline(a, sc, stream, log):
+    from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
     mixed = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream)
     n = sc.n
     value = n * a.steps / mixed["seconds"]
@@ -283,6 +308,10 @@ def main():
                              "ms_per_step": round(f64["seconds"] / a.steps * 1e3, 4),
                              "roofline": roofline_of(rows64), "kernels": kernels_of(rows64)}
 
+    return out
+
+
+def run_others(a, out, sc, batch, serve_in, stream, log):
     if batch:
         b = run_batched(batch, a.batch_steps, a.warmup, stream, a.tune_steps, log)
         brows = phase_rows(b["prof"], b["n"], 0, 0, False, 24)
@@ -314,7 +343,6 @@ def main():
 
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, a.cpu_budget)
-    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -214,7 +214,10 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
     constexpr int NW = DTILE / 64;
     __shared__ uint32_t s_pid[KMAX * DTILE];
     __shared__ uint32_t s_j[KMAX * DTILE];
-    __shared__ uint2 s_win[18 * DTILE];  // this lane's non-empty candidate ranges
+    // this lane's non-empty candidate ranges: 9 rows, plus the wrapped x
+    // neighbour of each row with periodic boxes
+    constexpr int NWIN = PER ? 18 : 9;
+    __shared__ uint2 s_win[NWIN * DTILE];
     __shared__ uint32_t s_excl[DTILE + 1];
     __shared__ uint32_t s_w[NW];
     __shared__ uint32_t s_base, s_flag;
@@ -310,7 +313,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
             if (whi[k] > wlo[k]) s_win[(nw++) * DTILE + t] = make_uint2(wlo[k], whi[k]);
-            if (phi[k] > plo[k]) s_win[(nw++) * DTILE + t] = make_uint2(plo[k], phi[k]);
+            if (PER && phi[k] > plo[k]) s_win[(nw++) * DTILE + t] = make_uint2(plo[k], phi[k]);
         }
 
         // FP32 pre-filter: never rejects a pair that touches in FP64 (NaN
@@ -336,33 +339,51 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
             const float sm = rm + b.w;
             return !(dx * dx + dy * dy + dz * dz >= sm * sm);
         };
-        // pass 1: one flat loop over all candidates of all ranges, the next
-        // candidate's record already in flight; survivors go unsorted into
-        // the row buffer
+        // pass 1: one flat loop over all candidates of all ranges with the
+        // records of the next PF candidates already in flight; survivors go
+        // unsorted into the row buffer.  A finished lane keeps loading its
+        // own record (always in bounds) and ignores it.
+        constexpr int PF = 4;
+        constexpr uint32_t NONE = 0xFFFFFFFFu;
         uint32_t sc = 0;
         if (nw > 0) {
             uint32_t w = 0;
             uint2 rg = s_win[t];
-            uint32_t j = rg.x;
-            float4 bn = xf[j];
-            for (;;) {
-                const float4 b = bn;
-                const uint32_t jc = j;
-                bool more = true;
+            uint32_t j = rg.x;  // next candidate to fetch; NONE when all are fetched
+            auto next = [&]() -> uint32_t {
+                if (j == NONE) return NONE;
+                const uint32_t c = j;
                 if (++j == rg.y) {
                     if (++w < nw) {
                         rg = s_win[w * DTILE + t];
                         j = rg.x;
                     } else {
-                        more = false;
+                        j = NONE;
                     }
                 }
-                if (more) bn = xf[j];
+                return c;
+            };
+            float4 q[PF];
+            uint32_t qj[PF];
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                qj[k] = next();
+                q[k] = xf[qj[k] != NONE ? qj[k] : i];
+            }
+            while (qj[0] != NONE) {
+                const float4 b = q[0];
+                const uint32_t jc = qj[0];
+#pragma unroll
+                for (int k = 0; k + 1 < PF; ++k) {
+                    q[k] = q[k + 1];
+                    qj[k] = qj[k + 1];
+                }
+                qj[PF - 1] = next();
+                q[PF - 1] = xf[qj[PF - 1] != NONE ? qj[PF - 1] : i];
                 if (jc != i && pre(b)) {
                     if (sc < KMAX) s_j[sc * DTILE + t] = jc;
                     ++sc;
                 }
-                if (!more) break;
             }
         }
         if (sc > KMAX) {
