@@ -217,7 +217,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
     // this lane's non-empty candidate ranges: 9 rows, plus the wrapped x
     // neighbour of each row with periodic boxes
     constexpr int NWIN = PER ? 18 : 9;
-    __shared__ uint2 s_win[NWIN * DTILE];
+    __shared__ uint2 s_win[(NWIN + 1) * DTILE];  // + the sentinel
     __shared__ uint32_t s_excl[DTILE + 1];
     __shared__ uint32_t s_w[NW];
     __shared__ uint32_t s_base, s_flag;
@@ -340,51 +340,51 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
             return !(dx * dx + dy * dy + dz * dz >= sm * sm);
         };
         // pass 1: one flat loop over all candidates of all ranges with the
-        // records of the next PF candidates already in flight; survivors go
-        // unsorted into the row buffer.  A finished lane keeps loading its
-        // own record (always in bounds) and ignores it.
-        constexpr int PF = 4;
+        // records of the next candidates already in flight; survivors go
+        // unsorted into the row buffer.  The walk over the ranges is
+        // branch-free: the range after the current one is always read ahead
+        // from LDS, and a sentinel range ends the walk.  A finished lane keeps
+        // loading its own record (always in bounds) and ignores it.
         constexpr uint32_t NONE = 0xFFFFFFFFu;
         uint32_t sc = 0;
         if (nw > 0) {
+            s_win[nw * DTILE + t] = make_uint2(NONE, NONE);
             uint32_t w = 0;
             uint2 rg = s_win[t];
-            uint32_t j = rg.x;  // next candidate to fetch; NONE when all are fetched
+            uint2 rn = s_win[DTILE + t];
+            uint32_t j = rg.x;  // next candidate to fetch
             auto next = [&]() -> uint32_t {
-                if (j == NONE) return NONE;
                 const uint32_t c = j;
-                if (++j == rg.y) {
-                    if (++w < nw) {
-                        rg = s_win[w * DTILE + t];
-                        j = rg.x;
-                    } else {
-                        j = NONE;
-                    }
-                }
+                const bool live = c != NONE;
+                const bool sw = live && c + 1 == rg.y;
+                j = !live ? NONE : (sw ? rn.x : c + 1);
+                rg.y = sw ? rn.y : rg.y;
+                w += sw ? 1u : 0u;
+                rn = s_win[min(w + 1, nw) * DTILE + t];
                 return c;
             };
-            float4 q[PF];
-            uint32_t qj[PF];
-#pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                qj[k] = next();
-                q[k] = xf[qj[k] != NONE ? qj[k] : i];
+            // four slots in rotation: a slot's record is tested, then the slot
+            // is refilled with the candidate four places ahead, so three loads
+            // stay in flight while a record is tested
+            uint32_t j0 = next(), j1 = next(), j2 = next(), j3 = next();
+            float4 q0 = xf[j0 != NONE ? j0 : i], q1 = xf[j1 != NONE ? j1 : i];
+            float4 q2 = xf[j2 != NONE ? j2 : i], q3 = xf[j3 != NONE ? j3 : i];
+#define DEM_PRE_STEP(Q, JQ)                                        \
+    {                                                              \
+        if (JQ == NONE) break;                                     \
+        const bool hit = (JQ != i) & pre(Q);                       \
+        s_j[min(sc, (uint32_t)KMAX - 1u) * DTILE + t] = JQ;        \
+        sc += hit ? 1u : 0u;                                       \
+        JQ = next();                                               \
+        Q = xf[JQ != NONE ? JQ : i];                               \
+    }
+            for (;;) {
+                DEM_PRE_STEP(q0, j0)
+                DEM_PRE_STEP(q1, j1)
+                DEM_PRE_STEP(q2, j2)
+                DEM_PRE_STEP(q3, j3)
             }
-            while (qj[0] != NONE) {
-                const float4 b = q[0];
-                const uint32_t jc = qj[0];
-#pragma unroll
-                for (int k = 0; k + 1 < PF; ++k) {
-                    q[k] = q[k + 1];
-                    qj[k] = qj[k + 1];
-                }
-                qj[PF - 1] = next();
-                q[PF - 1] = xf[qj[PF - 1] != NONE ? qj[PF - 1] : i];
-                if (jc != i && pre(b)) {
-                    if (sc < KMAX) s_j[sc * DTILE + t] = jc;
-                    ++sc;
-                }
-            }
+#undef DEM_PRE_STEP
         }
         if (sc > KMAX) {
             cnt = KMAX + 1;  // row buffer too small: reported below
