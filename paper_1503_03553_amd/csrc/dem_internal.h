@@ -33,6 +33,9 @@ struct MatTable {
 struct Geo {
     double lo[3], hi[3], L[3];
     double inv_cell[3];
+    double cw[3];           // cell widths L / nc
+    double reach;           // largest radius of the job plus a rounding margin: a
+                            // partner of particle i is within r_i + reach of it
     double inv_L[3];        // 1 / L, for the minimum-image choice
     int nc[3];
     uint32_t walls, periodic;

@@ -212,12 +212,19 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
                                                   uint2* __restrict__ rows,
                                                   uint32_t* __restrict__ col_j, uint32_t slots) {
     constexpr int NW = DTILE / 64;
-    __shared__ uint32_t s_pid[KMAX * DTILE];
-    __shared__ uint32_t s_j[KMAX * DTILE];
-    // this lane's non-empty candidate ranges: 9 rows, plus the wrapped x
-    // neighbour of each row with periodic boxes
+    // survivors, then contacts, of each lane; slot KMAX takes the writes of
+    // a lane whose row is already full
+    __shared__ uint32_t s_j[(KMAX + 1) * DTILE];
+    // this lane's non-empty candidate ranges (9 rows, plus the wrapped x
+    // neighbour of each row with periodic boxes, plus a sentinel) during the
+    // candidate walk; afterwards the same 8-byte slots (same lane, same
+    // stride, so no lane ever touches another lane's slots) hold the partner
+    // ids of the lane's contacts
     constexpr int NWIN = PER ? 18 : 9;
-    __shared__ uint2 s_win[(NWIN + 1) * DTILE];  // + the sentinel
+    constexpr int NSLOT = (NWIN + 1) > KMAX ? (NWIN + 1) : KMAX;
+    __shared__ uint2 s_winpid[NSLOT * DTILE];
+    uint2* const s_win = s_winpid;
+    auto pid_at = [&](int k) -> uint32_t& { return s_winpid[k * DTILE + threadIdx.x].x; };
     __shared__ uint32_t s_excl[DTILE + 1];
     __shared__ uint32_t s_w[NW];
     __shared__ uint32_t s_base, s_flag;
@@ -236,84 +243,116 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
     const uint32_t i = tile * DTILE + t;
     const bool act = i < J.p0 + J.n;
     const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
-    const bool px = G.periodic & 1u, py = G.periodic & 2u, pz = G.periodic & 4u;
+    // without periodic jobs in the pool the wrap and shear code compiles away
+    const bool px = PER && (G.periodic & 1u), py = PER && (G.periodic & 2u),
+               pz = PER && (G.periodic & 4u), le = PER && G.le;
 
     uint32_t cnt = 0;
+    uint32_t nw = 0;
     if (act) {
         const double4 a = xr[i];
         const double ri = (double)meta_r(a.w);
         const int cx = cell_coord(G, a.x, 0), cy = cell_coord(G, a.y, 1), cz = cell_coord(G, a.z, 2);
-        // the 9 rows: main range [wlo, whi) and wrapped cell [plo, phi)
-        uint32_t wlo[9], whi[9], plo[9], phi[9];
-        {
-            uint32_t il[9], im[9], ih[9];
-            bool okl[9], okm[9], okh[9], wrl[9], wrh[9];
+        // Reach pruning: a partner lies within r_i + reach of the particle, so
+        // a row of cells whose (y, z) slab is farther holds none, nor does an
+        // x-neighbour cell beyond the reach left in x.  Per offset -1, 0, +1
+        // along y and z: whether the neighbour row exists, its (wrapped)
+        // index, and the squared gap from the particle to its slab.
+        const double reach = ri + G.reach;
+        const double reach2 = reach * reach;
+        int qy[3], qz[3], ky[3];
+        bool oky[3], okz[3];
+        double gy2[3], gz2[3];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int oz = k / 3 - 1, oy = k % 3 - 1;
-                int qz = cz + oz, qy = cy + oy, kyc = 0;
-                bool ok = true;
-                if (qz < 0 || qz >= nz) {
-                    if (!pz) ok = false;
-                    qz = qz < 0 ? qz + nz : qz - nz;
-                }
-                if (qy < 0 || qy >= ny) {
-                    if (!py) ok = false;
-                    kyc = qy < 0 ? -1 : 1;
-                    qy -= kyc * ny;
-                }
-                int cxq = cx;
-                if (G.le && kyc != 0) {
-                    // across a sheared y boundary the partner row is offset along x
-                    double fx = floor((a.x - (double)kyc * G.le_shift - G.lo[0]) * G.inv_cell[0]);
-                    const double lim = 2.0 * (double)nx;
-                    if (!(fx >= -lim)) fx = -lim;  // also NaN
-                    if (fx > lim) fx = lim;
-                    cxq = (int)fx % nx;
-                    if (cxq < 0) cxq += nx;
-                }
-                int xl = cxq - 1, xh = cxq + 1;
-                okl[k] = okh[k] = okm[k] = ok;
-                wrl[k] = wrh[k] = false;
-                if (xl < 0) {
-                    if (px) { xl += nx; wrl[k] = true; } else okl[k] = false;
-                }
-                if (xh >= nx) {
-                    if (px) { xh -= nx; wrh[k] = true; } else okh[k] = false;
-                }
-                const uint32_t row = ok ? ((uint32_t)qz * (uint32_t)ny + (uint32_t)qy) * (uint32_t)nx : 0u;
-                il[k] = okl[k] ? row + (uint32_t)xl : 0u;
-                im[k] = ok ? row + (uint32_t)cxq : 0u;
-                ih[k] = okh[k] ? row + (uint32_t)xh : 0u;
+        for (int o = 0; o < 3; ++o) {
+            const int d = o - 1;
+            int y = cy + d, z = cz + d, kk = 0;
+            bool ok_y = true, ok_z = true;
+            if (y < 0 || y >= ny) {
+                if (!py) ok_y = false;
+                kk = y < 0 ? -1 : 1;
+                y -= kk * ny;
             }
-            uint2 cl[9], cm[9], cr[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                cl[k] = cells[il[k]];
-                cm[k] = cells[im[k]];
-                cr[k] = cells[ih[k]];
+            if (z < 0 || z >= nz) {
+                if (!pz) ok_z = false;
+                z = z < 0 ? z + nz : z - nz;
             }
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const uint2 z = make_uint2(0, 0);
-                const uint2 l = okl[k] ? cl[k] : z, m = okm[k] ? cm[k] : z, h = okh[k] ? cr[k] : z;
-                uint32_t lo = 0xFFFFFFFFu, hi = 0u, lo2 = 0xFFFFFFFFu, hi2 = 0u;
-                merge_range(m, lo, hi);
-                if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
-                if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
-                wlo[k] = lo;
-                whi[k] = hi;
-                plo[k] = lo2;
-                phi[k] = hi2;
+            qy[o] = y;
+            qz[o] = z;
+            ky[o] = kk;
+            oky[o] = ok_y;
+            okz[o] = ok_z;
+            double g = 0.0, h = 0.0;
+            if (d > 0) {
+                g = fmax(0.0, G.lo[1] + (double)(cy + 1) * G.cw[1] - a.y);
+                h = fmax(0.0, G.lo[2] + (double)(cz + 1) * G.cw[2] - a.z);
+            } else if (d < 0) {
+                g = fmax(0.0, a.y - (G.lo[1] + (double)cy * G.cw[1]));
+                h = fmax(0.0, a.z - (G.lo[2] + (double)cz * G.cw[2]));
             }
+            gy2[o] = g * g;
+            gz2[o] = h * h;
         }
+        const double dl = a.x - (G.lo[0] + (double)cx * G.cw[0]);
+        const double dh = G.lo[0] + (double)(cx + 1) * G.cw[0] - a.x;
+        const double dl2 = dl > 0.0 ? dl * dl : 0.0, dh2 = dh > 0.0 ? dh * dh : 0.0;
 
-        // non-empty ranges to LDS, so one flat loop walks all candidates
-        uint32_t nw = 0;
+        // the 9 rows' three cells (main range, plus the wrapped x neighbour
+        // with a periodic x axis); all 27 cell bounds are loaded before any is
+        // used
+        uint32_t il[9], im[9], ih[9];
+        bool okl[9], okm[9], okh[9], wrl[9], wrh[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            if (whi[k] > wlo[k]) s_win[(nw++) * DTILE + t] = make_uint2(wlo[k], whi[k]);
-            if (PER && phi[k] > plo[k]) s_win[(nw++) * DTILE + t] = make_uint2(plo[k], phi[k]);
+            const int oz = k / 3, oy = k % 3;
+            const double rx2 = reach2 - gy2[oy] - gz2[oz];
+            const bool ok = oky[oy] && okz[oz] && rx2 > 0.0;
+            int cxq = cx;
+            bool xprune = true;
+            if (le && ky[oy] != 0) {
+                // across a sheared y boundary the partner row is offset along x
+                double fx = floor((a.x - (double)ky[oy] * G.le_shift - G.lo[0]) * G.inv_cell[0]);
+                const double lim = 2.0 * (double)nx;
+                if (!(fx >= -lim)) fx = -lim;  // also NaN
+                if (fx > lim) fx = lim;
+                cxq = (int)fx % nx;
+                if (cxq < 0) cxq += nx;
+                xprune = false;
+            }
+            int xl = cxq - 1, xh = cxq + 1;
+            okm[k] = ok;
+            okl[k] = ok && !(xprune && dl2 >= rx2);
+            okh[k] = ok && !(xprune && dh2 >= rx2);
+            wrl[k] = wrh[k] = false;
+            if (xl < 0) {
+                if (px) { xl += nx; wrl[k] = true; } else okl[k] = false;
+            }
+            if (xh >= nx) {
+                if (px) { xh -= nx; wrh[k] = true; } else okh[k] = false;
+            }
+            const uint32_t row = ok ? ((uint32_t)qz[oz] * (uint32_t)ny + (uint32_t)qy[oy]) * (uint32_t)nx : 0u;
+            il[k] = okl[k] ? row + (uint32_t)xl : 0u;
+            im[k] = ok ? row + (uint32_t)cxq : 0u;
+            ih[k] = okh[k] ? row + (uint32_t)xh : 0u;
+        }
+        uint2 cl[9], cm[9], cr[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            cl[k] = cells[il[k]];
+            cm[k] = cells[im[k]];
+            cr[k] = cells[ih[k]];
+        }
+        // non-empty ranges to LDS, so one flat loop walks all candidates
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const uint2 z = make_uint2(0, 0);
+            const uint2 l = okl[k] ? cl[k] : z, m = okm[k] ? cm[k] : z, h = okh[k] ? cr[k] : z;
+            uint32_t lo = 0xFFFFFFFFu, hi = 0u, lo2 = 0xFFFFFFFFu, hi2 = 0u;
+            merge_range(m, lo, hi);
+            if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
+            if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
+            if (hi > lo) s_win[(nw++) * DTILE + t] = make_uint2(lo, hi);
+            if (PER && hi2 > lo2) s_win[(nw++) * DTILE + t] = make_uint2(lo2, hi2);
         }
 
         // FP32 pre-filter: never rejects a pair that touches in FP64 (NaN
@@ -367,16 +406,19 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
             // is refilled with the candidate four places ahead, so three loads
             // stay in flight while a record is tested
             uint32_t j0 = next(), j1 = next(), j2 = next(), j3 = next();
-            float4 q0 = xf[j0 != NONE ? j0 : i], q1 = xf[j1 != NONE ? j1 : i];
-            float4 q2 = xf[j2 != NONE ? j2 : i], q3 = xf[j3 != NONE ? j3 : i];
+            // every load index is checked against the position capacity
+            // (NONE is above it): an index that is not a position is never read
+            const uint32_t nsz = P.ns;
+            float4 q0 = xf[j0 < nsz ? j0 : i], q1 = xf[j1 < nsz ? j1 : i];
+            float4 q2 = xf[j2 < nsz ? j2 : i], q3 = xf[j3 < nsz ? j3 : i];
 #define DEM_PRE_STEP(Q, JQ)                                        \
     {                                                              \
         if (JQ == NONE) break;                                     \
         const bool hit = (JQ != i) & pre(Q);                       \
-        s_j[min(sc, (uint32_t)KMAX - 1u) * DTILE + t] = JQ;        \
+        s_j[min(sc, (uint32_t)KMAX) * DTILE + t] = JQ;             \
         sc += hit ? 1u : 0u;                                       \
         JQ = next();                                               \
-        Q = xf[JQ != NONE ? JQ : i];                               \
+        Q = xf[JQ < nsz ? JQ : i];                                 \
     }
             for (;;) {
                 DEM_PRE_STEP(q0, j0)
@@ -389,18 +431,19 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
         if (sc > KMAX) {
             cnt = KMAX + 1;  // row buffer too small: reported below
         } else {
-            // pass 2: exact FP64 test of the survivors, two loads in flight;
-            // a hit goes into the row in partner-id order (insertion only
-            // writes slots below the next survivors to be read)
-            for (uint32_t q0 = 0; q0 < sc; q0 += 2) {
-                uint32_t jj[2];
-                double4 bb[2];
+            // pass 2: exact FP64 test of the survivors, four loads in flight;
+            // a hit goes into the row in partner-id order (a group's partner
+            // indices are read before any insertion, and insertion only
+            // writes slots up to the hit count)
+            for (uint32_t q0 = 0; q0 < sc; q0 += 4) {
+                uint32_t jj[4];
+                double4 bb[4];
 #pragma unroll
-                for (int m = 0; m < 2; ++m) jj[m] = q0 + m < sc ? s_j[(q0 + m) * DTILE + t] : 0xFFFFFFFFu;
+                for (int m = 0; m < 4; ++m) jj[m] = q0 + m < sc ? s_j[(q0 + m) * DTILE + t] : 0xFFFFFFFFu;
 #pragma unroll
-                for (int m = 0; m < 2; ++m) bb[m] = xr[jj[m] != 0xFFFFFFFFu ? jj[m] : i];
+                for (int m = 0; m < 4; ++m) bb[m] = xr[jj[m] < P.ns ? jj[m] : i];
 #pragma unroll
-                for (int m = 0; m < 2; ++m) {
+                for (int m = 0; m < 4; ++m) {
                     if (jj[m] == 0xFFFFFFFFu) continue;
                     const double4 b = bb[m];
                     double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
@@ -415,12 +458,12 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
                     if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
                         const uint32_t pj = meta_pid(b.w);
                         int k = (int)cnt;
-                        while (k > 0 && s_pid[(k - 1) * DTILE + t] > pj) {
-                            s_pid[k * DTILE + t] = s_pid[(k - 1) * DTILE + t];
+                        while (k > 0 && pid_at(k - 1) > pj) {
+                            pid_at(k) = pid_at(k - 1);
                             s_j[k * DTILE + t] = s_j[(k - 1) * DTILE + t];
                             --k;
                         }
-                        s_pid[k * DTILE + t] = pj;
+                        pid_at(k) = pj;
                         s_j[k * DTILE + t] = jj[m];
                         ++cnt;
                     }
@@ -437,7 +480,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
                 const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
                 if (dist < ri) {
                     if (cnt < KMAX) {
-                        s_pid[cnt * DTILE + t] = FACE + (uint32_t)f;
+                        pid_at((int)cnt) = FACE + (uint32_t)f;
                         s_j[cnt * DTILE + t] = FACE + (uint32_t)f;
                     }
                     ++cnt;

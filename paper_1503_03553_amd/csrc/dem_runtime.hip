@@ -687,10 +687,16 @@ dem_status prepare_job(const dem_params* params, const dem_material* mats, uint3
         G.hi[a] = params->hi[a];
         G.L[a] = params->hi[a] - params->lo[a];
         G.inv_cell[a] = 1.0 / lay.cell[a];
+        G.cw[a] = lay.cell[a];
         G.inv_L[a] = 1.0 / G.L[a];
         G.nc[a] = lay.nc[a];
         G.g[a] = params->gravity[a];
     }
+    // the cell of a coordinate is computed in floating point, so a partner
+    // may sit a few rounding units outside its cell's slab
+    double span = 0.0;
+    for (int a = 0; a < 3; ++a) span = std::max(span, std::fabs(G.lo[a]) + std::fabs(G.hi[a]));
+    G.reach = rmax + 1e-9 * span;
     G.walls = params->walls;
     G.periodic = params->periodic;
     G.le = params->shear_rate != 0.0;
