@@ -18,6 +18,11 @@ constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 constexpr uint32_t ERR_CAPACITY = 1u;     // contact table too small for this step
 constexpr uint32_t ERR_ROW = 2u;          // a particle has more contacts than the row buffer
 constexpr uint32_t ERR_NONFINITE = 4u;    // NaN / Inf in a force or the new state
+constexpr uint32_t ERR_MOVERS = 8u;       // more particles changed cell than the merge sort takes
+
+// Particles that may change cell in one step for the merge sort; beyond
+// this the step is redone with the radix sort.
+constexpr uint32_t MAX_MOVERS = 8192;
 
 // Per material-pair constants of the contact law (section 2), computed on the
 // host in FP64 and kept in device memory.
@@ -76,14 +81,18 @@ struct Status {
     uint32_t err;
     uint32_t need;          // largest tile contact count seen when a tile overflowed
     unsigned long long steps_done;
+    uint32_t movers;        // particles whose cell key changed in the current step
+    uint32_t pad;
 };
 
 // Running counters of one workgroup (one slot per tile, so no two
 // workgroups ever update the same word): contacts written, contacts that found
 // their history, contacts of the step before.
 struct TileStats {
-    unsigned long long m, matched, old;
-};
+    unsigned long long m, matched, old;      // sums over completed steps
+    uint32_t m_step, matched_step, old_step; // the step in progress (folded in by
+    uint32_t pad;                            // the reorder kernel, so a redone step
+};                                           // counts once)
 
 // Sorted particle state: position + (radius bits | pid << 32) in one 32-byte
 // record, velocity and angular velocity in three 16-byte planes
@@ -126,11 +135,20 @@ struct PoolView {
 float detect_margin(const Geo& G);
 void launch_detect(const PoolView& P, int kmax, const State& A, const uint2* cells, uint2* rows,
                    uint32_t* col_j, uint32_t slots, hipStream_t s);
+// With `movers` non-null the force kernel also writes the key of every
+// position before the step (`oldkeys`) and appends (new key, position) of
+// the particles whose key changed to `movers` (at most MAX_MOVERS).
 void launch_force(const PoolView& P, bool fp64, const State& A, const State& B, const uint2* rows,
                   const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
                   const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
                   double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
-                  void* fo, hipStream_t s);
+                  void* fo, uint32_t* oldkeys, uint2* movers, hipStream_t s);
+// Stable sort of the n = ntiles * TILE keys by merging the few particles
+// that changed cell into the unchanged ones, which are still in key order;
+// the result (keys_s, vals_s) equals the radix sort's.
+void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
+                       const uint2* movers, unsigned long long* mk, uint32_t* mp,
+                       uint32_t* keys_s, uint32_t* vals_s, hipStream_t s);
 // Sorts (keys, vals) by the low `bits` bits of keys; the result ends in
 // (keys_out, vals_out).  tmp buffers are the ping-pong partners.
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,

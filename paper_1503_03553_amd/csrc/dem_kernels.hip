@@ -429,6 +429,33 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
 #undef DEM_PRE_STEP
         }
         if (sc > KMAX) {
+            // more survivors than the row holds (a particle far from the box,
+            // whose FP32 record passes every comparison, or a tight clump):
+            // walk the candidates again with the exact FP64 test, so only
+            // more real contacts than the row holds are an error
+            sc = 0;
+            for (uint32_t w2 = 0; w2 < nw; ++w2) {
+                const uint2 rg2 = s_win[w2 * DTILE + t];
+                for (uint32_t jx = rg2.x; jx < rg2.y; ++jx) {
+                    if (jx == i || jx >= P.ns) continue;
+                    const double4 b = xr[jx];
+                    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                    if (PER) {
+                        double Sx, Sy, Sz;
+                        int ky;
+                        image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                        dx = dx + Sx;
+                        dy = dy + Sy;
+                        dz = dz + Sz;
+                    }
+                    if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
+                        s_j[min(sc, (uint32_t)KMAX) * DTILE + t] = jx;
+                        ++sc;
+                    }
+                }
+            }
+        }
+        if (sc > KMAX) {
             cnt = KMAX + 1;  // row buffer too small: reported below
         } else {
             // pass 2: exact FP64 test of the survivors, four loads in flight;
@@ -504,7 +531,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
             atomicMax(&st->need, total);
             base = 0xFFFFFFFFu;
         } else {
-            P.ts[tile].m += total;
+            P.ts[tile].m_step = total;
         }
         s_base = base;
     }
@@ -575,7 +602,8 @@ __global__ __launch_bounds__(TILE) void k_force(
     const uint32_t* __restrict__ tab_pid_old, const double* __restrict__ tab_dt_old,
     uint32_t* __restrict__ tab_pid_new, double* __restrict__ tab_dt_new, uint64_t cap,
     uint2* __restrict__ cells, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    R* __restrict__ fo, PoolView P, const Job* __restrict__ jobs) {
+    R* __restrict__ fo, PoolView P, const Job* __restrict__ jobs, uint32_t* __restrict__ oldkeys,
+    uint2* __restrict__ movers) {
     __shared__ double4 s_x[TILE];
     __shared__ double2 s_vw[3][TILE];
     __shared__ uint2 s_old[TILE];
@@ -597,6 +625,7 @@ __global__ __launch_bounds__(TILE) void k_force(
         // not running: keys that keep every position of the tile in place
         keys[p0 + t] = P.tile_key[tile] | P.lmask;
         vals[p0 + t] = p0 + t;
+        if (movers) oldkeys[p0 + t] = P.tile_key[tile] | P.lmask;
         return;
     }
     const Job& J = *Jp;
@@ -609,6 +638,7 @@ __global__ __launch_bounds__(TILE) void k_force(
         // ghost slot after the job's last particle: sorts last, stays in place
         keys[i] = P.tile_key[tile] | P.lmask;
         vals[i] = i;
+        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
     }
     const uint32_t nt = (n - p0) < (uint32_t)TILE ? (n - p0) : (uint32_t)TILE;
     uint2 row = make_uint2(0, 0);
@@ -772,74 +802,256 @@ __global__ __launch_bounds__(TILE) void k_force(
         }
         __syncthreads();
         if (t == 0) {
-            P.ts[tile].matched += s_red[0] + s_red[2];
-            P.ts[tile].old += s_red[1] + s_red[3];
+            P.ts[tile].matched_step = s_red[0] + s_red[2];
+            P.ts[tile].old_step = s_red[1] + s_red[3];
         }
     }
-    if (i >= n) return;
+    bool moved = false;
+    uint32_t newkey = 0;
+    if (i < n) {
+        // per-particle totals, gravity, semi-implicit Euler (FP64)
+        const double4 a = s_x[t];
+        const double2 a0 = s_vw[0][t], a1 = s_vw[1][t], a2 = s_vw[2][t];
+        const int mi = s_mat[t];
+        const double r = (double)meta_r(a.w);
+        const double m = mt->mass_pref[mi] * r * r * r;
+        const double I = 0.4 * m * r * r;
+        const double Fx = (double)acc[0] + m * G.g[0];
+        const double Fy = (double)acc[1] + m * G.g[1];
+        const double Fz = (double)acc[2] + m * G.g[2];
+        double vx = a0.x + G.dt * Fx / m;
+        double vy = a0.y + G.dt * Fy / m;
+        double vz = a1.x + G.dt * Fz / m;
+        double x = a.x + G.dt * vx;
+        double y = a.y + G.dt * vy;
+        double z = a.z + G.dt * vz;
+        const double wx = a1.y + G.dt * (double)acc[3] / I;
+        const double wy = a2.x + G.dt * (double)acc[4] / I;
+        const double wz = a2.y + G.dt * (double)acc[5] / I;
+        if (G.periodic & 2u) {
+            if (y >= G.hi[1]) {
+                y -= G.L[1];
+                x -= G.le_shift_next;
+                vx -= G.le_dv;
+            } else if (y < G.lo[1]) {
+                y += G.L[1];
+                x += G.le_shift_next;
+                vx += G.le_dv;
+            }
+        }
+        // bounded wraps: a non-finite coordinate stays non-finite and is flagged
+        if (G.periodic & 1u) {
+            for (int k = 0; k < 4 && x >= G.hi[0]; ++k) x -= G.L[0];
+            for (int k = 0; k < 4 && x < G.lo[0]; ++k) x += G.L[0];
+        }
+        if (G.periodic & 4u) {
+            for (int k = 0; k < 4 && z >= G.hi[2]; ++k) z -= G.L[2];
+            for (int k = 0; k < 4 && z < G.lo[2]; ++k) z += G.L[2];
+        }
+        const bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) &&
+                            isfinite(vy) && isfinite(vz) && isfinite(wx) && isfinite(wy) &&
+                            isfinite(wz);
+        if (!finite) atomicOr(&P.job_fail[jb], 1u);
+        xr_b[i] = make_double4(x, y, z, a.w);
+        vw_b[i] = make_double2(vx, vy);
+        vw_b[ns + i] = make_double2(vz, wx);
+        vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
+        if (mat_b) mat_b[i] = (uint8_t)mi;
+        newkey = P.tile_key[tile] | cell_key(G, x, y, z);
+        keys[i] = newkey;
+        vals[i] = i;
+        if (fo) {
+            fo[i] = (R)Fx;
+            fo[ns + i] = (R)Fy;
+            fo[2 * (size_t)ns + i] = (R)Fz;
+            fo[3 * (size_t)ns + i] = acc[3];
+            fo[4 * (size_t)ns + i] = acc[4];
+            fo[5 * (size_t)ns + i] = acc[5];
+        }
+        // the first particle of its (old) cell empties the cell's bounds; the
+        // reorder kernel writes the bounds of the new order
+        const uint32_t okey = cell_key(G, a.x, a.y, a.z);
+        const uint32_t lin = key_lin(G, okey);
+        if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
+        if (movers) {
+            const uint32_t oldkey = P.tile_key[tile] | okey;
+            oldkeys[i] = oldkey;
+            moved = newkey != oldkey;
+        }
+    }
+    if (movers) {
+        // the particles that changed cell join the step's mover list: one
+        // reservation per workgroup that has any
+        __shared__ uint32_t s_mv[2], s_mvbase;
+        const int lane = t & 63, w = t >> 6;
+        const unsigned long long bal = __ballot(moved);
+        if (lane == 0) s_mv[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        if (t == 0) {
+            const uint32_t tot = s_mv[0] + s_mv[1];
+            uint32_t b = 0;
+            if (tot) {
+                b = atomicAdd(&st->movers, tot);
+                if (b + tot > MAX_MOVERS) {
+                    atomicOr(&st->err, ERR_MOVERS);
+                    b = 0xFFFFFFFFu;
+                }
+            }
+            s_mvbase = b;
+        }
+        __syncthreads();
+        if (moved && s_mvbase != 0xFFFFFFFFu) {
+            const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            movers[s_mvbase + (w ? s_mv[0] : 0u) + rank] = make_uint2(newkey, i);
+        }
+    }
+}
 
-    // per-particle totals, gravity, semi-implicit Euler (FP64)
-    const double4 a = s_x[t];
-    const double2 a0 = s_vw[0][t], a1 = s_vw[1][t], a2 = s_vw[2][t];
-    const int mi = s_mat[t];
-    const double r = (double)meta_r(a.w);
-    const double m = mt->mass_pref[mi] * r * r * r;
-    const double I = 0.4 * m * r * r;
-    const double Fx = (double)acc[0] + m * G.g[0];
-    const double Fy = (double)acc[1] + m * G.g[1];
-    const double Fz = (double)acc[2] + m * G.g[2];
-    double vx = a0.x + G.dt * Fx / m;
-    double vy = a0.y + G.dt * Fy / m;
-    double vz = a1.x + G.dt * Fz / m;
-    double x = a.x + G.dt * vx;
-    double y = a.y + G.dt * vy;
-    double z = a.z + G.dt * vz;
-    const double wx = a1.y + G.dt * (double)acc[3] / I;
-    const double wy = a2.x + G.dt * (double)acc[4] / I;
-    const double wz = a2.y + G.dt * (double)acc[5] / I;
-    if (G.periodic & 2u) {
-        if (y >= G.hi[1]) {
-            y -= G.L[1];
-            x -= G.le_shift_next;
-            vx -= G.le_dv;
-        } else if (y < G.lo[1]) {
-            y += G.L[1];
-            x += G.le_shift_next;
-            vx += G.le_dv;
+// ------------------------------------------------------------ merge sort
+// Between two steps few particles change cell.  The others keep their key
+// and are still in key order, so the stable order of the step is the merge
+// of that sequence with the movers sorted by (new key, position), which is
+// exactly what the radix sort produces.  A position p before the step has
+// key oldkeys[p], and (oldkeys[p], p) increases with p.
+//
+// k_mov_sort: one workgroup sorts the movers by (key, position) and by
+// position (bitonic networks in LDS).
+__global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ movers,
+                                                   unsigned long long* __restrict__ mk,
+                                                   uint32_t* __restrict__ mp, const Status* st) {
+    __shared__ unsigned long long s[MAX_MOVERS];
+    __shared__ uint32_t s_flag;
+    if (skip_if_error(st, &s_flag)) return;
+    const uint32_t M = st->movers;
+    if (M == 0) return;
+    uint32_t n2 = 1;
+    while (n2 < M) n2 <<= 1;
+    const int t = threadIdx.x;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t q = t; q < n2; q += 1024) {
+            if (q < M) {
+                const uint2 e = movers[q];
+                s[q] = pass == 0 ? (((unsigned long long)e.x << 32) | e.y) : (unsigned long long)e.y;
+            } else {
+                s[q] = ~0ull;
+            }
         }
+        __syncthreads();
+        for (uint32_t k = 2; k <= n2; k <<= 1) {
+            for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+                for (uint32_t q = t; q < n2 / 2; q += 1024) {
+                    const uint32_t lo = 2 * q - (q & (jj - 1));
+                    const uint32_t hi = lo + jj;
+                    const bool up = (lo & k) == 0;
+                    const unsigned long long u = s[lo], v = s[hi];
+                    if ((u > v) == up) {
+                        s[lo] = v;
+                        s[hi] = u;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t q = t; q < M; q += 1024) {
+            if (pass == 0) mk[q] = s[q];
+            else mp[q] = (uint32_t)s[q];
+        }
+        __syncthreads();
     }
-    // bounded wraps: a non-finite coordinate stays non-finite and is flagged
-    if (G.periodic & 1u) {
-        for (int k = 0; k < 4 && x >= G.hi[0]; ++k) x -= G.L[0];
-        for (int k = 0; k < 4 && x < G.lo[0]; ++k) x += G.L[0];
+}
+
+// Number of entries of the sorted a[0, m) below v.
+template <typename T>
+__device__ inline uint32_t count_below(const T* __restrict__ a, uint32_t m, T v) {
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < v) lo = mid + 1;
+        else hi = mid;
     }
-    if (G.periodic & 4u) {
-        for (int k = 0; k < 4 && z >= G.hi[2]; ++k) z -= G.L[2];
-        for (int k = 0; k < 4 && z < G.lo[2]; ++k) z += G.L[2];
+    return lo;
+}
+
+// k_mov_dest: the place of each mover: the unchanged particles before it
+// (positions p with (oldkeys[p], p) below its (key, position), less the
+// movers among them) plus its rank among the movers.
+__global__ __launch_bounds__(256) void k_mov_dest(PoolView P, const uint32_t* __restrict__ oldkeys,
+                                                  const unsigned long long* __restrict__ mk,
+                                                  const uint32_t* __restrict__ mp,
+                                                  uint32_t* __restrict__ keys_s,
+                                                  uint32_t* __restrict__ vals_s) {
+    __shared__ uint32_t s_flag;
+    if (skip_if_error(P.st, &s_flag)) return;
+    const uint32_t M = P.st->movers;
+    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const unsigned long long e = mk[m];
+    const uint32_t K = (uint32_t)(e >> 32), pos = (uint32_t)e;
+    uint32_t lo = 0, hi = P.ntiles * TILE;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint32_t ok = oldkeys[mid];
+        if (ok < K || (ok == K && mid < pos)) lo = mid + 1;
+        else hi = mid;
     }
-    const bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) &&
-                        isfinite(vy) && isfinite(vz) && isfinite(wx) && isfinite(wy) &&
-                        isfinite(wz);
-    if (!finite) atomicOr(&P.job_fail[jb], 1u);
-    xr_b[i] = make_double4(x, y, z, a.w);
-    vw_b[i] = make_double2(vx, vy);
-    vw_b[ns + i] = make_double2(vz, wx);
-    vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
-    if (mat_b) mat_b[i] = (uint8_t)mi;
-    keys[i] = P.tile_key[tile] | cell_key(G, x, y, z);
-    vals[i] = i;
-    if (fo) {
-        fo[i] = (R)Fx;
-        fo[ns + i] = (R)Fy;
-        fo[2 * (size_t)ns + i] = (R)Fz;
-        fo[3 * (size_t)ns + i] = acc[3];
-        fo[4 * (size_t)ns + i] = acc[4];
-        fo[5 * (size_t)ns + i] = acc[5];
+    const uint32_t dest = lo - count_below(mp, M, lo) + m;
+    if (dest >= P.ntiles * TILE) {  // inconsistent input: redo the step with the radix sort
+        atomicOr(&P.st->err, ERR_MOVERS);
+        return;
     }
-    // the first particle of its (old) cell empties the cell's bounds; the
-    // reorder kernel writes the bounds of the new order
-    const uint32_t lin = key_lin(G, cell_key(G, a.x, a.y, a.z));
-    if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
+    keys_s[dest] = K;
+    vals_s[dest] = pos;
+}
+
+// k_place: every unchanged particle moves by the movers that leave before it
+// and the movers that arrive before it.  Per tile the two counts are found
+// once and are the same for the whole tile unless a mover leaves from or
+// arrives inside it.
+__global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __restrict__ keys,
+                                                const uint32_t* __restrict__ oldkeys,
+                                                const unsigned long long* __restrict__ mk,
+                                                const uint32_t* __restrict__ mp,
+                                                uint32_t* __restrict__ keys_s,
+                                                uint32_t* __restrict__ vals_s) {
+    __shared__ uint32_t s_c[4];
+    __shared__ uint32_t s_flag;
+    if (skip_if_error(P.st, &s_flag)) return;
+    const uint32_t M = P.st->movers;
+    const int t = threadIdx.x;
+    const uint32_t p0 = blockIdx.x * TILE, i = p0 + t;
+    const uint32_t ok = oldkeys[i];
+    const bool moved = keys[i] != ok;
+    auto key_of = [](uint32_t k, uint32_t p) { return ((unsigned long long)k << 32) | p; };
+    if (M == 0) {
+        keys_s[i] = ok;
+        vals_s[i] = i;
+        return;
+    }
+    if (t < 4) {
+        // movers leaving before the tile / before its end; movers arriving
+        // before the tile's first / after its last unchanged position
+        const uint32_t pe = p0 + TILE - 1;
+        uint32_t c;
+        if (t == 0) c = count_below(mp, M, p0);
+        else if (t == 1) c = count_below(mp, M, pe + 1);
+        else if (t == 2) c = count_below(mk, M, key_of(oldkeys[p0], p0));
+        else c = count_below(mk, M, key_of(oldkeys[pe], pe) + 1);
+        s_c[t] = c;
+    }
+    __syncthreads();
+    if (moved) return;
+    uint32_t leave = s_c[0], arrive = s_c[2];
+    if (s_c[1] != s_c[0] || s_c[3] != s_c[2]) {
+        leave = count_below(mp, M, i);
+        arrive = count_below(mk, M, key_of(ok, i));
+    }
+    const uint32_t dest = i - leave + arrive;
+    if (dest >= P.ntiles * TILE) {  // inconsistent input: redo the step with the radix sort
+        atomicOr(&P.st->err, ERR_MOVERS);
+        return;
+    }
+    keys_s[dest] = ok;
+    vals_s[dest] = i;
 }
 
 // ------------------------------------------------------------- radix sort
@@ -988,6 +1200,13 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     if (!Jp) return;
     const Job& J = *Jp;
     const Geo& G = J.g;
+    if (threadIdx.x == 0) {
+        // the step completed: its counters join the sums
+        TileStats& q = P.ts[tile];
+        q.m += q.m_step;
+        q.matched += q.matched_step;
+        q.old += q.old_step;
+    }
     const uint32_t i = tile * TILE + threadIdx.x;
     const uint32_t end = J.p0 + J.n;
     if (i >= end) return;
@@ -1012,7 +1231,10 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
 __global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
     if (__atomic_load_n(&P.st->err, __ATOMIC_RELAXED)) return;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) P.st->steps_done += 1;
+    if (k == 0) {
+        P.st->steps_done += 1;
+        P.st->movers = 0;
+    }
     if (k >= njobs) return;
     Job& J = jobs[k];
     if (J.status != JOB_ACTIVE) return;
@@ -1064,17 +1286,30 @@ void launch_force(const PoolView& P, bool fp64, const State& A, const State& B, 
                   const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
                   const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
                   double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
-                  void* fo, hipStream_t s) {
+                  void* fo, uint32_t* oldkeys, uint2* movers, hipStream_t s) {
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
     if (fp64)
         hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, A.xr, A.vw, A.mat, B.xr,
                            B.vw, B.mat, rows, col_j, rows_old, prev, tab_pid_old, tab_dt_old,
-                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, P, P.jobs);
+                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, P, P.jobs,
+                           oldkeys, movers);
     else
         hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, A.xr, A.vw, A.mat, B.xr,
                            B.vw, B.mat, rows, col_j, rows_old, prev, tab_pid_old, tab_dt_old,
-                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs);
+                           tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs,
+                           oldkeys, movers);
+}
+
+void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
+                       const uint2* movers, unsigned long long* mk, uint32_t* mp,
+                       uint32_t* keys_s, uint32_t* vals_s, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    hipLaunchKernelGGL(k_mov_sort, dim3(1), dim3(1024), 0, s, movers, mk, mp, P.st);
+    hipLaunchKernelGGL(k_mov_dest, dim3(MAX_MOVERS / 256), dim3(256), 0, s, P, oldkeys, mk, mp,
+                       keys_s, vals_s);
+    hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, keys, oldkeys, mk, mp, keys_s,
+                       vals_s);
 }
 
 size_t sort_hist_words(uint32_t n) {

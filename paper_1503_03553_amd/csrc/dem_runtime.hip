@@ -129,6 +129,11 @@ struct dem_pool {
     uint32_t *keys = nullptr, *vals = nullptr, *keys_t = nullptr, *vals_t = nullptr;
     uint32_t* tile_hist = nullptr;
     uint32_t* digit_tot = nullptr;
+    uint32_t* oldkeys = nullptr;          // merge sort: keys before the step
+    uint2* movers = nullptr;              //   (new key, position) of cell changers
+    unsigned long long* mk = nullptr;     //   movers by (key, position)
+    uint32_t* mp = nullptr;               //   movers by position
+    uint32_t radix_left = 0;              // steps to take with the radix sort
     void* fo = nullptr;
     MatTable* mats = nullptr;
     Job* jobs_d = nullptr;
@@ -319,7 +324,8 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     b += np * (32 + 48 + 1 + 16);      // sorted state and its FP32 record
     b += np * (32 + 48 + 1);           // integrated state
     b += np * 2 * 8;                   // contact rows, two steps
-    b += np * 5 * 4;                   // prev, keys and values (two buffers)
+    b += np * 6 * 4;                   // prev, keys and values (two buffers), keys before
+    b += (uint64_t)MAX_MOVERS * 20;    // mover lists
     b += np * 6 * (fp64 ? 8 : 4);      // per-particle F, T
     b += max_cells * 8;                // cell bounds
     b += np * slots * (4 + 2 * 28);    // partner list and two history tables
@@ -393,6 +399,10 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->vals_t));
     ALLOC_OR_FAIL(dalloc_t(s, sort_hist_words((uint32_t)np), &s->tile_hist));
     ALLOC_OR_FAIL(dalloc_t(s, 256, &s->digit_tot));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->oldkeys));
+    ALLOC_OR_FAIL(dalloc_t(s, MAX_MOVERS, &s->movers));
+    ALLOC_OR_FAIL(dalloc_t(s, MAX_MOVERS, &s->mk));
+    ALLOC_OR_FAIL(dalloc_t(s, MAX_MOVERS, &s->mp));
     ALLOC_OR_FAIL(dalloc(s, 6 * np * (fp64 ? 8 : 4), &s->fo));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->mats));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->jobs_d));
@@ -815,15 +825,26 @@ dem_status enqueue_step(dem_pool* s, int o) {
     launch_detect(P, s->kmax, A, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
     prof_record(s, slot, 1);
     prof_record(s, slot, 2);
+    // the merge sort unless a recent step had too many cell changes
+    const bool merge = s->radix_left == 0;
+    if (s->radix_left) s->radix_left--;
     launch_force(P, s->fp64, A, B, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
                  s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals,
-                 (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo, s->stream);
+                 (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo,
+                 merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr, s->stream);
     prof_record(s, slot, 3);
     prof_record(s, slot, 4);
     uint32_t *ko, *vo;
-    launch_radix_sort(s->keys, s->vals, s->keys_t, s->vals_t, s->hw_tiles * TILE,
-                      s->lb + seg_bits(s->segs.size()), s->tile_hist, s->digit_tot, &ko, &vo, s->st,
-                      s->stream);
+    if (merge) {
+        launch_merge_sort(P, s->keys, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, s->vals_t,
+                          s->stream);
+        ko = s->keys_t;
+        vo = s->vals_t;
+    } else {
+        launch_radix_sort(s->keys, s->vals, s->keys_t, s->vals_t, s->hw_tiles * TILE,
+                          s->lb + seg_bits(s->segs.size()), s->tile_hist, s->digit_tot, &ko, &vo,
+                          s->st, s->stream);
+    }
     prof_record(s, slot, 5);
     prof_record(s, slot, 6);
     launch_reorder(P, ko, vo, B, A, s->prev, s->cells, s->stream);
@@ -909,6 +930,7 @@ dem_status sync_impl(dem_pool* s) {
             }
             s->kmax = s->kmax <= 8 ? 16 : 32;
         }
+        if (h.err & ERR_MOVERS) s->radix_left = 16 + (uint32_t)s->pending.size();
         if (h.err & ERR_CAPACITY) {
             r = regrow(s, h.need, o);
             if (r != DEM_OK) {
@@ -919,6 +941,7 @@ dem_status sync_impl(dem_pool* s) {
         Status z = h;
         z.err = 0;
         z.need = 0;
+        z.movers = 0;
         HIPCHK(hipMemcpy(s->st, &z, sizeof(Status), hipMemcpyHostToDevice));
         s->prof_used = 0;
         const size_t k = s->pending.size();

@@ -265,3 +265,33 @@ def test_invalid_arguments_rejected():
     with pytest.raises(DemError):  # fewer than 3 cells along a periodic axis
         Sim(lo=[0, 0, 0], hi=[1e-4] * 3, x=x, v=z, w=z, r=[2e-5] * 4, materials=[m], periodic=7,
             walls=0)
+
+
+def drifting_scene(n, seed):
+    # a dilute periodic cloud translating as a whole: about one cell per
+    # step, so most particles change cell every step, and no new contacts
+    sc = gen.scene_random(seed=seed, n=n, phi=0.02, p_touch=0.0, walls=0, periodic=7,
+                          gravity=(0, 0, 0), vel_sigma=1e-3)
+    sc.v += np.array([12.0, 7.0, 5.0])
+    return sc
+
+
+@pytest.mark.parametrize("n", [6000, 20000])
+def test_many_cell_changes_per_step(n):
+    # n = 6000: thousands of particles change cell per step and are merged
+    # into the unchanged ones; n = 20000: more than the merge takes, so the
+    # steps are redone with the radix sort
+    say("case many cell changes", n)
+    sc = drifting_scene(n, seed=31)
+    rep = trajectory_parity(sc, PREC_MIXED, steps=6, tol=1e-4, dt=1e-6)
+    say("  ", rep)
+
+
+def test_particle_far_outside_the_box():
+    # a particle far outside the box (its FP32 search record is not usable)
+    # passes every pre-filter comparison; the exact re-walk keeps its row
+    say("case far outside")
+    sc = gen.scene_random(seed=32, n=3000, phi=0.2, p_touch=0.7, vel_sigma=0.2)
+    L = sc.hi - sc.lo
+    sc.x[5] = sc.lo + np.array([0.5, 0.5, 5.0]) * L
+    step_parity(sc, PREC_FP64, tol=1e-9)
