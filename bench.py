@@ -168,18 +168,24 @@ def run_batched(scenes, steps, warmup, stream, tune_steps, log):
 
 # --------------------------------------------------------------- serving
 def run_serving(templates, arr, tmpl, steps, stream, budget_particles, superstep, log):
+    """Serve the requests at their arrival times; the same requests all
+    arriving at once give the throughput of a pool that is never idle."""
     from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, PREC_MIXED, Pool
     from paper_1503_03553_amd.serve import Request, Server
     max_jobs = 256
-    pool = Pool(max_particles=budget_particles, max_cells=4 * budget_particles + 4096 * 64,
-                max_jobs=max_jobs, precision=PREC_MIXED, stream=stream, flags=FLAG_NO_FORCE_OUTPUT)
-    reqs = [Request(q, templates[int(tmpl[q])], int(steps[q]), float(arr[q]))
-            for q in range(len(arr))]
-    srv = Server(pool, superstep=superstep)
-    st = srv.run(reqs, deadline=600.0)
-    pool.close()
-    log("serving: %s" % json.dumps(st))
-    return st
+    out = []
+    for at_once in (False, True):
+        pool = Pool(max_particles=budget_particles, max_cells=4 * budget_particles + 4096 * 64,
+                    max_jobs=max_jobs, precision=PREC_MIXED, stream=stream,
+                    flags=FLAG_NO_FORCE_OUTPUT)
+        reqs = [Request(q, templates[int(tmpl[q])], int(steps[q]), 0.0 if at_once else float(arr[q]))
+                for q in range(len(arr))]
+        srv = Server(pool, superstep=superstep)
+        st = srv.run(reqs, deadline=600.0)
+        pool.close()
+        log("serving%s: %s" % (" (all at once)" if at_once else "", json.dumps(st)))
+        out.append(st)
+    return out
 
 
 # ----------------------------------------------------------- cpu oracle
@@ -350,7 +356,8 @@ def run_others(a, out, sc, batch, serve_in, stream, log):
 
     if serve_in is not None:
         templates, arr, tmpl, steps = serve_in
-        st = run_serving(templates, arr, tmpl, steps, stream, a.serve_budget, a.superstep, log)
+        st, sat = run_serving(templates, arr, tmpl, steps, stream, a.serve_budget, a.superstep,
+                              log)
         out["serving"] = {"rate_jobs_per_s": a.serve_rate, "horizon_s": a.serve_horizon,
                           "requests": int(len(arr)), "budget_particles": a.serve_budget,
                           "superstep": a.superstep,
@@ -360,7 +367,11 @@ def run_others(a, out, sc, batch, serve_in, stream, log):
                           "wait_p99_s": round(st["wait_p99_s"], 4),
                           "value": round(st["particle_steps_per_s"], 1),
                           "unit": "particle-steps/s", "makespan_s": round(st["makespan_s"], 3),
-                          "failed": st["failed"]}
+                          "failed": st["failed"],
+                          "all_at_once": {"value": round(sat["particle_steps_per_s"], 1),
+                                          "makespan_s": round(sat["makespan_s"], 3),
+                                          "p50_latency_s": round(sat["p50_s"], 4),
+                                          "p99_latency_s": round(sat["p99_s"], 4)}}
 
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, a.cpu_budget)

@@ -197,6 +197,56 @@ def config_batch_job(k, m, n=None):
                    meta=dict(phi=phi))
 
 
+def rsa_tiled(r, lo, hi, splits=(4, 4, 4), p_touch=0.0, touch_max=2e-3, seed=0, threads=16,
+              big_first=True):
+    """RSA in a grid of sub-boxes filled in parallel threads (the C helper
+    releases the interpreter lock).  Particle k goes to sub-box k mod the
+    number of sub-boxes and lies wholly inside it, so spheres of different
+    sub-boxes never overlap, nor do periodic images of the whole box."""
+    import concurrent.futures as cf
+    r = np.asarray(r, np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    nx, ny, nz = splits
+    nsub = nx * ny * nz
+    h = (hi - lo) / np.array(splits, np.float64)
+    x = np.empty((r.size, 3))
+    build_helper()
+
+    def fill(s):
+        ix, iy, iz = s % nx, (s // nx) % ny, s // (nx * ny)
+        sl = lo + h * np.array([ix, iy, iz])
+        idx = np.arange(s, r.size, nsub)
+        if idx.size:
+            x[idx] = rsa(r[idx], sl, sl + h, periodic=0, p_touch=p_touch, touch_max=touch_max,
+                         seed=seed + 7919 * s, big_first=big_first)
+
+    with cf.ThreadPoolExecutor(max(1, min(threads, os.cpu_count() or 1))) as ex:
+        list(ex.map(fill, range(nsub)))
+    return x
+
+
+def config_dense_shear(seed=None, n=8_000_000, phi=0.4, shear_rate=100.0, p_touch=0.9,
+                       splits=(4, 4, 4)):
+    """Dense periodic pack under Lees-Edwards simple shear: N polydisperse
+    spheres (the radius law of the dilute workload), shear rate 100/s along x
+    with velocity gradient along y, no gravity, 100 steps.  RSA jams before
+    the dense limit, so the volume fraction is 0.4 (largest spheres first,
+    most spheres placed touching an earlier one)."""
+    seed = SEED_BASE + 3 if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = lognormal_radii(rng, n)
+    L = box_side(r, phi)
+    lo, hi = np.zeros(3), np.full(3, L)
+    x = rsa_tiled(r, lo, hi, splits=splits, p_touch=p_touch, seed=seed)
+    mats = [Material.make(restitution=0.5, mu=0.3)]
+    sc = _finish(rng, x, r, lo, hi, mats, vel_sigma=0.01, walls=0, periodic=7,
+                 gravity=(0.0, 0.0, 0.0), shear_rate=shear_rate, steps=100,
+                 name="dense-shear-%d" % n, meta=dict(phi=phi))
+    sc.v[:, 0] += shear_rate * (x[:, 1] - lo[1])
+    return sc
+
+
 def batch_sizes(k, jobs, lo=1e3, hi=2e5):
     """Particle counts of a batched workload: log-uniform in [lo, hi]."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7000 + k))

@@ -124,20 +124,26 @@ class Server:
         self._t0 = self.clock()
         while pending or self.queue or self.running:
             now = self.now()
+            if deadline is not None and now > deadline:
+                raise TimeoutError("serving run exceeded %.1f s" % deadline)
             while pending and pending[0].arrival <= now:
                 self.queue.append(pending.popleft())
-            self.admit()
             if self.running:
+                # the superstep is enqueued first: the host work of admitting
+                # new requests overlaps it on the device
                 self.pool.step(self.superstep)
                 self.supersteps += 1
+                self.admit()
                 self._retire()
-            elif pending:
+                continue
+            self.admit()
+            if self.running:
+                continue
+            if pending:
                 # idle until the next arrival
                 self.sleep(max(0.0, pending[0].arrival - self.now()))
             elif self.queue:
                 raise RuntimeError("request %d can never fit in the pool" % self.queue[0].rid)
-            if deadline is not None and self.now() > deadline:
-                raise TimeoutError("serving run exceeded %.1f s" % deadline)
         return self.stats()
 
     def stats(self) -> dict:

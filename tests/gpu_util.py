@@ -57,6 +57,76 @@ def natural_force_scale(o, scene):
     return sF, sT
 
 
+def contact_overlaps(scene, x, i, j, time):
+    """Overlap of each contact (i, j) at positions x: the natural length of
+    its tangential displacement (the tangential spring force over the normal
+    force scales as their ratio).  Minimum image on periodic axes, with the
+    shear offset across y."""
+    i = np.asarray(i, np.int64)
+    j = np.asarray(j, np.int64)
+    r = np.asarray(scene.r, np.float64)
+    out = np.zeros(i.size)
+    face = j >= FACE
+    pi = i[~face]
+    pj = j[~face]
+    d = x[pj] - x[pi]
+    L = np.asarray(scene.hi, float) - np.asarray(scene.lo, float)
+    per = int(scene.periodic)
+    if per & 2:
+        ky = -np.rint(d[:, 1] / L[1])
+        d[:, 1] += ky * L[1]
+        if scene.shear_rate:
+            shift = np.fmod(scene.shear_rate * L[1] * time, L[0])
+            d[:, 0] += ky * shift
+    if per & 1:
+        d[:, 0] -= L[0] * np.rint(d[:, 0] / L[0])
+    if per & 4:
+        d[:, 2] -= L[2] * np.rint(d[:, 2] / L[2])
+    out[~face] = r[pi] + r[pj] - np.linalg.norm(d, axis=1)
+    f = (j[face] - FACE).astype(np.int64)
+    fi = i[face]
+    ax = f // 2
+    p = x[fi, ax]
+    lo = np.asarray(scene.lo, float)[ax]
+    hi = np.asarray(scene.hi, float)[ax]
+    out[face] = r[fi] - np.where(f % 2 == 1, hi - p, p - lo)
+    return out
+
+
+def check_step(o, scene, st, ci, cj, cdt, tol, allow_cap_flips=0.0, x0=None, time=0.0):
+    """Compare one GPU step (new state `st` with F, T; contacts ci, cj, cdt)
+    with the oracle `o` that took the same step with keep_contact_forces.
+    Tangential displacements are compared against the larger of their own
+    magnitude and the contact's overlap at the start of the step (positions
+    x0, default the scene's)."""
+    compare_contacts(ci, cj, o.hist.i, o.hist.j)
+    # tangential displacement per contact
+    ref = o.hist.dt
+    err = np.linalg.norm(cdt - ref, axis=1)
+    scale = np.linalg.norm(ref, axis=1)
+    dn = contact_overlaps(scene, scene.x if x0 is None else x0, o.hist.i, o.hist.j, time)
+    floor = np.maximum(dn, 1e-9 * (scale.max() if scale.size else 0.0)) + 1e-300
+    bad = err > tol * np.maximum(scale, floor)
+    nbad = int(bad.sum())
+    if nbad:
+        assert nbad <= allow_cap_flips * len(ref), \
+            "%d of %d tangential displacements off (max rel %.3g)" % (
+                nbad, len(ref), float((err / np.maximum(scale, floor)).max()))
+    # per-particle force and torque
+    sF, sT = natural_force_scale(o, scene)
+    eF = np.linalg.norm(st["F"] - o.F, axis=1)
+    eT = np.linalg.norm(st["T"] - o.T, axis=1)
+    okF = eF <= tol * sF + 1e-300
+    okT = eT <= tol * np.maximum(sT, 1e-300) + 1e-300
+    if allow_cap_flips == 0.0:
+        assert okF.all(), "force off: max rel %.3g" % float((eF / np.maximum(sF, 1e-300)).max())
+        assert okT.all(), "torque off: max rel %.3g" % float((eT / np.maximum(sT, 1e-300)).max())
+    else:
+        assert (~okF).sum() <= allow_cap_flips * scene.n + 1
+        assert (~okT).sum() <= allow_cap_flips * scene.n + 1
+    return dict(contacts=len(ref), bad_dt=nbad)
+
+
 def step_parity(scene, precision, history=None, tol=1e-5, dt=None, allow_cap_flips=0.0, **kw):
     """One step from identical state and history; compares contact set,
     tangential displacements, per-particle F and T and the new state."""
@@ -72,31 +142,9 @@ def step_parity(scene, precision, history=None, tol=1e-5, dt=None, allow_cap_fli
         st = g.get_state()
         ci, cj, cdt = g.get_contacts()
         o.step(keep_contact_forces=True)
-        compare_contacts(ci, cj, o.hist.i, o.hist.j)
-        # tangential displacement per contact
-        ref = o.hist.dt
-        err = np.linalg.norm(cdt - ref, axis=1)
-        scale = np.linalg.norm(ref, axis=1)
-        floor = 1e-9 * (scale.max() if scale.size else 0.0) + 1e-300
-        bad = err > tol * np.maximum(scale, floor)
-        nbad = int(bad.sum())
-        if nbad:
-            assert nbad <= allow_cap_flips * len(ref), \
-                "%d of %d tangential displacements off (max rel %.3g)" % (
-                    nbad, len(ref), float((err / np.maximum(scale, floor)).max()))
-        # per-particle force and torque
-        sF, sT = natural_force_scale(o, scene)
-        eF = np.linalg.norm(st["F"] - o.F, axis=1)
-        eT = np.linalg.norm(st["T"] - o.T, axis=1)
-        okF = eF <= tol * sF + 1e-300
-        okT = eT <= tol * np.maximum(sT, 1e-300) + 1e-300
-        if allow_cap_flips == 0.0:
-            assert okF.all(), "force off: max rel %.3g" % float((eF / np.maximum(sF, 1e-300)).max())
-            assert okT.all(), "torque off: max rel %.3g" % float((eT / np.maximum(sT, 1e-300)).max())
-        else:
-            assert (~okF).sum() <= allow_cap_flips * scene.n + 1
-            assert (~okT).sum() <= allow_cap_flips * scene.n + 1
-        return g, o, st, dict(contacts=len(ref), bad_dt=nbad)
+        rep = check_step(o, scene, st, ci, cj, cdt, tol, allow_cap_flips, x0=scene.x,
+                         time=0.0)
+        return g, o, st, rep
     finally:
         g.close()
 
