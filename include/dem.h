@@ -94,6 +94,9 @@ typedef struct {
 } dem_params;
 
 #define DEM_FLAG_NO_FORCE_OUTPUT 1u /* do not store per-particle F, T each step */
+#define DEM_FLAG_RADIX_SORT 2u      /* sort all keys every step (LSD radix sort) instead of
+                                       merging the particles that changed cell; same
+                                       results, for comparison */
 
 /* Diagnostics of a simulation (dem_get_info). */
 typedef struct {

@@ -826,7 +826,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
     prof_record(s, slot, 1);
     prof_record(s, slot, 2);
     // the merge sort unless a recent step had too many cell changes
-    const bool merge = s->radix_left == 0;
+    const bool merge = s->radix_left == 0 && !(s->flags & DEM_FLAG_RADIX_SORT);
     if (s->radix_left) s->radix_left--;
     launch_force(P, s->fp64, A, B, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
                  s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals,

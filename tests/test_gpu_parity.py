@@ -295,3 +295,24 @@ def test_particle_far_outside_the_box():
     L = sc.hi - sc.lo
     sc.x[5] = sc.lo + np.array([0.5, 0.5, 5.0]) * L
     step_parity(sc, PREC_FP64, tol=1e-9)
+
+
+@pytest.mark.parametrize("name", ["random3000", "shear1500"])
+def test_merge_sort_equals_radix_sort(name):
+    # the order of every step, hence every result, is the same whether the
+    # particles that changed cell are merged or all keys are radix sorted
+    say("case merge vs radix", name)
+    from paper_1503_03553_amd import FLAG_RADIX_SORT
+    sc = SCENES[name]()
+    sc.v *= 50.0  # many cell changes per step
+    o = oracle.Sim(sc, mode=1)
+    runs = []
+    for flags in (0, FLAG_RADIX_SORT):
+        g = Sim.from_scene(sc, precision=PREC_MIXED, dt=o.dt, flags=flags)
+        g.step(40)
+        runs.append((g.get_state(), g.get_contacts()))
+        g.close()
+    for k in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(runs[0][0][k], runs[1][0][k]), k
+    for u, v in zip(runs[0][1], runs[1][1]):
+        assert np.array_equal(u, v)
