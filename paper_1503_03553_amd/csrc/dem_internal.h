@@ -154,9 +154,11 @@ void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* 
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                        uint32_t n, int bits, uint32_t* tile_hist, uint32_t* digit_tot,
                        uint32_t** keys_out, uint32_t** vals_out, const Status* st, hipStream_t s);
-void launch_reorder(const PoolView& P, const uint32_t* keys_s, const uint32_t* vals_s,
-                    const State& B, const State& A, uint32_t* prev, uint2* cells, hipStream_t s);
-void launch_tick(const PoolView& P, Job* jobs, uint32_t njobs, hipStream_t s);
+// Gathers the state into the sorted order and writes cell bounds, then ends
+// the step for the `njobs` job descriptors (time, steps, status).
+void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
+                    const uint32_t* vals_s, const State& B, const State& A, uint32_t* prev,
+                    uint2* cells, hipStream_t s);
 // Shear offset of the image along x at time t: D(t) = (shear_rate L_y t) mod L_x.
 double le_offset(const Geo& G, double t);
 size_t sort_hist_words(uint32_t n);

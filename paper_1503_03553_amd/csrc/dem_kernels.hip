@@ -915,7 +915,7 @@ __global__ __launch_bounds__(TILE) void k_force(
 // key oldkeys[p], and (oldkeys[p], p) increases with p.
 //
 // k_mov_sort: one workgroup sorts the movers by (key, position) and by
-// position (bitonic networks in LDS).
+// position (bitonic networks in LDS); k_place then places every particle.
 __global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ movers,
                                                    unsigned long long* __restrict__ mk,
                                                    uint32_t* __restrict__ mp, const Status* st) {
@@ -972,52 +972,39 @@ __device__ inline uint32_t count_below(const T* __restrict__ a, uint32_t m, T v)
     return lo;
 }
 
-// k_mov_dest: the place of each mover: the unchanged particles before it
-// (positions p with (oldkeys[p], p) below its (key, position), less the
-// movers among them) plus its rank among the movers.
-__global__ __launch_bounds__(256) void k_mov_dest(PoolView P, const uint32_t* __restrict__ oldkeys,
-                                                  const unsigned long long* __restrict__ mk,
-                                                  const uint32_t* __restrict__ mp,
-                                                  uint32_t* __restrict__ keys_s,
-                                                  uint32_t* __restrict__ vals_s) {
-    __shared__ uint32_t s_flag;
-    if (skip_if_error(P.st, &s_flag)) return;
-    const uint32_t M = P.st->movers;
-    const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const unsigned long long e = mk[m];
-    const uint32_t K = (uint32_t)(e >> 32), pos = (uint32_t)e;
-    uint32_t lo = 0, hi = P.ntiles * TILE;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const uint32_t ok = oldkeys[mid];
-        if (ok < K || (ok == K && mid < pos)) lo = mid + 1;
-        else hi = mid;
-    }
-    const uint32_t dest = lo - count_below(mp, M, lo) + m;
-    if (dest >= P.ntiles * TILE) {  // inconsistent input: redo the step with the radix sort
-        atomicOr(&P.st->err, ERR_MOVERS);
-        return;
-    }
-    keys_s[dest] = K;
-    vals_s[dest] = pos;
+// k_place: one workgroup per tile of positions.  Every unchanged particle
+// moves by the movers that leave before it and the movers that arrive before
+// it; both counts are found once per tile and are the same for the whole
+// tile unless a mover leaves from or arrives inside it.  The movers whose
+// (key, position) falls between this tile's first old (key, position) and
+// the next tile's are placed by this tile (the first tile also takes those
+// that sort before every position): the unchanged particles before a
+// mover are the positions before it in old order (all positions before the
+// tile, and those of the tile found by binary search) less the movers among
+// them.  Mover lists of up to LDS_MOVERS entries are searched in LDS.
+constexpr uint32_t LDS_MOVERS = 512;
+
+template <typename K>
+__device__ inline uint32_t count_below_in(const K* lds, const K* glob, bool in_lds, uint32_t m,
+                                          K v) {
+    return in_lds ? count_below(lds, m, v) : count_below(glob, m, v);
 }
 
-// k_place: every unchanged particle moves by the movers that leave before it
-// and the movers that arrive before it.  Per tile the two counts are found
-// once and are the same for the whole tile unless a mover leaves from or
-// arrives inside it.
 __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __restrict__ keys,
                                                 const uint32_t* __restrict__ oldkeys,
                                                 const unsigned long long* __restrict__ mk,
                                                 const uint32_t* __restrict__ mp,
                                                 uint32_t* __restrict__ keys_s,
                                                 uint32_t* __restrict__ vals_s) {
+    __shared__ unsigned long long s_mk[LDS_MOVERS];
+    __shared__ uint32_t s_mp[LDS_MOVERS];
+    __shared__ unsigned long long s_ok[TILE];
     __shared__ uint32_t s_c[4];
     __shared__ uint32_t s_flag;
     if (skip_if_error(P.st, &s_flag)) return;
     const uint32_t M = P.st->movers;
     const int t = threadIdx.x;
+    const uint32_t N = P.ntiles * TILE;
     const uint32_t p0 = blockIdx.x * TILE, i = p0 + t;
     const uint32_t ok = oldkeys[i];
     const bool moved = keys[i] != ok;
@@ -1027,31 +1014,53 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __re
         vals_s[i] = i;
         return;
     }
+    const bool in_lds = M <= LDS_MOVERS;
+    if (in_lds) {
+        for (uint32_t q = t; q < M; q += TILE) {
+            s_mk[q] = mk[q];
+            s_mp[q] = mp[q];
+        }
+    }
+    s_ok[t] = key_of(ok, i);
+    __syncthreads();
     if (t < 4) {
-        // movers leaving before the tile / before its end; movers arriving
-        // before the tile's first / after its last unchanged position
-        const uint32_t pe = p0 + TILE - 1;
+        // movers leaving before the tile / before the next tile; movers whose
+        // place is before the tile's first / the next tile's first position
         uint32_t c;
-        if (t == 0) c = count_below(mp, M, p0);
-        else if (t == 1) c = count_below(mp, M, pe + 1);
-        else if (t == 2) c = count_below(mk, M, key_of(oldkeys[p0], p0));
-        else c = count_below(mk, M, key_of(oldkeys[pe], pe) + 1);
+        if (t == 0) c = count_below_in(s_mp, mp, in_lds, M, p0);
+        else if (t == 1) c = count_below_in(s_mp, mp, in_lds, M, p0 + TILE);
+        else if (t == 2) c = count_below_in(s_mk, mk, in_lds, M, s_ok[0]);
+        else c = p0 + TILE < N ? count_below_in(s_mk, mk, in_lds, M,
+                                                key_of(oldkeys[p0 + TILE], p0 + TILE))
+                               : M;
         s_c[t] = c;
     }
     __syncthreads();
-    if (moved) return;
-    uint32_t leave = s_c[0], arrive = s_c[2];
-    if (s_c[1] != s_c[0] || s_c[3] != s_c[2]) {
-        leave = count_below(mp, M, i);
-        arrive = count_below(mk, M, key_of(ok, i));
+    if (!moved) {
+        uint32_t leave = s_c[0], arrive = s_c[2];
+        if (s_c[1] != s_c[0]) leave = count_below_in(s_mp, mp, in_lds, M, i);
+        if (s_c[3] != s_c[2]) arrive = count_below_in(s_mk, mk, in_lds, M, key_of(ok, i));
+        const uint32_t dest = i - leave + arrive;
+        if (dest >= N) {  // inconsistent input: redo the step with the radix sort
+            atomicOr(&P.st->err, ERR_MOVERS);
+        } else {
+            keys_s[dest] = ok;
+            vals_s[dest] = i;
+        }
     }
-    const uint32_t dest = i - leave + arrive;
-    if (dest >= P.ntiles * TILE) {  // inconsistent input: redo the step with the radix sort
-        atomicOr(&P.st->err, ERR_MOVERS);
-        return;
+    // the first tile also places the movers that sort before every position
+    const uint32_t mlo = blockIdx.x == 0 ? 0u : s_c[2];
+    for (uint32_t m = mlo + t; m < s_c[3]; m += TILE) {
+        const unsigned long long e = in_lds ? s_mk[m] : mk[m];
+        const uint32_t lb = p0 + count_below(s_ok, (uint32_t)TILE, e);
+        const uint32_t dest = lb - count_below_in(s_mp, mp, in_lds, M, lb) + m;
+        if (dest >= N) {
+            atomicOr(&P.st->err, ERR_MOVERS);
+        } else {
+            keys_s[dest] = (uint32_t)(e >> 32);
+            vals_s[dest] = (uint32_t)e;
+        }
     }
-    keys_s[dest] = ok;
-    vals_s[dest] = i;
 }
 
 // ------------------------------------------------------------- radix sort
@@ -1179,6 +1188,25 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 }
 
 // ------------------------------------------------------------------ reorder
+// End of a step for one job: time, step count and shear offsets advance; a
+// job that produced a non-finite state is marked failed.
+__device__ inline void tick_job(const PoolView& P, Job* jobs, uint32_t k) {
+    Job& J = jobs[k];
+    if (J.status != JOB_ACTIVE) return;
+    if (P.job_fail[k]) {
+        J.status = JOB_FAILED;
+        return;
+    }
+    const double t = J.t + J.g.dt;
+    J.t = t;
+    if (J.g.le) {
+        J.g.le_shift = fmod(J.g.le_dv * t, J.g.L[0]);
+        J.g.le_shift_next = fmod(J.g.le_dv * (t + J.g.dt), J.g.L[0]);
+    }
+    J.steps_done += 1;
+    if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
+}
+
 // One workgroup per tile.  Positions of free tiles, of jobs that are not
 // running and ghost slots kept their place in the sort and are left alone.
 __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restrict__ jobs,
@@ -1197,37 +1225,40 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     const uint32_t tile = blockIdx.x;
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
-    if (!Jp) return;
-    const Job& J = *Jp;
-    const Geo& G = J.g;
-    if (threadIdx.x == 0) {
-        // the step completed: its counters join the sums
-        TileStats& q = P.ts[tile];
-        q.m += q.m_step;
-        q.matched += q.matched_step;
-        q.old += q.old_step;
+    if (Jp) {
+        const Job& J = *Jp;
+        const Geo& G = J.g;
+        if (threadIdx.x == 0) {
+            // the step completed: its counters join the sums
+            TileStats& q = P.ts[tile];
+            q.m += q.m_step;
+            q.matched += q.matched_step;
+            q.old += q.old_step;
+        }
+        const uint32_t i = tile * TILE + threadIdx.x;
+        const uint32_t end = J.p0 + J.n;
+        if (i < end) {
+            const uint32_t ns = P.ns;
+            // a source index is a position by construction; checked so that
+            // a sort defect can never read outside the arrays
+            const uint32_t src = vals_s[i] < ns ? vals_s[i] : i;
+            const double4 p = xr_b[src];
+            xr[i] = p;
+            xf[i] = far_record(G, p);
+            vw[i] = vw_b[src];
+            vw[ns + i] = vw_b[ns + src];
+            vw[2 * (size_t)ns + i] = vw_b[2 * (size_t)ns + src];
+            if (mat) mat[i] = mat_b[src];
+            prev[i] = src;
+            const uint32_t key = keys_s[i];
+            const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
+            if (i == J.p0 || keys_s[i - 1] != key) cells[lin].x = i;
+            if (i == end - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
+        }
     }
-    const uint32_t i = tile * TILE + threadIdx.x;
-    const uint32_t end = J.p0 + J.n;
-    if (i >= end) return;
-    const uint32_t ns = P.ns;
-    const uint32_t src = vals_s[i];
-    const double4 p = xr_b[src];
-    xr[i] = p;
-    xf[i] = far_record(G, p);
-    vw[i] = vw_b[src];
-    vw[ns + i] = vw_b[ns + src];
-    vw[2 * (size_t)ns + i] = vw_b[2 * (size_t)ns + src];
-    if (mat) mat[i] = mat_b[src];
-    prev[i] = src;
-    const uint32_t key = keys_s[i];
-    const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
-    if (i == J.p0 || keys_s[i - 1] != key) cells[lin].x = i;
-    if (i == end - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
 }
 
-// End of a step: the running jobs advance their time, step count and shear
-// offsets; a job that produced a non-finite state is marked failed.
+// End of a step: every running job advances (one thread per job).
 __global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
     if (__atomic_load_n(&P.st->err, __ATOMIC_RELAXED)) return;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1235,21 +1266,7 @@ __global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
         P.st->steps_done += 1;
         P.st->movers = 0;
     }
-    if (k >= njobs) return;
-    Job& J = jobs[k];
-    if (J.status != JOB_ACTIVE) return;
-    if (P.job_fail[k]) {
-        J.status = JOB_FAILED;
-        return;
-    }
-    const double t = J.t + J.g.dt;
-    J.t = t;
-    if (J.g.le) {
-        J.g.le_shift = fmod(J.g.le_dv * t, J.g.L[0]);
-        J.g.le_shift_next = fmod(J.g.le_dv * (t + J.g.dt), J.g.L[0]);
-    }
-    J.steps_done += 1;
-    if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
+    if (k < njobs) tick_job(P, jobs, k);
 }
 
 // ------------------------------------------------------------------ launch
@@ -1306,8 +1323,6 @@ void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* 
                        uint32_t* keys_s, uint32_t* vals_s, hipStream_t s) {
     if (P.ntiles == 0) return;
     hipLaunchKernelGGL(k_mov_sort, dim3(1), dim3(1024), 0, s, movers, mk, mp, P.st);
-    hipLaunchKernelGGL(k_mov_dest, dim3(MAX_MOVERS / 256), dim3(256), 0, s, P, oldkeys, mk, mp,
-                       keys_s, vals_s);
     hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, keys, oldkeys, mk, mp, keys_s,
                        vals_s);
 }
@@ -1342,17 +1357,16 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
     *vals_out = vi;
 }
 
-void launch_reorder(const PoolView& P, const uint32_t* keys_s, const uint32_t* vals_s,
-                    const State& B, const State& A, uint32_t* prev, uint2* cells, hipStream_t s) {
-    if (P.ntiles == 0) return;
-    hipLaunchKernelGGL(k_reorder, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, keys_s, vals_s, B.xr, B.vw,
-                       B.mat, A.xr, A.xf, A.vw, A.mat, prev, cells);
-}
-
-void launch_tick(const PoolView& P, Job* jobs, uint32_t njobs, hipStream_t s) {
+void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
+                    const uint32_t* vals_s, const State& B, const State& A, uint32_t* prev,
+                    uint2* cells, hipStream_t s) {
+    if (P.ntiles > 0)
+        hipLaunchKernelGGL(k_reorder, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, keys_s, vals_s,
+                           B.xr, B.vw, B.mat, A.xr, A.xf, A.vw, A.mat, prev, cells);
     const uint32_t nb = (njobs + 255) / 256;
     hipLaunchKernelGGL(k_tick, dim3(nb ? nb : 1), dim3(256), 0, s, P, jobs, njobs);
 }
+
 
 double le_offset(const Geo& G, double t) { return G.le ? std::fmod(G.le_dv * t, G.L[0]) : 0.0; }
 

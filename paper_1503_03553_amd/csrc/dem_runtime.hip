@@ -847,8 +847,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
     }
     prof_record(s, slot, 5);
     prof_record(s, slot, 6);
-    launch_reorder(P, ko, vo, B, A, s->prev, s->cells, s->stream);
-    launch_tick(P, s->jobs_d, s->max_jobs, s->stream);
+    launch_reorder(P, s->jobs_d, s->max_jobs, ko, vo, B, A, s->prev, s->cells, s->stream);
     prof_record(s, slot, 7);
     HIPCHK(hipGetLastError());
     return DEM_OK;

@@ -316,3 +316,15 @@ def test_merge_sort_equals_radix_sort(name):
         assert np.array_equal(runs[0][0][k], runs[1][0][k]), k
     for u, v in zip(runs[0][1], runs[1][1]):
         assert np.array_equal(u, v)
+
+
+def test_mover_into_the_first_cell():
+    # one particle crosses into the corner cell, whose key sorts before every
+    # other particle's: the merge must place it first
+    say("case mover into first cell")
+    sc = gen.scene_cluster(seed=5, n_side=3, vel_sigma=0.05)
+    o = oracle.Sim(sc, mode=1)
+    cell = 2.0 * float(sc.r.max())
+    sc.x[0] = sc.lo + 1.0005 * cell
+    sc.v[0] = -0.002 * cell / o.dt
+    trajectory_parity(sc, PREC_MIXED, steps=2, tol=1e-4)
