@@ -252,6 +252,25 @@ dem_status dem_pool_add(dem_pool *pool, const dem_params *params, const dem_mate
                         const double *w, const float *radius, const uint16_t *mat_id,
                         uint32_t steps, uint64_t *job);
 
+/*
+ * The host half of dem_pool_add, separately: dem_job_prepare validates a job
+ * and places its particles in cell order (arguments as dem_pool_add; no GPU
+ * call, safe to run on other threads while a pool steps);
+ * dem_pool_add_prepared then admits it between steps (DEM_EBUSY leaves the
+ * prepared job usable for a later try; any other outcome consumes it).
+ * dem_job_prep_cells gives the cells it takes (0 once consumed), and
+ * dem_job_prep_free releases it (NULL ignored).  The host copies of a
+ * prepared job are owned by it until it is admitted.
+ */
+typedef struct dem_job_prep dem_job_prep; /* opaque */
+dem_status dem_job_prepare(const dem_params *params, const dem_material *mats, uint32_t n_mats,
+                           uint64_t n, const double *x, const double *v, const double *w,
+                           const float *radius, const uint16_t *mat_id, dem_job_prep **out);
+uint64_t dem_job_prep_cells(const dem_job_prep *prep);
+dem_status dem_pool_add_prepared(dem_pool *pool, dem_job_prep *prep, uint32_t steps,
+                                 uint64_t *job);
+void dem_job_prep_free(dem_job_prep *prep);
+
 /* Enqueue nsteps steps of every running job (finished jobs are skipped). */
 dem_status dem_pool_step(dem_pool *pool, uint32_t nsteps);
 

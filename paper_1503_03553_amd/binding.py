@@ -31,7 +31,8 @@ EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state", "dem_get_conta
            "dem_footprint", "dem_profile", "dem_profile_read", "dem_pool_footprint",
            "dem_pool_create", "dem_pool_add", "dem_pool_step", "dem_pool_sync", "dem_pool_poll",
            "dem_pool_job_info", "dem_pool_get_state", "dem_pool_remove", "dem_pool_capacity",
-           "dem_job_cells",
+           "dem_job_cells", "dem_job_prepare", "dem_job_prep_cells", "dem_pool_add_prepared",
+           "dem_job_prep_free",
            "dem_pool_profile", "dem_pool_profile_read", "dem_pool_destroy")
 
 JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2
@@ -150,6 +151,15 @@ def lib():
         L.dem_pool_remove.argtypes = [_vp, ctypes.c_uint64]
         L.dem_pool_capacity.restype = ctypes.c_int
         L.dem_pool_capacity.argtypes = [_vp, u64p, u64p, u32p]
+        L.dem_job_prepare.restype = ctypes.c_int
+        L.dem_job_prepare.argtypes = [P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp, _vp,
+                                      _vp, ctypes.POINTER(_vp)]
+        L.dem_job_prep_cells.restype = ctypes.c_uint64
+        L.dem_job_prep_cells.argtypes = [_vp]
+        L.dem_pool_add_prepared.restype = ctypes.c_int
+        L.dem_pool_add_prepared.argtypes = [_vp, _vp, ctypes.c_uint32, u64p]
+        L.dem_job_prep_free.restype = None
+        L.dem_job_prep_free.argtypes = [_vp]
         L.dem_job_cells.restype = ctypes.c_uint64
         L.dem_job_cells.argtypes = [P, ctypes.c_uint64, ctypes.c_double]
         L.dem_pool_profile.restype = ctypes.c_int
@@ -370,6 +380,55 @@ def job_fits(sc, cap, cell_size=0.0) -> bool:
     return c > 0 and tiles * 128 <= cap["particles"] and c <= cap["cells"]
 
 
+class PreparedJob:
+    """A job validated and placed in cell order on the host (dem_job_prepare),
+    waiting for admission into a pool; safe to create on another thread."""
+
+    def __init__(self, lo, hi, x, v, w, r, materials, precision, mat=None, walls=0x3F,
+                 periodic=0, gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
+                 kn_form=0, cell_size=0.0):
+        P = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time, precision,
+                        kn_form, cell_size)
+        x = _c(x, np.float64, (-1, 3))
+        n = x.shape[0]
+        v = _c(v, np.float64, (n, 3))
+        w = _c(w, np.float64, (n, 3))
+        r32 = _c(r, np.float32, (n,))
+        mats = (Material * len(materials))()
+        for k, m in enumerate(materials):
+            mats[k] = Material(m.E, m.poisson, m.G, m.density, m.restitution, m.mu)
+        mat16 = None if mat is None else _c(mat, np.uint16, (n,))
+        self.n = n
+        self._h = _vp()
+        _check(lib().dem_job_prepare(ctypes.byref(P), ctypes.cast(mats, _vp), len(materials), n,
+                                     x.ctypes.data, v.ctypes.data, w.ctypes.data,
+                                     r32.ctypes.data, None if mat16 is None else mat16.ctypes.data,
+                                     ctypes.byref(self._h)), "dem_job_prepare")
+
+    @classmethod
+    def from_scene(cls, sc, precision, **kw):
+        args = dict(lo=sc.lo, hi=sc.hi, x=sc.x, v=sc.v, w=sc.w, r=sc.r, materials=sc.materials,
+                    mat=sc.mat if len(sc.materials) > 1 else None, walls=sc.walls,
+                    periodic=sc.periodic, gravity=sc.gravity, shear_rate=sc.shear_rate, dt=sc.dt,
+                    kn_form=sc.kn_form)
+        args.update(kw)
+        return cls(precision=precision, **args)
+
+    def cells(self) -> int:
+        return int(lib().dem_job_prep_cells(self._h)) if self._h else 0
+
+    def close(self):
+        if self._h:
+            lib().dem_job_prep_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Pool:
     """Many simulations advanced by shared launches (dem_pool_*)."""
 
@@ -417,6 +476,18 @@ class Pool:
                     kn_form=sc.kn_form)
         args.update(kw)
         return self.add(steps=steps, **args)
+
+    def prepare_scene(self, sc, **kw) -> PreparedJob:
+        """Host-side preparation of a job for this pool (any thread)."""
+        return PreparedJob.from_scene(sc, self.precision, **kw)
+
+    def add_prepared(self, prep, steps) -> int:
+        job = ctypes.c_uint64()
+        _check(lib().dem_pool_add_prepared(self._handle(), prep._h, int(steps), ctypes.byref(job)),
+               "dem_pool_add_prepared")
+        self._n[job.value] = prep.n
+        prep.close()
+        return job.value
 
     def step(self, k=1):
         _check(lib().dem_pool_step(self._handle(), int(k)), "dem_pool_step")

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -116,6 +117,7 @@ struct dem_pool {
     uint64_t regrows = 0;
     dem_status failed = DEM_OK;
     std::vector<std::vector<char>> staging;  // host buffers of uploads in flight
+    std::vector<std::shared_ptr<void>> held; // host arrays moved in for uploads in flight
     // device memory
     std::vector<Buf> bufs;
     size_t device_bytes = 0;
@@ -205,6 +207,17 @@ dem_status upload(dem_pool* s, void* dst, const void* src, size_t bytes) {
     if (!bytes) return DEM_OK;
     s->staging.emplace_back((const char*)src, (const char*)src + bytes);
     HIPCHK(hipMemcpyAsync(dst, s->staging.back().data(), bytes, hipMemcpyHostToDevice, s->stream));
+    return DEM_OK;
+}
+
+// Asynchronous upload of a host array that the pool takes over until the
+// next sync (no copy).
+template <typename T>
+dem_status upload_vec(dem_pool* s, void* dst, std::vector<T>& v) {
+    if (v.empty()) return DEM_OK;
+    auto h = std::make_shared<std::vector<T>>(std::move(v));
+    s->held.push_back(h);
+    HIPCHK(hipMemcpyAsync(dst, h->data(), h->size() * sizeof(T), hipMemcpyHostToDevice, s->stream));
     return DEM_OK;
 }
 
@@ -604,13 +617,16 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     auto up = [&](void* dst, const void* src, size_t bytes) {
         if (r == DEM_OK) r = upload(s, dst, src, bytes);
     };
-    up(s->A.xr + p0, pl.xr.data(), n * sizeof(double4));
-    up(s->A.xf + p0, pl.xf.data(), n * sizeof(float4));
-    up(s->A.vw + p0, pl.vw0.data(), n * sizeof(double2));
-    up(s->A.vw + np + p0, pl.vw1.data(), n * sizeof(double2));
-    up(s->A.vw + 2 * np + p0, pl.vw2.data(), n * sizeof(double2));
-    up(s->A.mat + p0, pl.mat.data(), n);
-    up(s->cells + J.cell_base, pl.cells.data(), (size_t)J.ncells * sizeof(uint2));
+    auto upv = [&](void* dst, auto& v) {
+        if (r == DEM_OK) r = upload_vec(s, dst, v);
+    };
+    upv(s->A.xr + p0, pl.xr);
+    upv(s->A.xf + p0, pl.xf);
+    upv(s->A.vw + p0, pl.vw0);
+    upv(s->A.vw + np + p0, pl.vw1);
+    upv(s->A.vw + 2 * np + p0, pl.vw2);
+    upv(s->A.mat + p0, pl.mat);
+    upv(s->cells + J.cell_base, pl.cells);
     const uint64_t span = (uint64_t)J.ntiles * TILE;
     std::vector<uint2> zr(span, make_uint2(0, 0));
     std::vector<uint32_t> idp(span);
@@ -915,6 +931,7 @@ dem_status sync_impl(dem_pool* s) {
         dem_status r = read_status(s, h);
         if (r != DEM_OK) return r;
         s->staging.clear();
+        s->held.clear();
         while (s->steps_confirmed < h.steps_done && !s->pending.empty()) {
             s->pending.pop_front();
             s->steps_confirmed++;
@@ -1154,6 +1171,7 @@ dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* 
     if (r != DEM_OK) return r;
     HIPCHK(hipStreamSynchronize(s->stream));
     s->staging.clear();
+    s->held.clear();
     return write_contacts(s, slot, c);
 }
 
@@ -1413,6 +1431,52 @@ dem_status dem_pool_add(dem_pool* s, const dem_params* params, const dem_materia
     *job = s->jobs[slot].id;
     return DEM_OK;
 }
+
+struct dem_job_prep {
+    Prepared pj;
+    bool used = false;
+};
+
+dem_status dem_job_prepare(const dem_params* params, const dem_material* mats, uint32_t n_mats,
+                           uint64_t n, const double* x, const double* v, const double* w,
+                           const float* radius, const uint16_t* mat_id, dem_job_prep** out) {
+    if (!out) return DEM_EINVAL;
+    *out = nullptr;
+    dem_job_prep* p = new (std::nothrow) dem_job_prep();
+    if (!p) return DEM_ENOMEM;
+    dem_status r = DEM_OK;
+    try {
+        r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, p->pj);
+    } catch (const std::bad_alloc&) {
+        r = DEM_ENOMEM;
+    }
+    if (r != DEM_OK) {
+        delete p;
+        return r;
+    }
+    *out = p;
+    return DEM_OK;
+}
+
+uint64_t dem_job_prep_cells(const dem_job_prep* p) { return p && !p->used ? p->pj.J.ncells : 0; }
+
+dem_status dem_pool_add_prepared(dem_pool* s, dem_job_prep* p, uint32_t steps, uint64_t* job) {
+    if (!s || !p || !job || p->used) return DEM_EINVAL;
+    if (s->failed != DEM_OK) return s->failed;
+    if (steps == 0 || steps == 0xFFFFFFFFu) return DEM_EINVAL;
+    if ((p->pj.J.P.precision == DEM_PREC_FP64) != s->fp64) return DEM_EINVAL;
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    int slot = 0;
+    r = commit_job(s, p->pj, steps, &slot);
+    if (r == DEM_EBUSY) return r;  // the prepared job stays usable
+    p->used = true;
+    if (r != DEM_OK) return r;
+    *job = s->jobs[slot].id;
+    return DEM_OK;
+}
+
+void dem_job_prep_free(dem_job_prep* p) { delete p; }
 
 static int slot_of(dem_pool* s, uint64_t id) {
     for (uint32_t k = 0; k < s->max_jobs; ++k)

@@ -49,8 +49,15 @@ class Request:
 
 class Server:
     def __init__(self, pool, superstep=20, max_bypass=50, clock=time.perf_counter,
-                 sleep=time.sleep, add_kw=None, on_done=None):
+                 sleep=time.sleep, add_kw=None, on_done=None, prepare_workers=4, lookahead=16):
         self.pool = pool
+        # host-side preparation of queued requests on worker threads (the
+        # library releases the interpreter lock), when the pool offers it
+        self.lookahead = int(lookahead)
+        self._exec = None
+        if prepare_workers and hasattr(pool, "prepare_scene"):
+            import concurrent.futures as cf
+            self._exec = cf.ThreadPoolExecutor(int(prepare_workers))
         self.superstep = int(superstep)
         self.max_bypass = int(max_bypass)
         self.clock = clock
@@ -69,20 +76,36 @@ class Server:
         return self.clock() - self._t0
 
     # ---------------------------------------------------------- admission
+    def _prepare_ahead(self):
+        if self._exec is None:
+            return
+        for k, r in enumerate(self.queue):
+            if k >= self.lookahead:
+                break
+            if "prep" not in r.extra:
+                r.extra["prep"] = self._exec.submit(self.pool.prepare_scene, r.scene,
+                                                    **self.add_kw)
+
     def _try_add(self, req) -> bool:
         from .binding import DemError
         try:
-            req.job = self.pool.add_scene(req.scene, steps=req.steps, **self.add_kw)
+            fut = req.extra.get("prep")
+            if fut is not None:
+                req.job = self.pool.add_prepared(fut.result(), req.steps)
+            else:
+                req.job = self.pool.add_scene(req.scene, steps=req.steps, **self.add_kw)
         except DemError as e:
             if e.code == EBUSY:
                 return False
             raise
+        req.extra.pop("prep", None)
         req.admitted = self.now()
         self.running[req.job] = req
         return True
 
     def admit(self) -> int:
         """Admit waiting requests that fit; returns how many were admitted."""
+        self._prepare_ahead()
         k = 0
         while self.queue and self._fits(self.queue[0]) and self._try_add(self.queue[0]):
             self.queue.popleft()
@@ -128,6 +151,7 @@ class Server:
                 raise TimeoutError("serving run exceeded %.1f s" % deadline)
             while pending and pending[0].arrival <= now:
                 self.queue.append(pending.popleft())
+            self._prepare_ahead()
             if self.running:
                 # the superstep is enqueued first: the host work of admitting
                 # new requests overlaps it on the device
@@ -144,6 +168,8 @@ class Server:
                 self.sleep(max(0.0, pending[0].arrival - self.now()))
             elif self.queue:
                 raise RuntimeError("request %d can never fit in the pool" % self.queue[0].rid)
+        if self._exec is not None:
+            self._exec.shutdown(wait=True)
         return self.stats()
 
     def stats(self) -> dict:

@@ -177,3 +177,29 @@ def test_autotuner_picks_the_fastest_candidate_and_lays_jobs_out_in_order():
     # density order: the smallest box is the densest
     assert tune.job_order(scenes, "density_desc")[0] == 0
     assert tune.cell_size_for(scenes[0], 1.0) == 0.0
+
+
+class PreparingPool(FakePool):
+    """FakePool with the prepare / add-prepared split of binding.Pool."""
+
+    def __init__(self, *a, **kw):
+        super().__init__(*a, **kw)
+        self.prepared = []
+
+    def prepare_scene(self, sc):
+        self.prepared.append(sc)
+        return types.SimpleNamespace(sc=sc, n=sc.n)
+
+    def add_prepared(self, prep, steps):
+        return self.add_scene(prep.sc, steps)
+
+
+def test_requests_are_prepared_ahead_once_each():
+    clk = Clock()
+    pool = PreparingPool(clk, 1000, 4)
+    reqs = [Request(k, scene(100 + 10 * k), 30, 0.001 * k) for k in range(20)]
+    srv = Server(pool, superstep=10, clock=clk, sleep=clk.sleep, lookahead=3)
+    st = srv.run(reqs)
+    assert st["jobs"] == 20
+    assert len(pool.prepared) == 20
+    assert len({id(s) for s in pool.prepared}) == 20
