@@ -180,7 +180,7 @@ def run_serving(templates, arr, tmpl, steps, stream, budget_particles, superstep
                     flags=FLAG_NO_FORCE_OUTPUT)
         reqs = [Request(q, templates[int(tmpl[q])], int(steps[q]), 0.0 if at_once else float(arr[q]))
                 for q in range(len(arr))]
-        srv = Server(pool, superstep=superstep)
+        srv = Server(pool, superstep=superstep, target_s=0.05)
         st = srv.run(reqs, deadline=600.0)
         pool.close()
         log("serving%s: %s" % (" (all at once)" if at_once else "", json.dumps(st)))
@@ -360,7 +360,7 @@ def run_others(a, out, sc, batch, serve_in, stream, log):
                               log)
         out["serving"] = {"rate_jobs_per_s": a.serve_rate, "horizon_s": a.serve_horizon,
                           "requests": int(len(arr)), "budget_particles": a.serve_budget,
-                          "superstep": a.superstep,
+                          "superstep": "adaptive, %d to start, about 50 ms each" % a.superstep,
                           "p50_latency_s": round(st["p50_s"], 4),
                           "p99_latency_s": round(st["p99_s"], 4),
                           "wait_p50_s": round(st["wait_p50_s"], 4),

@@ -49,8 +49,13 @@ class Request:
 
 class Server:
     def __init__(self, pool, superstep=20, max_bypass=50, clock=time.perf_counter,
-                 sleep=time.sleep, add_kw=None, on_done=None, prepare_workers=4, lookahead=16):
+                 sleep=time.sleep, add_kw=None, on_done=None, prepare_workers=4, lookahead=16,
+                 target_s=None, max_superstep=200):
         self.pool = pool
+        # with target_s the superstep adapts so that one lasts about target_s
+        # seconds: fewer host round trips when the pool is large
+        self.target_s = target_s
+        self.max_superstep = int(max_superstep)
         # host-side preparation of queued requests on worker threads (the
         # library releases the interpreter lock), when the pool offers it
         self.lookahead = int(lookahead)
@@ -127,6 +132,13 @@ class Server:
             self._bypassed += 1
         return k + passed
 
+    def _adapt(self, seconds):
+        if not self.target_s or seconds <= 0.0:
+            return
+        k = int(self.superstep * self.target_s / seconds)
+        k = max(self.superstep // 2, min(2 * self.superstep, k))
+        self.superstep = max(1, min(self.max_superstep, k))
+
     def _fits(self, req) -> bool:
         return self.pool.fits(req.scene, cell_size=self.add_kw.get("cell_size", 0.0))
 
@@ -155,10 +167,12 @@ class Server:
             if self.running:
                 # the superstep is enqueued first: the host work of admitting
                 # new requests overlaps it on the device
+                t0 = self.clock()
                 self.pool.step(self.superstep)
                 self.supersteps += 1
                 self.admit()
                 self._retire()
+                self._adapt(self.clock() - t0)
                 continue
             self.admit()
             if self.running:
