@@ -43,18 +43,20 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False):
         # write 8; partner index 4 per contact
         return 48 * n + 4 * m
     if phase == "force":
-        # reads: state 80, rows 8, prev 4, old row 8, cell bound 4;
-        # writes: integrated state 80, key+index 8, F/T 24 (48 in FP64) when
-        # stored; per contact: partner index 4 + new history 28; per old
-        # contact 28
+        # reads: sorted position 32, velocities 48 and old row 8 through the
+        # permutation 4, new row 8, cell bound 4; writes: integrated state 80,
+        # key, index and key before the step 12, F/T 24 (48 in FP64) when
+        # stored; per contact: partner index 4, partner permutation 4, new
+        # history 28; per old contact 28
         fo = (48 if fp64 else 24) if force_out else 0
-        return (104 + 88 + fo) * n + 32 * m + 28 * m_old
+        return (104 + 92 + fo) * n + 36 * m + 28 * m_old
     if phase == "sort":
         passes = max(1, (key_bits + 7) // 8)
         return 20 * n * passes
     if phase == "reorder":
-        # keys+index 8, gather 80, write 80, prev 4, cell bounds ~8
-        return 180 * n
+        # sorted key and source index 8, gathered position 32, sorted position
+        # and FP32 record written 48, permutation 4, cell bounds ~8
+        return 100 * n
     return 0
 
 

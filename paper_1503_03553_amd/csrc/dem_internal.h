@@ -94,15 +94,23 @@ struct TileStats {
     uint32_t pad;                            // the reorder kernel, so a redone step
 };                                           // counts once)
 
-// Sorted particle state: position + (radius bits | pid << 32) in one 32-byte
+// Particle state: position + (radius bits | pid << 32) in one 32-byte
 // record, velocity and angular velocity in three 16-byte planes
-// (vx,vy) (vz,wx) (wy,wz), and a material byte.
+// (vx,vy) (vz,wx) (wy,wz), and a material byte.  Two such buffers alternate:
+// a step reads one through the permutation `perm` (sorted position ->
+// buffer position) and writes the other in its own sorted order.
 struct State {
     double4* xr;
     double2* vw;   // 3 planes of n
     uint8_t* mat;  // may be null (one material)
-    float4* xf;    // sorted state only: (x - lo, y - lo, z - lo) in FP32 and the radius,
-                   // the compact record the contact search pre-filters on
+};
+
+// The records the contact search reads, in the sorted order of the step:
+// the FP64 position record and its compact FP32 form ((x, y, z) - lo and the
+// radius; NaN coordinates beyond 3 box lengths).
+struct Sorted {
+    double4* xr;
+    float4* xf;
 };
 
 __host__ __device__ inline uint64_t pack_meta(float r, uint32_t pid) {
@@ -133,13 +141,16 @@ struct PoolView {
 };
 // FP32 pre-filter margin of the contact search for a box of this geometry.
 float detect_margin(const Geo& G);
-void launch_detect(const PoolView& P, int kmax, const State& A, const uint2* cells, uint2* rows,
+void launch_detect(const PoolView& P, int kmax, const Sorted& S, const uint2* cells, uint2* rows,
                    uint32_t* col_j, uint32_t slots, hipStream_t s);
 // With `movers` non-null the force kernel also writes the key of every
 // position before the step (`oldkeys`) and appends (new key, position) of
 // the particles whose key changed to `movers` (at most MAX_MOVERS).
-void launch_force(const PoolView& P, bool fp64, const State& A, const State& B, const uint2* rows,
-                  const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
+// X: the state the step reads (through perm), Y: the state it writes (in
+// sorted order); S: the sorted positions.
+void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
+                  const uint2* rows, const uint32_t* col_j, const uint2* rows_old,
+                  const uint32_t* perm,
                   const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
                   double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
                   void* fo, uint32_t* oldkeys, uint2* movers, hipStream_t s);
@@ -154,12 +165,15 @@ void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* 
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                        uint32_t n, int bits, uint32_t* tile_hist, uint32_t* digit_tot,
                        uint32_t** keys_out, uint32_t** vals_out, const Status* st, hipStream_t s);
-// Gathers the state into the sorted order and writes cell bounds, then ends
-// the step for the `njobs` job descriptors (time, steps, status).
+// After the sort: the permutation (new sorted position -> position in Y),
+// the sorted position records gathered from Y, the cell bounds; then the
+// step ends for the `njobs` job descriptors (time, steps, status).
 void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
-                    const uint32_t* vals_s, const State& B, const State& A, uint32_t* prev,
+                    const uint32_t* vals_s, const State& Y, const Sorted& S, uint32_t* perm,
                     uint2* cells, hipStream_t s);
+// Rewrites the cell bounds of the current order from the sorted positions.
+void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipStream_t s);
+size_t sort_hist_words(uint32_t n);
 // Shear offset of the image along x at time t: D(t) = (shear_rate L_y t) mod L_x.
 double le_offset(const Geo& G, double t);
-size_t sort_hist_words(uint32_t n);
 }  // namespace dem

@@ -595,10 +595,11 @@ __device__ inline void contact_law(R nx, R ny, R nz, R dn, R vx, R vy, R vz, R r
 // ------------------------------------------------------------------ force
 template <typename R>
 __global__ __launch_bounds__(TILE) void k_force(
-    const double4* __restrict__ xr, const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
+    const double4* __restrict__ xr, const double4* __restrict__ xr_x,
+    const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
     double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
     const uint2* __restrict__ rows, const uint32_t* __restrict__ col_j,
-    const uint2* __restrict__ rows_old, const uint32_t* __restrict__ prev,
+    const uint2* __restrict__ rows_old, const uint32_t* __restrict__ perm,
     const uint32_t* __restrict__ tab_pid_old, const double* __restrict__ tab_dt_old,
     uint32_t* __restrict__ tab_pid_new, double* __restrict__ tab_dt_new, uint64_t cap,
     uint2* __restrict__ cells, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
@@ -622,10 +623,22 @@ __global__ __launch_bounds__(TILE) void k_force(
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
     if (!Jp) {
-        // not running: keys that keep every position of the tile in place
+        // not running: keys that keep every position of the tile in place;
+        // a finished job's state is carried over into the buffer written
         keys[p0 + t] = P.tile_key[tile] | P.lmask;
         vals[p0 + t] = p0 + t;
         if (movers) oldkeys[p0 + t] = P.tile_key[tile] | P.lmask;
+        if (jb != NO_JOB) {
+            const uint32_t i = p0 + t;
+            if (i < jobs[jb].p0 + jobs[jb].n) {
+                const uint32_t q = perm[i];
+                xr_b[i] = xr_x[q];
+                vw_b[i] = vw[q];
+                vw_b[ns + i] = vw[ns + q];
+                vw_b[2 * (size_t)ns + i] = vw[2 * (size_t)ns + q];
+                if (mat_b) mat_b[i] = mat[q];
+            }
+        }
         return;
     }
     const Job& J = *Jp;
@@ -644,13 +657,15 @@ __global__ __launch_bounds__(TILE) void k_force(
     uint2 row = make_uint2(0, 0);
     uint2 orow = make_uint2(0, 0);
     if (i < n) {
+        // own position in sorted order; velocities through the permutation
+        const uint32_t q = perm[i];
         row = rows[i];
-        orow = rows_old[prev[i]];
+        orow = rows_old[q];
         s_x[t] = xr[i];
-        s_vw[0][t] = vw[i];
-        s_vw[1][t] = vw[ns + i];
-        s_vw[2][t] = vw[2 * (size_t)ns + i];
-        s_mat[t] = mat ? mat[i] : (uint8_t)0;
+        s_vw[0][t] = vw[q];
+        s_vw[1][t] = vw[ns + q];
+        s_vw[2][t] = vw[2 * (size_t)ns + q];
+        s_mat[t] = mat ? mat[q] : (uint8_t)0;
     }
     s_old[t] = orow;
     if (t == 0) s_base = row.x;
@@ -687,8 +702,9 @@ __global__ __launch_bounds__(TILE) void k_force(
             if (code < FACE) {
                 const uint32_t j = code;
                 const double4 b = xr[j];
-                const double2 b0 = vw[j], b1 = vw[ns + j], b2 = vw[2 * (size_t)ns + j];
-                mj = mat ? mat[j] : 0;
+                const uint32_t qj = perm[j];
+                const double2 b0 = vw[qj], b1 = vw[ns + qj], b2 = vw[2 * (size_t)ns + qj];
+                mj = mat ? mat[qj] : 0;
                 pid_j = meta_pid(b.w);
                 const double rjd = (double)meta_r(b.w);
                 const R rj = (R)meta_r(b.w);
@@ -1207,55 +1223,74 @@ __device__ inline void tick_job(const PoolView& P, Job* jobs, uint32_t k) {
     if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
 }
 
-// One workgroup per tile.  Positions of free tiles, of jobs that are not
-// running and ghost slots kept their place in the sort and are left alone.
+// One workgroup per tile.  The new sorted order: the permutation into the
+// buffer just written, the position records gathered from it, and the cell
+// bounds.  Positions of free tiles and ghost slots kept their place in the
+// sort and are left alone; a finished job's positions map to themselves.
 __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restrict__ jobs,
                                                   const uint32_t* __restrict__ keys_s,
                                                   const uint32_t* __restrict__ vals_s,
-                                                  const double4* __restrict__ xr_b,
-                                                  const double2* __restrict__ vw_b,
-                                                  const uint8_t* __restrict__ mat_b,
-                                                  double4* __restrict__ xr, float4* __restrict__ xf,
-                                                  double2* __restrict__ vw,
-                                                  uint8_t* __restrict__ mat,
-                                                  uint32_t* __restrict__ prev,
+                                                  const double4* __restrict__ xr_y,
+                                                  double4* __restrict__ xs, float4* __restrict__ xf,
+                                                  uint32_t* __restrict__ perm,
                                                   uint2* __restrict__ cells) {
     __shared__ uint32_t s_flag;
     if (skip_if_error(P.st, &s_flag)) return;
     const uint32_t tile = blockIdx.x;
+    const uint32_t i = tile * TILE + threadIdx.x;
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
-    if (Jp) {
-        const Job& J = *Jp;
-        const Geo& G = J.g;
-        if (threadIdx.x == 0) {
-            // the step completed: its counters join the sums
-            TileStats& q = P.ts[tile];
-            q.m += q.m_step;
-            q.matched += q.matched_step;
-            q.old += q.old_step;
-        }
-        const uint32_t i = tile * TILE + threadIdx.x;
-        const uint32_t end = J.p0 + J.n;
-        if (i < end) {
-            const uint32_t ns = P.ns;
-            // a source index is a position by construction; checked so that
-            // a sort defect can never read outside the arrays
-            const uint32_t src = vals_s[i] < ns ? vals_s[i] : i;
-            const double4 p = xr_b[src];
-            xr[i] = p;
-            xf[i] = far_record(G, p);
-            vw[i] = vw_b[src];
-            vw[ns + i] = vw_b[ns + src];
-            vw[2 * (size_t)ns + i] = vw_b[2 * (size_t)ns + src];
-            if (mat) mat[i] = mat_b[src];
-            prev[i] = src;
-            const uint32_t key = keys_s[i];
-            const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
-            if (i == J.p0 || keys_s[i - 1] != key) cells[lin].x = i;
-            if (i == end - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
-        }
+    if (!Jp) {
+        if (jb != NO_JOB && i < jobs[jb].p0 + jobs[jb].n) perm[i] = i;
+        return;
     }
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    if (threadIdx.x == 0) {
+        // the step completed: its counters join the sums
+        TileStats& q = P.ts[tile];
+        q.m += q.m_step;
+        q.matched += q.matched_step;
+        q.old += q.old_step;
+    }
+    const uint32_t end = J.p0 + J.n;
+    if (i >= end) return;
+    // a source index is a position by construction; checked so that a sort
+    // defect can never read outside the arrays
+    const uint32_t src = vals_s[i] < P.ns ? vals_s[i] : i;
+    const double4 p = xr_y[src];
+    xs[i] = p;
+    xf[i] = far_record(G, p);
+    perm[i] = src;
+    const uint32_t key = keys_s[i];
+    const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
+    if (i == J.p0 || keys_s[i - 1] != key) cells[lin].x = i;
+    if (i == end - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
+}
+
+// Cell bounds of the current sorted order, from the sorted positions: after
+// a step that was abandoned once the force kernel had started (it empties the
+// bounds of the cells it leaves), before that step is redone.
+__global__ __launch_bounds__(TILE) void k_rebuild_cells(PoolView P, const Job* __restrict__ jobs,
+                                                        const double4* __restrict__ xs,
+                                                        uint2* __restrict__ cells) {
+    const uint32_t tile = blockIdx.x;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) return;
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const uint32_t i = tile * TILE + threadIdx.x;
+    const uint32_t end = J.p0 + J.n;
+    if (i >= end) return;
+    auto key_at = [&](uint32_t q) {
+        const double4 p = xs[q];
+        return cell_key(G, p.x, p.y, p.z);
+    };
+    const uint32_t key = key_at(i);
+    const uint32_t lin = J.cell_base + key_lin(G, key);
+    if (i == J.p0 || key_at(i - 1) != key) cells[lin].x = i;
+    if (i == end - 1 || key_at(i + 1) != key) cells[lin].y = i + 1;
 }
 
 // End of a step: every running job advances (one thread per job).
@@ -1281,12 +1316,12 @@ float detect_margin(const Geo& G) {
     return (float)(48.0 * 3.0 * Lm * 0x1p-24 + dmax * 0x1p-20);
 }
 
-void launch_detect(const PoolView& P, int kmax, const State& A, const uint2* cells, uint2* rows,
+void launch_detect(const PoolView& P, int kmax, const Sorted& S, const uint2* cells, uint2* rows,
                    uint32_t* col_j, uint32_t slots, hipStream_t s) {
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
 #define DEM_DETECT(K, PER)                                                                        \
-    hipLaunchKernelGGL((k_detect<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs, A.xr, A.xf,   \
+    hipLaunchKernelGGL((k_detect<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs, S.xr, S.xf,   \
                        cells, rows, col_j, slots)
     const bool per = P.any_periodic;
     if (kmax <= 8) {
@@ -1299,21 +1334,22 @@ void launch_detect(const PoolView& P, int kmax, const State& A, const uint2* cel
 #undef DEM_DETECT
 }
 
-void launch_force(const PoolView& P, bool fp64, const State& A, const State& B, const uint2* rows,
-                  const uint32_t* col_j, const uint2* rows_old, const uint32_t* prev,
-                  const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
-                  double* tab_dt_new, uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals,
-                  void* fo, uint32_t* oldkeys, uint2* movers, hipStream_t s) {
+void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
+                  const uint2* rows, const uint32_t* col_j, const uint2* rows_old,
+                  const uint32_t* perm, const uint32_t* tab_pid_old, const double* tab_dt_old,
+                  uint32_t* tab_pid_new, double* tab_dt_new, uint64_t cap, uint2* cells,
+                  uint32_t* keys, uint32_t* vals, void* fo, uint32_t* oldkeys, uint2* movers,
+                  hipStream_t s) {
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
     if (fp64)
-        hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, A.xr, A.vw, A.mat, B.xr,
-                           B.vw, B.mat, rows, col_j, rows_old, prev, tab_pid_old, tab_dt_old,
+        hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat,
+                           Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, P, P.jobs,
                            oldkeys, movers);
     else
-        hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, A.xr, A.vw, A.mat, B.xr,
-                           B.vw, B.mat, rows, col_j, rows_old, prev, tab_pid_old, tab_dt_old,
+        hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat,
+                           Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs,
                            oldkeys, movers);
 }
@@ -1357,12 +1393,18 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
     *vals_out = vi;
 }
 
+void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipStream_t s) {
+    if (P.ntiles > 0)
+        hipLaunchKernelGGL(k_rebuild_cells, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, S.xr,
+                           cells);
+}
+
 void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
-                    const uint32_t* vals_s, const State& B, const State& A, uint32_t* prev,
+                    const uint32_t* vals_s, const State& Y, const Sorted& S, uint32_t* perm,
                     uint2* cells, hipStream_t s) {
     if (P.ntiles > 0)
         hipLaunchKernelGGL(k_reorder, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, keys_s, vals_s,
-                           B.xr, B.vw, B.mat, A.xr, A.xf, A.vw, A.mat, prev, cells);
+                           Y.xr, S.xr, S.xf, perm, cells);
     const uint32_t nb = (njobs + 255) / 256;
     hipLaunchKernelGGL(k_tick, dim3(nb ? nb : 1), dim3(256), 0, s, P, jobs, njobs);
 }

@@ -84,8 +84,6 @@ struct HostJob {
     Layout lay{};
     Geo geo{};
     bool multi_mat = false;
-    bool hist_in_A = true;    // contact history indexed by the sorted order (else by the
-                              // order before the last reorder)
     bool reported = false;    // finished/failed status already returned by poll
     std::vector<float> r;
     std::vector<uint16_t> mat;
@@ -121,7 +119,8 @@ struct dem_pool {
     // device memory
     std::vector<Buf> bufs;
     size_t device_bytes = 0;
-    State A{}, B{};
+    State S[2]{};                     // state buffers; S[cur] holds the current state
+    Sorted srt{};                     // sorted position records of the current order
     uint2* cells = nullptr;
     uint2* rows[2] = {nullptr, nullptr};
     uint32_t* col_j = nullptr;
@@ -334,8 +333,8 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
                     uint64_t slots) {
     const uint64_t np = max_tiles * TILE;
     uint64_t b = 0;
-    b += np * (32 + 48 + 1 + 16);      // sorted state and its FP32 record
-    b += np * (32 + 48 + 1);           // integrated state
+    b += 2 * np * (32 + 48 + 1);       // two state buffers
+    b += np * (32 + 16);               // sorted positions and their FP32 records
     b += np * 2 * 8;                   // contact rows, two steps
     b += np * 6 * 4;                   // prev, keys and values (two buffers), keys before
     b += (uint64_t)MAX_MOVERS * 20;    // mover lists
@@ -378,7 +377,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     s->free_cells.push_back({0, s->max_cells});
     const size_t np = (size_t)mt * TILE;
     dem_status r = DEM_OK;
-    void *xa, *va, *ma, *xfa, *xb, *vb, *mb;
+    void *xa, *va, *ma, *xsa, *xfa, *xb, *vb, *mb;
 #define ALLOC_OR_FAIL(call)   \
     do {                      \
         r = (call);           \
@@ -390,18 +389,19 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xa));
     ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &va));
     ALLOC_OR_FAIL(dalloc(s, np, &ma));
+    ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xsa));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(float4), &xfa));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xb));
     ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &vb));
     ALLOC_OR_FAIL(dalloc(s, np, &mb));
-    s->A.xr = (double4*)xa;
-    s->A.vw = (double2*)va;
-    s->A.mat = (uint8_t*)ma;
-    s->A.xf = (float4*)xfa;
-    s->B.xr = (double4*)xb;
-    s->B.vw = (double2*)vb;
-    s->B.mat = (uint8_t*)mb;
-    s->B.xf = nullptr;
+    s->S[0].xr = (double4*)xa;
+    s->S[0].vw = (double2*)va;
+    s->S[0].mat = (uint8_t*)ma;
+    s->S[1].xr = (double4*)xb;
+    s->S[1].vw = (double2*)vb;
+    s->S[1].mat = (uint8_t*)mb;
+    s->srt.xr = (double4*)xsa;
+    s->srt.xf = (float4*)xfa;
     ALLOC_OR_FAIL(dalloc_t(s, s->max_cells, &s->cells));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[0]));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[1]));
@@ -436,8 +436,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     if (e == hipSuccess) e = hipMemset(s->fo, 0, 6 * np * (fp64 ? 8 : 4));
     if (e == hipSuccess) e = hipMemset(s->jobs_d, 0, max_jobs * sizeof(Job));
     if (e == hipSuccess) e = hipMemset(s->job_fail, 0, max_jobs * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(s->A.mat, 0, np);
-    if (e == hipSuccess) e = hipMemset(s->B.mat, 0, np);
+    if (e == hipSuccess) e = hipMemset(s->S[0].mat, 0, np);
+    if (e == hipSuccess) e = hipMemset(s->S[1].mat, 0, np);
     std::vector<uint32_t> tj(mt, NO_JOB);
     if (e == hipSuccess) e = hipMemcpy(s->tile_job, tj.data(), mt * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(s->tile_key, 0, mt * 4);
@@ -620,12 +620,18 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     auto upv = [&](void* dst, auto& v) {
         if (r == DEM_OK) r = upload_vec(s, dst, v);
     };
-    upv(s->A.xr + p0, pl.xr);
-    upv(s->A.xf + p0, pl.xf);
-    upv(s->A.vw + p0, pl.vw0);
-    upv(s->A.vw + np + p0, pl.vw1);
-    upv(s->A.vw + 2 * np + p0, pl.vw2);
-    upv(s->A.mat + p0, pl.mat);
+    // the state into the current buffer, in sorted order; the sorted
+    // position records are a copy of its positions
+    State& X = s->S[s->cur];
+    upv(X.xr + p0, pl.xr);
+    if (r == DEM_OK && n)
+        r = hip_status(hipMemcpyAsync(s->srt.xr + p0, X.xr + p0, n * sizeof(double4),
+                                      hipMemcpyDeviceToDevice, s->stream));
+    upv(s->srt.xf + p0, pl.xf);
+    upv(X.vw + p0, pl.vw0);
+    upv(X.vw + np + p0, pl.vw1);
+    upv(X.vw + 2 * np + p0, pl.vw2);
+    upv(X.mat + p0, pl.mat);
     upv(s->cells + J.cell_base, pl.cells);
     const uint64_t span = (uint64_t)J.ntiles * TILE;
     std::vector<uint2> zr(span, make_uint2(0, 0));
@@ -661,7 +667,6 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     up(s->jobs_d + slot, &jd, sizeof(Job));
     const uint32_t zero = 0;
     up(s->job_fail + slot, &zero, sizeof(zero));
-    J.hist_in_A = true;
     return r;
 }
 
@@ -826,8 +831,9 @@ void prof_record(dem_pool* s, size_t slot, int ev) {
 dem_status enqueue_step(dem_pool* s, int o) {
     const int w = 1 - o;
     PoolView P = view(s);
-    State A = s->A, B = s->B;
-    if (!s->any_multi_mat) A.mat = B.mat = nullptr;
+    // the step reads the state of buffer o and writes buffer w
+    State X = s->S[o], Y = s->S[w];
+    if (!s->any_multi_mat) X.mat = Y.mat = nullptr;
     size_t slot = 0;
     if (s->prof) {
         if (s->prof_used == s->prof_ev.size()) {
@@ -838,13 +844,13 @@ dem_status enqueue_step(dem_pool* s, int o) {
         slot = s->prof_used++;
     }
     prof_record(s, slot, 0);
-    launch_detect(P, s->kmax, A, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
+    launch_detect(P, s->kmax, s->srt, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
     prof_record(s, slot, 1);
     prof_record(s, slot, 2);
     // the merge sort unless a recent step had too many cell changes
     const bool merge = s->radix_left == 0 && !(s->flags & DEM_FLAG_RADIX_SORT);
     if (s->radix_left) s->radix_left--;
-    launch_force(P, s->fp64, A, B, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
+    launch_force(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
                  s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals,
                  (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo,
                  merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr, s->stream);
@@ -863,7 +869,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
     }
     prof_record(s, slot, 5);
     prof_record(s, slot, 6);
-    launch_reorder(P, s->jobs_d, s->max_jobs, ko, vo, B, A, s->prev, s->cells, s->stream);
+    launch_reorder(P, s->jobs_d, s->max_jobs, ko, vo, Y, s->srt, s->prev, s->cells, s->stream);
     prof_record(s, slot, 7);
     HIPCHK(hipGetLastError());
     return DEM_OK;
@@ -877,8 +883,6 @@ dem_status step_impl(dem_pool* s, uint32_t nsteps) {
         s->pending.push_back(s->cur);
         s->cur = 1 - s->cur;
     }
-    if (nsteps)
-        for (HostJob& j : s->jobs) j.hist_in_A = false;
     return DEM_OK;
 }
 
@@ -959,6 +963,10 @@ dem_status sync_impl(dem_pool* s) {
         z.need = 0;
         z.movers = 0;
         HIPCHK(hipMemcpy(s->st, &z, sizeof(Status), hipMemcpyHostToDevice));
+        // the abandoned step may have emptied cell bounds (the force kernel
+        // does so as it runs): restore those of the order it started from
+        launch_rebuild_cells(view(s), s->srt, s->cells, s->stream);
+        HIPCHK(hipGetLastError());
         s->prof_used = 0;
         const size_t k = s->pending.size();
         s->pending.clear();
@@ -973,14 +981,14 @@ dem_status read_job(dem_pool* s, int slot, Job& jd) {
     return DEM_OK;
 }
 
-// pids of a job's positions in A (current order) or B (order of the last
-// step's rows)
-dem_status job_pids(dem_pool* s, const HostJob& J, bool fromA, std::vector<uint32_t>& pid) {
+// pids of a job's positions in the current state buffer: the order in which
+// the last step wrote its state, forces and contact rows
+dem_status job_pids(dem_pool* s, const HostJob& J, std::vector<uint32_t>& pid) {
     const uint64_t n = J.n;
     std::vector<double4> xr(n);
     pid.resize(n);
     const uint32_t p0 = J.tile0 * TILE;
-    if (n) HIPCHK(hipMemcpy(xr.data(), (fromA ? s->A.xr : s->B.xr) + p0, n * sizeof(double4),
+    if (n) HIPCHK(hipMemcpy(xr.data(), s->S[s->cur].xr + p0, n * sizeof(double4),
                             hipMemcpyDeviceToHost));
     for (uint64_t i = 0; i < n; ++i) {
         uint64_t m;
@@ -998,10 +1006,11 @@ dem_status get_state_impl(dem_pool* s, int slot, double* x, double* v, double* w
     if (n == 0) return DEM_OK;
     std::vector<double4> xr(n);
     std::vector<double2> v0(n), v1(n), v2(n);
-    HIPCHK(hipMemcpy(xr.data(), s->A.xr + p0, n * sizeof(double4), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(v0.data(), s->A.vw + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(v1.data(), s->A.vw + np + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(v2.data(), s->A.vw + 2 * np + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
+    const State& X = s->S[s->cur];
+    HIPCHK(hipMemcpy(xr.data(), X.xr + p0, n * sizeof(double4), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v0.data(), X.vw + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v1.data(), X.vw + np + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(v2.data(), X.vw + 2 * np + p0, n * sizeof(double2), hipMemcpyDeviceToHost));
     for (uint64_t i = 0; i < n; ++i) {
         uint64_t m;
         std::memcpy(&m, &xr[i].w, 8);
@@ -1023,10 +1032,10 @@ dem_status get_state_impl(dem_pool* s, int slot, double* x, double* v, double* w
         }
     }
     if (F || T) {
-        // F, T were written in the order before the last reorder (that of B);
-        // before any step they are zero at the positions of A
+        // F, T were written at the positions of the current buffer (zero
+        // before the first step)
         std::vector<uint32_t> pid;
-        dem_status r = job_pids(s, J, J.hist_in_A, pid);
+        dem_status r = job_pids(s, J, pid);
         if (r != DEM_OK) return r;
         std::vector<double> f(6 * n);
         for (int c = 0; c < 6; ++c) {
@@ -1072,7 +1081,7 @@ dem_status read_contacts(dem_pool* s, int slot, std::vector<Contact>& out) {
             hi = std::max<uint64_t>(hi, (uint64_t)q.x + q.y);
         }
     std::vector<uint32_t> pid;
-    dem_status r = job_pids(s, J, J.hist_in_A, pid);
+    dem_status r = job_pids(s, J, pid);
     if (r != DEM_OK) return r;
     if (hi <= lo) return DEM_OK;
     const uint64_t m = hi - lo;
@@ -1093,8 +1102,9 @@ dem_status read_contacts(dem_pool* s, int slot, std::vector<Contact>& out) {
     return DEM_OK;
 }
 
-// Install a history (pid keyed) as the old table of the job's next step, in
-// the current sorted order, inside the job's own tile regions.
+// Install a history (pid keyed) as the old table of the job's next step, at
+// the positions of the current state buffer (which the next step reaches
+// through its permutation), inside the job's own tile regions.
 dem_status write_contacts(dem_pool* s, int slot, std::vector<Contact>& c) {
     HostJob& J = s->jobs[slot];
     const uint64_t n = J.n;
@@ -1115,7 +1125,7 @@ dem_status write_contacts(dem_pool* s, int slot, std::vector<Contact>& c) {
         if (r != DEM_OK) return r;
     }
     std::vector<uint32_t> pid;
-    dem_status r = job_pids(s, J, true, pid);
+    dem_status r = job_pids(s, J, pid);
     if (r != DEM_OK) return r;
     std::vector<uint32_t> pos(n);
     for (uint64_t q = 0; q < n; ++q) pos[pid[q]] = (uint32_t)q;
@@ -1145,10 +1155,6 @@ dem_status write_contacts(dem_pool* s, int slot, std::vector<Contact>& c) {
             HIPCHK(hipMemcpy(s->tab_dt[o] + (size_t)a * s->cap + base, td.data() + a * m, m * 8,
                              hipMemcpyHostToDevice));
     }
-    std::vector<uint32_t> idp(n);
-    std::iota(idp.begin(), idp.end(), p0);
-    if (n) HIPCHK(hipMemcpy(s->prev + p0, idp.data(), n * 4, hipMemcpyHostToDevice));
-    J.hist_in_A = true;
     return DEM_OK;
 }
 
