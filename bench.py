@@ -105,10 +105,11 @@ def kernels_of(rows):
 
 
 # ------------------------------------------------------------ single sim
-def run_single(sc, precision, steps, warmup, stream):
+def run_single(sc, precision, steps, warmup, stream, flags=0):
     import torch
     from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, Sim
-    sim = Sim.from_scene(sc, precision=precision, stream=stream, flags=FLAG_NO_FORCE_OUTPUT)
+    sim = Sim.from_scene(sc, precision=precision, stream=stream,
+                         flags=FLAG_NO_FORCE_OUTPUT | flags)
     sim.step(warmup)
     sim.sync()
     info0 = sim.info()
@@ -128,6 +129,36 @@ def run_single(sc, precision, steps, warmup, stream):
                 contacts=(info1["sum_contacts"] - info0["sum_contacts"]) / k,
                 contacts_old=(info1["sum_old"] - info0["sum_old"]) / k,
                 matched=(info1["sum_matched"] - info0["sum_matched"]) / k)
+
+
+# -------------------------------------------------------------- ablation
+def run_ablation(sizes, steps, warmup, stream, log):
+    """The fused single loop against the split path (section 3.4; the
+    comparison of section 4) on the grid inputs of gen.config_ablation, in
+    mixed precision.  "collide" is the contact search plus the force kernel:
+    detect + force for the split path, the fused kernel plus the clearing of
+    the old cell bounds for the fused one."""
+    import gen
+    from paper_1503_03553_amd import FLAG_FUSED, PREC_MIXED
+    rows = []
+    for n in sizes:
+        for regime in ("dense", "sparse"):
+            sc = gen.config_ablation(n, regime)
+            row = {"n": sc.n, "regime": regime}
+            for name, flag in (("split", 0), ("fused", FLAG_FUSED)):
+                r = run_single(sc, PREC_MIXED, steps, warmup, stream, flags=flag)
+                ph = {p: ms / c * 1e3 for p, (ms, c) in r["prof"].items() if c}
+                row["contacts_per_particle"] = round(r["contacts"] / sc.n, 3)
+                row[name] = {"ms_per_step": round(r["seconds"] / steps * 1e3, 4),
+                             "collide_us": round(ph.get("detect", 0.0) + ph.get("force", 0.0), 2),
+                             "phases_us": {p: round(v, 2) for p, v in ph.items()}}
+            row["collide_fused_over_split"] = round(row["fused"]["collide_us"] /
+                                                    row["split"]["collide_us"], 3)
+            row["step_fused_over_split"] = round(row["fused"]["ms_per_step"] /
+                                                 row["split"]["ms_per_step"], 3)
+            log("ablation %s" % json.dumps(row))
+            rows.append(row)
+    return rows
 
 
 # --------------------------------------------------------------- batched
@@ -230,7 +261,11 @@ def main():
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB 5 times "
                          "(reference reads/writes for HBM traffic counters)")
-    ap.add_argument("--only", choices=("all", "single", "batch", "serve"), default="all",
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--ablation-sizes", default="131072,524288,2097152")
+    ap.add_argument("--ablation-steps", type=int, default=20)
+    ap.add_argument("--only", choices=("all", "single", "batch", "serve", "ablation"),
+                    default="all",
                     help="run one part only (for profiling); the JSON line then lacks the others")
     ap.add_argument("--verbose", action="store_true")
     a = ap.parse_args()
@@ -239,6 +274,7 @@ def main():
         a.no_cpu = True
         a.no_batch = a.only != "batch"
         a.no_serve = a.only != "serve"
+        a.no_ablation = a.only != "ablation"
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(got --gpus %d)" % a.gpus, file=sys.stderr)
@@ -252,8 +288,9 @@ def main():
     # every input is drawn before anything touches the GPU (the generators
     # fork worker processes)
     t = time.perf_counter()
-    sc = gen.config_dilute(n=a.n)
-    log("headline input: %d spheres in %.1fs" % (sc.n, time.perf_counter() - t))
+    sc = gen.config_dilute(n=a.n) if a.only in ("all", "single") or not a.no_cpu else None
+    if sc is not None:
+        log("headline input: %d spheres in %.1fs" % (sc.n, time.perf_counter() - t))
     batch = []
     if not a.no_batch:
         t = time.perf_counter()
@@ -374,6 +411,14 @@ def run_others(a, out, sc, batch, serve_in, stream, log):
                                           "makespan_s": round(sat["makespan_s"], 3),
                                           "p50_latency_s": round(sat["p50_s"], 4),
                                           "p99_latency_s": round(sat["p99_s"], 4)}}
+
+    if not a.no_ablation:
+        sizes = [int(v) for v in a.ablation_sizes.split(",") if v]
+        out["ablation_fused_vs_split"] = {
+            "what": "collide = contact search + force kernels per step, mixed precision; "
+                    "fused = the single loop before the split of section 3.4",
+            "steps": a.ablation_steps, "warmup": 5,
+            "rows": run_ablation(sizes, a.ablation_steps, 5, stream, log)}
 
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sc, a.cpu_budget)

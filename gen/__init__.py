@@ -247,6 +247,37 @@ def config_dense_shear(seed=None, n=8_000_000, phi=0.4, shear_rate=100.0, p_touc
     return sc
 
 
+def config_ablation(n, regime, seed=None, r=5e-6):
+    """Inputs of the fused-versus-split comparison of section 4 (N from
+    131,072 up to 2M): monodisperse spheres on a simple cubic grid with small
+    random offsets, six walls, gravity.
+
+    "dense" stands in for the packed state after the warm-up: spacing
+    2 r (1 - 1e-3) and offsets U(-2e-3 r, 2e-3 r) per coordinate, so that
+    most grid neighbours overlap (about five directed contacts per sphere,
+    varying from sphere to sphere).  "sparse" is the initial state with no
+    contacts: spacing 2.2 r and offsets U(-0.05 r, 0.05 r)."""
+    seed = SEED_BASE + 7000 + (0 if regime == "dense" else 1) if seed is None else seed
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if regime == "dense":
+        h, jit = 2.0 * r * (1.0 - 1e-3), 2e-3 * r
+    elif regime == "sparse":
+        h, jit = 2.2 * r, 0.05 * r
+    else:
+        raise ValueError(regime)
+    m = int(round(n ** (1.0 / 3.0)))
+    nz = -(-n // (m * m))
+    k = np.arange(n)
+    ijk = np.stack([k % m, (k // m) % m, k // (m * m)], axis=1).astype(np.float64)
+    lo = np.zeros(3)
+    hi = np.array([m, m, nz], np.float64) * h + 2.0 * r
+    x = r + 0.5 * (h - 2.0 * r) + ijk * h + rng.uniform(-jit, jit, size=(n, 3))
+    x = np.clip(x, lo + r, hi - r)
+    mats = [Material.make(restitution=0.5, mu=0.3)]
+    return _finish(rng, x, f32(np.full(n, r)), lo, hi, mats, steps=20,
+                   name="ablation-%s-%d" % (regime, n), meta=dict(regime=regime))
+
+
 def batch_sizes(k, jobs, lo=1e3, hi=2e5):
     """Particle counts of a batched workload: log-uniform in [lo, hi]."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7000 + k))

@@ -97,6 +97,12 @@ typedef struct {
 #define DEM_FLAG_RADIX_SORT 2u      /* sort all keys every step (LSD radix sort) instead of
                                        merging the particles that changed cell; same
                                        results, for comparison */
+#define DEM_FLAG_FUSED 4u           /* ablation of the split of section 3.4: one kernel
+                                       whose lane per particle runs the contact law as
+                                       soon as it finds a contact (Algorithm 1 before
+                                       the split).  Same contact set; the per-particle
+                                       sums follow the order the contacts were found
+                                       instead of ascending partner id */
 
 /* Diagnostics of a simulation (dem_get_info). */
 typedef struct {

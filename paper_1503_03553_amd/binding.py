@@ -19,6 +19,7 @@ PREC_FP64 = 0
 PREC_MIXED = 1
 FLAG_NO_FORCE_OUTPUT = 1
 FLAG_RADIX_SORT = 2
+FLAG_FUSED = 4
 NPHASE = 4
 PHASES = ("detect", "force", "sort", "reorder")
 

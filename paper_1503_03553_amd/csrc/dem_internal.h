@@ -157,6 +157,13 @@ void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X,
 // Stable sort of the n = ntiles * TILE keys by merging the few particles
 // that changed cell into the unchanged ones, which are still in key order;
 // the result (keys_s, vals_s) equals the radix sort's.
+// The fused single loop (detect and force in one kernel), then the clearing
+// of the old cell bounds.
+void launch_fused(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
+                  uint2* rows, uint32_t* col_j, const uint2* rows_old, const uint32_t* perm,
+                  const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
+                  double* tab_dt_new, uint64_t cap, uint32_t slots, uint2* cells, uint32_t* keys,
+                  uint32_t* vals, void* fo, uint32_t* oldkeys, uint2* movers, hipStream_t s);
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
                        const uint2* movers, unsigned long long* mk, uint32_t* mp,
                        uint32_t* keys_s, uint32_t* vals_s, hipStream_t s);

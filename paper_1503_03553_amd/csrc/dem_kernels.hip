@@ -190,11 +190,166 @@ __device__ inline void merge_range(uint2 c, uint32_t& lo, uint32_t& hi) {
     }
 }
 
+// Candidate ranges of the particle at a (radius ri), written to
+// s_win[k * DTILE + t]; returns their number.  The lane scans the 27 cells
+// around the particle as 9 contiguous ranges: in each (y, z) row the three
+// x-neighbouring cells are consecutive cell keys (plus, across a periodic x
+// boundary, one wrapped cell).  All 27 cell bounds are loaded before any is
+// used.
+template <bool PER>
+__device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4& a, double ri,
+                                                     const uint2* __restrict__ cells,
+                                                     uint2* s_win, int t) {
+    const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+    // without periodic jobs in the pool the wrap and shear code compiles away
+    const bool px = PER && (G.periodic & 1u), py = PER && (G.periodic & 2u),
+               pz = PER && (G.periodic & 4u), le = PER && G.le;
+    uint32_t nw = 0;
+    const int cx = cell_coord(G, a.x, 0), cy = cell_coord(G, a.y, 1), cz = cell_coord(G, a.z, 2);
+    // Reach pruning: a partner lies within r_i + reach of the particle, so
+    // a row of cells whose (y, z) slab is farther holds none, nor does an
+    // x-neighbour cell beyond the reach left in x.  Per offset -1, 0, +1
+    // along y and z: whether the neighbour row exists, its (wrapped)
+    // index, and the squared gap from the particle to its slab.
+    const double reach = ri + G.reach;
+    const double reach2 = reach * reach;
+    int qy[3], qz[3], ky[3];
+    bool oky[3], okz[3];
+    double gy2[3], gz2[3];
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+        const int d = o - 1;
+        int y = cy + d, z = cz + d, kk = 0;
+        bool ok_y = true, ok_z = true;
+        if (y < 0 || y >= ny) {
+            if (!py) ok_y = false;
+            kk = y < 0 ? -1 : 1;
+            y -= kk * ny;
+        }
+        if (z < 0 || z >= nz) {
+            if (!pz) ok_z = false;
+            z = z < 0 ? z + nz : z - nz;
+        }
+        qy[o] = y;
+        qz[o] = z;
+        ky[o] = kk;
+        oky[o] = ok_y;
+        okz[o] = ok_z;
+        double g = 0.0, h = 0.0;
+        if (d > 0) {
+            g = fmax(0.0, G.lo[1] + (double)(cy + 1) * G.cw[1] - a.y);
+            h = fmax(0.0, G.lo[2] + (double)(cz + 1) * G.cw[2] - a.z);
+        } else if (d < 0) {
+            g = fmax(0.0, a.y - (G.lo[1] + (double)cy * G.cw[1]));
+            h = fmax(0.0, a.z - (G.lo[2] + (double)cz * G.cw[2]));
+        }
+        gy2[o] = g * g;
+        gz2[o] = h * h;
+    }
+    const double dl = a.x - (G.lo[0] + (double)cx * G.cw[0]);
+    const double dh = G.lo[0] + (double)(cx + 1) * G.cw[0] - a.x;
+    const double dl2 = dl > 0.0 ? dl * dl : 0.0, dh2 = dh > 0.0 ? dh * dh : 0.0;
+
+    // the 9 rows' three cells (main range, plus the wrapped x neighbour
+    // with a periodic x axis); all 27 cell bounds are loaded before any is
+    // used
+    uint32_t il[9], im[9], ih[9];
+    bool okl[9], okm[9], okh[9], wrl[9], wrh[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int oz = k / 3, oy = k % 3;
+        const double rx2 = reach2 - gy2[oy] - gz2[oz];
+        const bool ok = oky[oy] && okz[oz] && rx2 > 0.0;
+        int cxq = cx;
+        bool xprune = true;
+        if (le && ky[oy] != 0) {
+            // across a sheared y boundary the partner row is offset along x
+            double fx = floor((a.x - (double)ky[oy] * G.le_shift - G.lo[0]) * G.inv_cell[0]);
+            const double lim = 2.0 * (double)nx;
+            if (!(fx >= -lim)) fx = -lim;  // also NaN
+            if (fx > lim) fx = lim;
+            cxq = (int)fx % nx;
+            if (cxq < 0) cxq += nx;
+            xprune = false;
+        }
+        int xl = cxq - 1, xh = cxq + 1;
+        okm[k] = ok;
+        okl[k] = ok && !(xprune && dl2 >= rx2);
+        okh[k] = ok && !(xprune && dh2 >= rx2);
+        wrl[k] = wrh[k] = false;
+        if (xl < 0) {
+            if (px) { xl += nx; wrl[k] = true; } else okl[k] = false;
+        }
+        if (xh >= nx) {
+            if (px) { xh -= nx; wrh[k] = true; } else okh[k] = false;
+        }
+        const uint32_t row = ok ? ((uint32_t)qz[oz] * (uint32_t)ny + (uint32_t)qy[oy]) * (uint32_t)nx : 0u;
+        il[k] = okl[k] ? row + (uint32_t)xl : 0u;
+        im[k] = ok ? row + (uint32_t)cxq : 0u;
+        ih[k] = okh[k] ? row + (uint32_t)xh : 0u;
+    }
+    uint2 cl[9], cm[9], cr[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        cl[k] = cells[il[k]];
+        cm[k] = cells[im[k]];
+        cr[k] = cells[ih[k]];
+    }
+    // non-empty ranges to LDS, so one flat loop walks all candidates
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const uint2 z = make_uint2(0, 0);
+        const uint2 l = okl[k] ? cl[k] : z, m = okm[k] ? cm[k] : z, h = okh[k] ? cr[k] : z;
+        uint32_t lo = 0xFFFFFFFFu, hi = 0u, lo2 = 0xFFFFFFFFu, hi2 = 0u;
+        merge_range(m, lo, hi);
+        if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
+        if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
+        if (hi > lo) s_win[(nw++) * DTILE + t] = make_uint2(lo, hi);
+        if (PER && hi2 > lo2) s_win[(nw++) * DTILE + t] = make_uint2(lo2, hi2);
+    }
+    return nw;
+}
+
+// FP32 pre-filter of a candidate record: never rejects a pair that touches in
+// FP64 (NaN records of particles far from the box always pass).
+template <bool PER>
+struct PreFilter {
+    float4 me;
+    float Lx, Ly, Lz, Df, iLx, iLy, iLz, rm;
+    uint32_t per;
+    __device__ PreFilter(const Geo& G, const double4& a, float margin) {
+        me = far_record(G, a);
+        Lx = (float)G.L[0];
+        Ly = (float)G.L[1];
+        Lz = (float)G.L[2];
+        Df = (float)G.le_shift;
+        iLx = (float)G.inv_L[0];
+        iLy = (float)G.inv_L[1];
+        iLz = (float)G.inv_L[2];
+        rm = me.w + margin;
+        per = G.periodic;
+    }
+    __device__ bool operator()(const float4& b) const {
+        float dx = b.x - me.x, dy = b.y - me.y, dz = b.z - me.z;
+        if (PER) {
+            int ky = 0;
+            if (per & 2u) {
+                ky = -(int)rintf(dy * iLy);
+                dy += (float)ky * Ly;
+            }
+            if (per & 1u) {
+                const int kx = -(int)rintf((dx + (float)ky * Df) * iLx);
+                dx += (float)kx * Lx + (float)ky * Df;
+            }
+            if (per & 4u) dz += (float)(-(int)rintf(dz * iLz)) * Lz;
+        }
+        const float sm = rm + b.w;
+        return !(dx * dx + dy * dy + dz * dz >= sm * sm);
+    }
+};
+
 // One lane per particle, DTILE consecutive particles (cell order) per
-// workgroup.  The lane scans the 27 cells around its particle as 9 contiguous
-// ranges: in each (y, z) row the three x-neighbouring cells are consecutive
-// cell keys (plus, across a periodic x boundary, one wrapped cell).  All 27
-// cell bounds are loaded before any is used.
+// workgroup; the lane walks the candidate ranges of its particle.
 //
 // Candidates are read as one 16-byte FP32 record each (position relative to
 // the box corner, radius) and pre-filtered with a margin that covers the
@@ -242,142 +397,17 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
     cells += J.cell_base;
     const uint32_t i = tile * DTILE + t;
     const bool act = i < J.p0 + J.n;
-    const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
-    // without periodic jobs in the pool the wrap and shear code compiles away
-    const bool px = PER && (G.periodic & 1u), py = PER && (G.periodic & 2u),
-               pz = PER && (G.periodic & 4u), le = PER && G.le;
 
     uint32_t cnt = 0;
     uint32_t nw = 0;
     if (act) {
         const double4 a = xr[i];
         const double ri = (double)meta_r(a.w);
-        const int cx = cell_coord(G, a.x, 0), cy = cell_coord(G, a.y, 1), cz = cell_coord(G, a.z, 2);
-        // Reach pruning: a partner lies within r_i + reach of the particle, so
-        // a row of cells whose (y, z) slab is farther holds none, nor does an
-        // x-neighbour cell beyond the reach left in x.  Per offset -1, 0, +1
-        // along y and z: whether the neighbour row exists, its (wrapped)
-        // index, and the squared gap from the particle to its slab.
-        const double reach = ri + G.reach;
-        const double reach2 = reach * reach;
-        int qy[3], qz[3], ky[3];
-        bool oky[3], okz[3];
-        double gy2[3], gz2[3];
-#pragma unroll
-        for (int o = 0; o < 3; ++o) {
-            const int d = o - 1;
-            int y = cy + d, z = cz + d, kk = 0;
-            bool ok_y = true, ok_z = true;
-            if (y < 0 || y >= ny) {
-                if (!py) ok_y = false;
-                kk = y < 0 ? -1 : 1;
-                y -= kk * ny;
-            }
-            if (z < 0 || z >= nz) {
-                if (!pz) ok_z = false;
-                z = z < 0 ? z + nz : z - nz;
-            }
-            qy[o] = y;
-            qz[o] = z;
-            ky[o] = kk;
-            oky[o] = ok_y;
-            okz[o] = ok_z;
-            double g = 0.0, h = 0.0;
-            if (d > 0) {
-                g = fmax(0.0, G.lo[1] + (double)(cy + 1) * G.cw[1] - a.y);
-                h = fmax(0.0, G.lo[2] + (double)(cz + 1) * G.cw[2] - a.z);
-            } else if (d < 0) {
-                g = fmax(0.0, a.y - (G.lo[1] + (double)cy * G.cw[1]));
-                h = fmax(0.0, a.z - (G.lo[2] + (double)cz * G.cw[2]));
-            }
-            gy2[o] = g * g;
-            gz2[o] = h * h;
-        }
-        const double dl = a.x - (G.lo[0] + (double)cx * G.cw[0]);
-        const double dh = G.lo[0] + (double)(cx + 1) * G.cw[0] - a.x;
-        const double dl2 = dl > 0.0 ? dl * dl : 0.0, dh2 = dh > 0.0 ? dh * dh : 0.0;
-
-        // the 9 rows' three cells (main range, plus the wrapped x neighbour
-        // with a periodic x axis); all 27 cell bounds are loaded before any is
-        // used
-        uint32_t il[9], im[9], ih[9];
-        bool okl[9], okm[9], okh[9], wrl[9], wrh[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const int oz = k / 3, oy = k % 3;
-            const double rx2 = reach2 - gy2[oy] - gz2[oz];
-            const bool ok = oky[oy] && okz[oz] && rx2 > 0.0;
-            int cxq = cx;
-            bool xprune = true;
-            if (le && ky[oy] != 0) {
-                // across a sheared y boundary the partner row is offset along x
-                double fx = floor((a.x - (double)ky[oy] * G.le_shift - G.lo[0]) * G.inv_cell[0]);
-                const double lim = 2.0 * (double)nx;
-                if (!(fx >= -lim)) fx = -lim;  // also NaN
-                if (fx > lim) fx = lim;
-                cxq = (int)fx % nx;
-                if (cxq < 0) cxq += nx;
-                xprune = false;
-            }
-            int xl = cxq - 1, xh = cxq + 1;
-            okm[k] = ok;
-            okl[k] = ok && !(xprune && dl2 >= rx2);
-            okh[k] = ok && !(xprune && dh2 >= rx2);
-            wrl[k] = wrh[k] = false;
-            if (xl < 0) {
-                if (px) { xl += nx; wrl[k] = true; } else okl[k] = false;
-            }
-            if (xh >= nx) {
-                if (px) { xh -= nx; wrh[k] = true; } else okh[k] = false;
-            }
-            const uint32_t row = ok ? ((uint32_t)qz[oz] * (uint32_t)ny + (uint32_t)qy[oy]) * (uint32_t)nx : 0u;
-            il[k] = okl[k] ? row + (uint32_t)xl : 0u;
-            im[k] = ok ? row + (uint32_t)cxq : 0u;
-            ih[k] = okh[k] ? row + (uint32_t)xh : 0u;
-        }
-        uint2 cl[9], cm[9], cr[9];
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            cl[k] = cells[il[k]];
-            cm[k] = cells[im[k]];
-            cr[k] = cells[ih[k]];
-        }
-        // non-empty ranges to LDS, so one flat loop walks all candidates
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            const uint2 z = make_uint2(0, 0);
-            const uint2 l = okl[k] ? cl[k] : z, m = okm[k] ? cm[k] : z, h = okh[k] ? cr[k] : z;
-            uint32_t lo = 0xFFFFFFFFu, hi = 0u, lo2 = 0xFFFFFFFFu, hi2 = 0u;
-            merge_range(m, lo, hi);
-            if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
-            if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
-            if (hi > lo) s_win[(nw++) * DTILE + t] = make_uint2(lo, hi);
-            if (PER && hi2 > lo2) s_win[(nw++) * DTILE + t] = make_uint2(lo2, hi2);
-        }
+        nw = candidate_ranges<PER>(G, a, ri, cells, s_win, t);
 
         // FP32 pre-filter: never rejects a pair that touches in FP64 (NaN
         // records of particles far from the box always pass)
-        const float4 me = far_record(G, a);
-        const float Lx = (float)G.L[0], Ly = (float)G.L[1], Lz = (float)G.L[2], Df = (float)G.le_shift;
-        const float iLx = (float)G.inv_L[0], iLy = (float)G.inv_L[1], iLz = (float)G.inv_L[2];
-        const float rm = me.w + margin;
-        auto pre = [&](const float4& b) {
-            float dx = b.x - me.x, dy = b.y - me.y, dz = b.z - me.z;
-            if (PER) {
-                int ky = 0;
-                if (G.periodic & 2u) {
-                    ky = -(int)rintf(dy * iLy);
-                    dy += (float)ky * Ly;
-                }
-                if (G.periodic & 1u) {
-                    const int kx = -(int)rintf((dx + (float)ky * Df) * iLx);
-                    dx += (float)kx * Lx + (float)ky * Df;
-                }
-                if (G.periodic & 4u) dz += (float)(-(int)rintf(dz * iLz)) * Lz;
-            }
-            const float sm = rm + b.w;
-            return !(dx * dx + dy * dy + dz * dz >= sm * sm);
-        };
+        const PreFilter<PER> pre(G, a, margin);
         // pass 1: one flat loop over all candidates of all ranges with the
         // records of the next candidates already in flight; survivors go
         // unsorted into the row buffer.  The walk over the ranges is
@@ -593,6 +623,290 @@ __device__ inline void contact_law(R nx, R ny, R nz, R dn, R vx, R vy, R vz, R r
 }
 
 // ------------------------------------------------------------------ force
+// Terms of one contact of the particle at a (state a0, a1, a2 = v_x v_y,
+// v_z w_x, w_y w_z; material mi) with `code`, a partner's sorted position or
+// a box face: unit normal towards the partner, overlap, relative velocity of
+// the centres, the radius-weighted sum of angular velocities, reduced radius
+// and mass, the partner's material and id.  A face has infinite radius and
+// mass and the particle's own material.
+template <typename R>
+struct PairTerms {
+    R nx, ny, nz, dn, vx, vy, vz, rwx, rwy, rwz, rs, ms;
+    int mj;
+    uint32_t pid;
+};
+
+template <typename R>
+__device__ __forceinline__ PairTerms<R> pair_terms(
+    const Geo& G, const MatTable* __restrict__ mt, uint32_t code, const double4& a,
+    const double2& a0, const double2& a1, const double2& a2, int mi,
+    const double4* __restrict__ xr, const double2* __restrict__ vw,
+    const uint8_t* __restrict__ mat, const uint32_t* __restrict__ perm, uint32_t ns) {
+    PairTerms<R> p;
+    const R ri = (R)meta_r(a.w);
+    const double rid = (double)meta_r(a.w);
+    const R mass_i = (R)(mt->mass_pref[mi] * rid * rid * rid);
+    if (code < FACE) {
+        const uint32_t j = code;
+        const double4 b = xr[j];
+        const uint32_t qj = perm[j];
+        const double2 b0 = vw[qj], b1 = vw[ns + qj], b2 = vw[2 * (size_t)ns + qj];
+        p.mj = mat ? mat[qj] : 0;
+        p.pid = meta_pid(b.w);
+        const double rjd = (double)meta_r(b.w);
+        const R rj = (R)meta_r(b.w);
+        double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+        int ky = 0;
+        if (G.periodic) {
+            double Sx, Sy, Sz;
+            image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+            dx = dx + Sx;
+            dy = dy + Sy;
+            dz = dz + Sz;
+        }
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double s = rid + rjd;
+        if (sizeof(R) == 8) {
+            const double d = sqrt(d2);
+            p.nx = (R)(dx / d);
+            p.ny = (R)(dy / d);
+            p.nz = (R)(dz / d);
+            p.dn = (R)(s - d);
+        } else {
+            // overlap from (s^2 - d^2) / (s + d): the subtraction in FP64
+            // avoids the cancellation of s - d in FP32
+            const float d32 = sqrtf((float)d2);
+            const float inv = 1.0f / d32;
+            p.nx = (R)((float)dx * inv);
+            p.ny = (R)((float)dy * inv);
+            p.nz = (R)((float)dz * inv);
+            p.dn = (R)((float)(s * s - d2) / ((float)s + d32));
+        }
+        p.vx = (R)((a0.x - b0.x) - (double)ky * G.le_dv);
+        p.vy = (R)(a0.y - b0.y);
+        p.vz = (R)(a1.x - b1.x);
+        p.rwx = ri * (R)a1.y + rj * (R)b1.y;
+        p.rwy = ri * (R)a2.x + rj * (R)b2.x;
+        p.rwz = ri * (R)a2.y + rj * (R)b2.y;
+        p.rs = ri * rj / (ri + rj);
+        const R mass_j = (R)(mt->mass_pref[p.mj] * rjd * rjd * rjd);
+        p.ms = mass_i * mass_j / (mass_i + mass_j);
+    } else {
+        const int f = (int)(code - FACE), ax = f >> 1;
+        p.pid = code;
+        p.mj = mi;
+        const double q = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+        const double dist = (f & 1) ? G.hi[ax] - q : q - G.lo[ax];
+        const R sg = (f & 1) ? (R)1 : (R)-1;
+        p.nx = ax == 0 ? sg : (R)0;
+        p.ny = ax == 1 ? sg : (R)0;
+        p.nz = ax == 2 ? sg : (R)0;
+        p.dn = (R)(rid - dist);
+        p.vx = (R)a0.x;
+        p.vy = (R)a0.y;
+        p.vz = (R)a1.x;
+        p.rwx = ri * (R)a1.y;
+        p.rwy = ri * (R)a2.x;
+        p.rwz = ri * (R)a2.y;
+        p.rs = ri;
+        p.ms = mass_i;
+    }
+    return p;
+}
+
+// Tangential displacement carried by the pair with partner id `pid` in the
+// previous step's row `orw` of the particle; zero for a new contact.  Returns
+// whether the pair was found.  Rows of the split path are sorted by partner
+// id, which ends the search early; rows of the fused path are in the order
+// the candidates were visited.
+template <bool SORTED>
+__device__ __forceinline__ bool history_of(uint2 orw, uint32_t pid,
+                                           const uint32_t* __restrict__ tab_pid_old,
+                                           const double* __restrict__ tab_dt_old, uint64_t cap,
+                                           double& dtx, double& dty, double& dtz) {
+    dtx = dty = dtz = 0.0;
+    for (uint32_t k = orw.x; k < orw.x + orw.y; ++k) {
+        const uint32_t pk = tab_pid_old[k];
+        if (pk == pid) {
+            dtx = tab_dt_old[k];
+            dty = tab_dt_old[(size_t)cap + k];
+            dtz = tab_dt_old[2 * (size_t)cap + k];
+            return true;
+        }
+        if (SORTED && pk > pid) break;
+    }
+    return false;
+}
+
+// A tile whose job is not running: keys that keep every position of the
+// tile in place; a finished job's state is carried over into the buffer
+// written.
+__device__ __forceinline__ void idle_tile(const PoolView& P, const Job* __restrict__ jobs,
+                                          uint32_t tile, uint32_t jb, int t,
+                                          const double4* __restrict__ xr_x,
+                                          const double2* __restrict__ vw,
+                                          const uint8_t* __restrict__ mat,
+                                          double4* __restrict__ xr_b, double2* __restrict__ vw_b,
+                                          uint8_t* __restrict__ mat_b,
+                                          const uint32_t* __restrict__ perm,
+                                          uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                          uint32_t* __restrict__ oldkeys, bool movers) {
+    const uint32_t p0 = tile * TILE, ns = P.ns;
+    keys[p0 + t] = P.tile_key[tile] | P.lmask;
+    vals[p0 + t] = p0 + t;
+    if (movers) oldkeys[p0 + t] = P.tile_key[tile] | P.lmask;
+    if (jb != NO_JOB) {
+        const uint32_t i = p0 + t;
+        if (i < jobs[jb].p0 + jobs[jb].n) {
+            const uint32_t q = perm[i];
+            xr_b[i] = xr_x[q];
+            vw_b[i] = vw[q];
+            vw_b[ns + i] = vw[ns + q];
+            vw_b[2 * (size_t)ns + i] = vw[2 * (size_t)ns + q];
+            if (mat_b) mat_b[i] = mat[q];
+        }
+    }
+}
+
+// The end of a step for the TILE particles of a running tile, called by every
+// lane of the workgroup: churn counters (and, when `m` is given, the contact
+// count) into the tile's own slot; per-particle totals, gravity and the
+// semi-implicit Euler update in FP64 (section 3.4, "ForceGravity" and
+// "Integrate") into the buffer written; the new cell key ("CalcHash"); the
+// cell-change list.  With clear_cells, the first particle of each old cell
+// also empties that cell's bounds (the reorder writes those of the new order).
+template <typename R>
+__device__ __forceinline__ void finish_tile(
+    const PoolView& P, const Geo& G, const MatTable* __restrict__ mt, uint32_t tile, uint32_t jb,
+    int t, uint32_t i, uint32_t n, const double4& a, const double2& a0, const double2& a1,
+    const double2& a2, int mi, const R* acc, uint32_t matched, uint32_t old, const uint32_t* m,
+    double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
+    uint2* __restrict__ cells, bool clear_cells, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ vals, R* __restrict__ fo, uint32_t* __restrict__ oldkeys,
+    uint2* __restrict__ movers) {
+    __shared__ uint32_t s_red[6];
+    const uint32_t ns = P.ns;
+    Status* st = P.st;
+    {
+        uint32_t mv = matched, ov = old, cv = m ? *m : 0u;
+        for (int o = 32; o > 0; o >>= 1) {
+            mv += __shfl_down(mv, o, 64);
+            ov += __shfl_down(ov, o, 64);
+            if (m) cv += __shfl_down(cv, o, 64);
+        }
+        if ((t & 63) == 0) {
+            s_red[3 * (t >> 6)] = mv;
+            s_red[3 * (t >> 6) + 1] = ov;
+            s_red[3 * (t >> 6) + 2] = cv;
+        }
+        __syncthreads();
+        if (t == 0) {
+            P.ts[tile].matched_step = s_red[0] + s_red[3];
+            P.ts[tile].old_step = s_red[1] + s_red[4];
+            if (m) P.ts[tile].m_step = s_red[2] + s_red[5];
+        }
+    }
+    bool moved = false;
+    uint32_t newkey = 0;
+    if (i < n) {
+        const double r = (double)meta_r(a.w);
+        const double mass = mt->mass_pref[mi] * r * r * r;
+        const double I = 0.4 * mass * r * r;
+        const double Fx = (double)acc[0] + mass * G.g[0];
+        const double Fy = (double)acc[1] + mass * G.g[1];
+        const double Fz = (double)acc[2] + mass * G.g[2];
+        double vx = a0.x + G.dt * Fx / mass;
+        double vy = a0.y + G.dt * Fy / mass;
+        double vz = a1.x + G.dt * Fz / mass;
+        double x = a.x + G.dt * vx;
+        double y = a.y + G.dt * vy;
+        double z = a.z + G.dt * vz;
+        const double wx = a1.y + G.dt * (double)acc[3] / I;
+        const double wy = a2.x + G.dt * (double)acc[4] / I;
+        const double wz = a2.y + G.dt * (double)acc[5] / I;
+        if (G.periodic & 2u) {
+            if (y >= G.hi[1]) {
+                y -= G.L[1];
+                x -= G.le_shift_next;
+                vx -= G.le_dv;
+            } else if (y < G.lo[1]) {
+                y += G.L[1];
+                x += G.le_shift_next;
+                vx += G.le_dv;
+            }
+        }
+        // bounded wraps: a non-finite coordinate stays non-finite and is flagged
+        if (G.periodic & 1u) {
+            for (int k = 0; k < 4 && x >= G.hi[0]; ++k) x -= G.L[0];
+            for (int k = 0; k < 4 && x < G.lo[0]; ++k) x += G.L[0];
+        }
+        if (G.periodic & 4u) {
+            for (int k = 0; k < 4 && z >= G.hi[2]; ++k) z -= G.L[2];
+            for (int k = 0; k < 4 && z < G.lo[2]; ++k) z += G.L[2];
+        }
+        const bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) &&
+                            isfinite(vy) && isfinite(vz) && isfinite(wx) && isfinite(wy) &&
+                            isfinite(wz);
+        if (!finite) atomicOr(&P.job_fail[jb], 1u);
+        xr_b[i] = make_double4(x, y, z, a.w);
+        vw_b[i] = make_double2(vx, vy);
+        vw_b[ns + i] = make_double2(vz, wx);
+        vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
+        if (mat_b) mat_b[i] = (uint8_t)mi;
+        newkey = P.tile_key[tile] | cell_key(G, x, y, z);
+        keys[i] = newkey;
+        vals[i] = i;
+        if (fo) {
+            fo[i] = (R)Fx;
+            fo[ns + i] = (R)Fy;
+            fo[2 * (size_t)ns + i] = (R)Fz;
+            fo[3 * (size_t)ns + i] = acc[3];
+            fo[4 * (size_t)ns + i] = acc[4];
+            fo[5 * (size_t)ns + i] = acc[5];
+        }
+        const uint32_t okey = cell_key(G, a.x, a.y, a.z);
+        if (clear_cells) {
+            const uint32_t lin = key_lin(G, okey);
+            if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
+        }
+        if (movers) {
+            const uint32_t oldkey = P.tile_key[tile] | okey;
+            oldkeys[i] = oldkey;
+            moved = newkey != oldkey;
+        }
+    }
+    if (movers) {
+        // the particles that changed cell join the step's mover list: one
+        // reservation per workgroup that has any
+        __shared__ uint32_t s_mv[2], s_mvbase;
+        const int lane = t & 63, w = t >> 6;
+        const unsigned long long bal = __ballot(moved);
+        if (lane == 0) s_mv[w] = (uint32_t)__popcll(bal);
+        __syncthreads();
+        if (t == 0) {
+            const uint32_t tot = s_mv[0] + s_mv[1];
+            uint32_t b = 0;
+            if (tot) {
+                b = atomicAdd(&st->movers, tot);
+                if (b + tot > MAX_MOVERS) {
+                    atomicOr(&st->err, ERR_MOVERS);
+                    b = 0xFFFFFFFFu;
+                }
+            }
+            s_mvbase = b;
+        }
+        __syncthreads();
+        if (moved && s_mvbase != 0xFFFFFFFFu) {
+            const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            movers[s_mvbase + (w ? s_mv[0] : 0u) + rank] = make_uint2(newkey, i);
+        }
+    }
+}
+
+// Split path, second loop (section 3.4): one lane per compacted contact of
+// the tile.  Velocities come through the permutation, history is matched by
+// partner id, the contact law runs, and each particle then adds its own
+// contacts in row order (ascending partner id, faces last) from LDS.
 template <typename R>
 __global__ __launch_bounds__(TILE) void k_force(
     const double4* __restrict__ xr, const double4* __restrict__ xr_x,
@@ -612,7 +926,6 @@ __global__ __launch_bounds__(TILE) void k_force(
     __shared__ R s_f[6][TILE];
     __shared__ uint8_t s_mat[TILE];
     __shared__ uint32_t s_base, s_total, s_flag;
-    __shared__ uint32_t s_red[4];
     Status* st = P.st;
     if (skip_if_error(st, &s_flag)) return;
 
@@ -623,22 +936,8 @@ __global__ __launch_bounds__(TILE) void k_force(
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
     if (!Jp) {
-        // not running: keys that keep every position of the tile in place;
-        // a finished job's state is carried over into the buffer written
-        keys[p0 + t] = P.tile_key[tile] | P.lmask;
-        vals[p0 + t] = p0 + t;
-        if (movers) oldkeys[p0 + t] = P.tile_key[tile] | P.lmask;
-        if (jb != NO_JOB) {
-            const uint32_t i = p0 + t;
-            if (i < jobs[jb].p0 + jobs[jb].n) {
-                const uint32_t q = perm[i];
-                xr_b[i] = xr_x[q];
-                vw_b[i] = vw[q];
-                vw_b[ns + i] = vw[ns + q];
-                vw_b[2 * (size_t)ns + i] = vw[2 * (size_t)ns + q];
-                if (mat_b) mat_b[i] = mat[q];
-            }
-        }
+        idle_tile(P, jobs, tile, jb, t, xr_x, vw, mat, xr_b, vw_b, mat_b, perm, keys, vals, oldkeys,
+                  movers != nullptr);
         return;
     }
     const Job& J = *Jp;
@@ -689,101 +988,19 @@ __global__ __launch_bounds__(TILE) void k_force(
         if (q < total) {
             const int o = owner_of(s_excl, q);
             const uint32_t g = base + q;
-            const uint32_t code = col_j[g];
             const double4 a = s_x[o];
-            const double2 a0 = s_vw[0][o], a1 = s_vw[1][o], a2 = s_vw[2][o];
             const int mi = s_mat[o];
-            const R ri = (R)meta_r(a.w);
-            const double rid = (double)meta_r(a.w);
-            const R mass_i = (R)(mt->mass_pref[mi] * rid * rid * rid);
-            R nx, ny, nz, dn, vx, vy, vz, rwx, rwy, rwz, rs, ms;
-            int mj;
-            uint32_t pid_j;
-            if (code < FACE) {
-                const uint32_t j = code;
-                const double4 b = xr[j];
-                const uint32_t qj = perm[j];
-                const double2 b0 = vw[qj], b1 = vw[ns + qj], b2 = vw[2 * (size_t)ns + qj];
-                mj = mat ? mat[qj] : 0;
-                pid_j = meta_pid(b.w);
-                const double rjd = (double)meta_r(b.w);
-                const R rj = (R)meta_r(b.w);
-                double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                int ky = 0;
-                if (G.periodic) {
-                    double Sx, Sy, Sz;
-                    image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
-                    dx = dx + Sx;
-                    dy = dy + Sy;
-                    dz = dz + Sz;
-                }
-                const double d2 = dx * dx + dy * dy + dz * dz;
-                const double s = rid + rjd;
-                if (sizeof(R) == 8) {
-                    const double d = sqrt(d2);
-                    nx = (R)(dx / d);
-                    ny = (R)(dy / d);
-                    nz = (R)(dz / d);
-                    dn = (R)(s - d);
-                } else {
-                    // overlap from (s^2 - d^2) / (s + d): the subtraction in FP64
-                    // avoids the cancellation of s - d in FP32
-                    const float d32 = sqrtf((float)d2);
-                    const float inv = 1.0f / d32;
-                    nx = (R)((float)dx * inv);
-                    ny = (R)((float)dy * inv);
-                    nz = (R)((float)dz * inv);
-                    dn = (R)((float)(s * s - d2) / ((float)s + d32));
-                }
-                vx = (R)((a0.x - b0.x) - (double)ky * G.le_dv);
-                vy = (R)(a0.y - b0.y);
-                vz = (R)(a1.x - b1.x);
-                rwx = ri * (R)a1.y + rj * (R)b1.y;
-                rwy = ri * (R)a2.x + rj * (R)b2.x;
-                rwz = ri * (R)a2.y + rj * (R)b2.y;
-                rs = ri * rj / (ri + rj);
-                const R mass_j = (R)(mt->mass_pref[mj] * rjd * rjd * rjd);
-                ms = mass_i * mass_j / (mass_i + mass_j);
-            } else {
-                const int f = (int)(code - FACE), ax = f >> 1;
-                pid_j = code;
-                mj = mi;
-                const double p = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
-                const double dist = (f & 1) ? G.hi[ax] - p : p - G.lo[ax];
-                const R sg = (f & 1) ? (R)1 : (R)-1;
-                nx = ax == 0 ? sg : (R)0;
-                ny = ax == 1 ? sg : (R)0;
-                nz = ax == 2 ? sg : (R)0;
-                dn = (R)(rid - dist);
-                vx = (R)a0.x;
-                vy = (R)a0.y;
-                vz = (R)a1.x;
-                rwx = ri * (R)a1.y;
-                rwy = ri * (R)a2.x;
-                rwz = ri * (R)a2.y;
-                rs = ri;
-                ms = mass_i;
-            }
-            // history: the previous step's row of this particle, sorted by partner id
-            double dtx = 0.0, dty = 0.0, dtz = 0.0;
-            const uint2 orw = s_old[o];
-            for (uint32_t k = orw.x; k < orw.x + orw.y; ++k) {
-                const uint32_t pk = tab_pid_old[k];
-                if (pk == pid_j) {
-                    dtx = tab_dt_old[k];
-                    dty = tab_dt_old[(size_t)cap + k];
-                    dtz = tab_dt_old[2 * (size_t)cap + k];
-                    ++matched;
-                    break;
-                }
-                if (pk > pid_j) break;
-            }
-            const int pr = mi * MAXMAT + mj;
+            const PairTerms<R> p = pair_terms<R>(G, mt, col_j[g], a, s_vw[0][o], s_vw[1][o],
+                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns);
+            double dtx, dty, dtz;
+            matched += history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
+                                        dtz) ? 1u : 0u;
+            const int pr = mi * MAXMAT + p.mj;
             R F[3], T[3];
-            contact_law<R>(nx, ny, nz, dn, vx, vy, vz, rwx, rwy, rwz, dtx, dty, dtz, rs, ms, ri,
-                           (R)mt->kn_pref[pr], (R)mt->kt_pref[pr], (R)mt->alpha[pr],
-                           (R)mt->mu[pr], G.dt, F, T);
-            tab_pid_new[g] = pid_j;
+            contact_law<R>(p.nx, p.ny, p.nz, p.dn, p.vx, p.vy, p.vz, p.rwx, p.rwy, p.rwz, dtx, dty,
+                           dtz, p.rs, p.ms, (R)meta_r(a.w), (R)mt->kn_pref[pr],
+                           (R)mt->kt_pref[pr], (R)mt->alpha[pr], (R)mt->mu[pr], G.dt, F, T);
+            tab_pid_new[g] = p.pid;
             tab_dt_new[g] = dtx;
             tab_dt_new[(size_t)cap + g] = dty;
             tab_dt_new[2 * (size_t)cap + g] = dtz;
@@ -804,123 +1021,201 @@ __global__ __launch_bounds__(TILE) void k_force(
         }
         __syncthreads();
     }
+    finish_tile<R>(P, G, mt, tile, jb, t, i, n, s_x[t], s_vw[0][t], s_vw[1][t], s_vw[2][t],
+                   s_mat[t], acc, matched, (i < n) ? orow.y : 0u, nullptr, xr_b, vw_b, mat_b,
+                   cells, true, keys, vals, fo, oldkeys, movers);
+}
 
-    // churn counters into this tile's own slot
-    {
-        uint32_t mv = matched, ov = (i < n) ? orow.y : 0u;
-        for (int o = 32; o > 0; o >>= 1) {
-            mv += __shfl_down(mv, o, 64);
-            ov += __shfl_down(ov, o, 64);
-        }
-        if ((t & 63) == 0) {
-            s_red[2 * (t >> 6)] = mv;
-            s_red[2 * (t >> 6) + 1] = ov;
-        }
-        __syncthreads();
-        if (t == 0) {
-            P.ts[tile].matched_step = s_red[0] + s_red[2];
-            P.ts[tile].old_step = s_red[1] + s_red[3];
-        }
+// ------------------------------------------------------------------ fused
+// The single loop the paper starts from (section 3.4, Algorithm 1 before the
+// split), kept as an ablation of the split path: one lane per particle walks
+// its candidates exactly as the detect kernel does and, for every partner it
+// touches, matches the history, runs the contact law at once and adds the
+// force.  Lanes of a wavefront that find a contact run the contact law while
+// the others wait: the divergence the split removes.  The particle's
+// contacts go to its own slab of `slots` entries in the tile's region of the
+// contact table, in the order they were found (faces last), and the
+// per-particle sums follow that order.  Cell bounds are only read here (other
+// workgroups may still be walking them); k_clear_cells empties the old ones
+// afterwards.
+template <typename R, bool PER>
+__global__ __launch_bounds__(TILE) void k_fused(
+    PoolView P, const Job* __restrict__ jobs, const double4* __restrict__ xr,
+    const float4* __restrict__ xf, const double4* __restrict__ xr_x,
+    const double2* __restrict__ vw, const uint8_t* __restrict__ mat, double4* __restrict__ xr_b,
+    double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b, uint2* __restrict__ rows,
+    uint32_t* __restrict__ col_j, const uint2* __restrict__ rows_old,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ tab_pid_old,
+    const double* __restrict__ tab_dt_old, uint32_t* __restrict__ tab_pid_new,
+    double* __restrict__ tab_dt_new, uint64_t cap, uint32_t slots,
+    const uint2* __restrict__ cells, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    R* __restrict__ fo, uint32_t* __restrict__ oldkeys, uint2* __restrict__ movers) {
+    static_assert(DTILE == TILE, "the candidate ranges use the detect tile layout");
+    constexpr int NWIN = PER ? 18 : 9;
+    __shared__ uint2 s_win[(NWIN + 1) * TILE];
+    __shared__ uint32_t s_flag;
+    Status* st = P.st;
+    if (skip_if_error(st, &s_flag)) return;
+
+    const int t = threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t p0 = tile * TILE;
+    const uint32_t ns = P.ns;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) {
+        idle_tile(P, jobs, tile, jb, t, xr_x, vw, mat, xr_b, vw_b, mat_b, perm, keys, vals, oldkeys,
+                  movers != nullptr);
+        return;
     }
-    bool moved = false;
-    uint32_t newkey = 0;
-    if (i < n) {
-        // per-particle totals, gravity, semi-implicit Euler (FP64)
-        const double4 a = s_x[t];
-        const double2 a0 = s_vw[0][t], a1 = s_vw[1][t], a2 = s_vw[2][t];
-        const int mi = s_mat[t];
-        const double r = (double)meta_r(a.w);
-        const double m = mt->mass_pref[mi] * r * r * r;
-        const double I = 0.4 * m * r * r;
-        const double Fx = (double)acc[0] + m * G.g[0];
-        const double Fy = (double)acc[1] + m * G.g[1];
-        const double Fz = (double)acc[2] + m * G.g[2];
-        double vx = a0.x + G.dt * Fx / m;
-        double vy = a0.y + G.dt * Fy / m;
-        double vz = a1.x + G.dt * Fz / m;
-        double x = a.x + G.dt * vx;
-        double y = a.y + G.dt * vy;
-        double z = a.z + G.dt * vz;
-        const double wx = a1.y + G.dt * (double)acc[3] / I;
-        const double wy = a2.x + G.dt * (double)acc[4] / I;
-        const double wz = a2.y + G.dt * (double)acc[5] / I;
-        if (G.periodic & 2u) {
-            if (y >= G.hi[1]) {
-                y -= G.L[1];
-                x -= G.le_shift_next;
-                vx -= G.le_dv;
-            } else if (y < G.lo[1]) {
-                y += G.L[1];
-                x += G.le_shift_next;
-                vx += G.le_dv;
-            }
-        }
-        // bounded wraps: a non-finite coordinate stays non-finite and is flagged
-        if (G.periodic & 1u) {
-            for (int k = 0; k < 4 && x >= G.hi[0]; ++k) x -= G.L[0];
-            for (int k = 0; k < 4 && x < G.lo[0]; ++k) x += G.L[0];
-        }
-        if (G.periodic & 4u) {
-            for (int k = 0; k < 4 && z >= G.hi[2]; ++k) z -= G.L[2];
-            for (int k = 0; k < 4 && z < G.lo[2]; ++k) z += G.L[2];
-        }
-        const bool finite = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(vx) &&
-                            isfinite(vy) && isfinite(vz) && isfinite(wx) && isfinite(wy) &&
-                            isfinite(wz);
-        if (!finite) atomicOr(&P.job_fail[jb], 1u);
-        xr_b[i] = make_double4(x, y, z, a.w);
-        vw_b[i] = make_double2(vx, vy);
-        vw_b[ns + i] = make_double2(vz, wx);
-        vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
-        if (mat_b) mat_b[i] = (uint8_t)mi;
-        newkey = P.tile_key[tile] | cell_key(G, x, y, z);
-        keys[i] = newkey;
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const MatTable* __restrict__ mt = P.mats + J.mat;
+    const uint32_t i = p0 + t;
+    const uint32_t n = J.p0 + J.n;
+    if (i >= n) {
+        keys[i] = P.tile_key[tile] | P.lmask;
         vals[i] = i;
-        if (fo) {
-            fo[i] = (R)Fx;
-            fo[ns + i] = (R)Fy;
-            fo[2 * (size_t)ns + i] = (R)Fz;
-            fo[3 * (size_t)ns + i] = acc[3];
-            fo[4 * (size_t)ns + i] = acc[4];
-            fo[5 * (size_t)ns + i] = acc[5];
-        }
-        // the first particle of its (old) cell empties the cell's bounds; the
-        // reorder kernel writes the bounds of the new order
-        const uint32_t okey = cell_key(G, a.x, a.y, a.z);
-        const uint32_t lin = key_lin(G, okey);
-        if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
-        if (movers) {
-            const uint32_t oldkey = P.tile_key[tile] | okey;
-            oldkeys[i] = oldkey;
-            moved = newkey != oldkey;
-        }
+        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
     }
-    if (movers) {
-        // the particles that changed cell join the step's mover list: one
-        // reservation per workgroup that has any
-        __shared__ uint32_t s_mv[2], s_mvbase;
-        const int lane = t & 63, w = t >> 6;
-        const unsigned long long bal = __ballot(moved);
-        if (lane == 0) s_mv[w] = (uint32_t)__popcll(bal);
-        __syncthreads();
-        if (t == 0) {
-            const uint32_t tot = s_mv[0] + s_mv[1];
-            uint32_t b = 0;
-            if (tot) {
-                b = atomicAdd(&st->movers, tot);
-                if (b + tot > MAX_MOVERS) {
-                    atomicOr(&st->err, ERR_MOVERS);
-                    b = 0xFFFFFFFFu;
-                }
+    R acc[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t matched = 0, cnt = 0;
+    uint2 orow = make_uint2(0, 0);
+    double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0;
+    int mi = 0;
+    const uint64_t slab = ((uint64_t)tile * TILE + (uint64_t)t) * slots;
+    if (i < n) {
+        const uint32_t q = perm[i];
+        orow = rows_old[q];
+        a = xr[i];
+        a0 = vw[q];
+        a1 = vw[ns + q];
+        a2 = vw[2 * (size_t)ns + q];
+        mi = mat ? mat[q] : 0;
+        const double rid = (double)meta_r(a.w);
+        const R ri = (R)meta_r(a.w);
+        // a contact found: history, contact law and sum at once
+        auto contact = [&](uint32_t code) {
+            if (cnt < slots) {
+                const uint64_t g = slab + cnt;
+                const PairTerms<R> p =
+                    pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr, vw, mat, perm, ns);
+                double dtx, dty, dtz;
+                matched += history_of<false>(orow, p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
+                                             dtz) ? 1u : 0u;
+                const int pr = mi * MAXMAT + p.mj;
+                R F[3], T[3];
+                contact_law<R>(p.nx, p.ny, p.nz, p.dn, p.vx, p.vy, p.vz, p.rwx, p.rwy, p.rwz, dtx,
+                               dty, dtz, p.rs, p.ms, ri, (R)mt->kn_pref[pr], (R)mt->kt_pref[pr],
+                               (R)mt->alpha[pr], (R)mt->mu[pr], G.dt, F, T);
+                acc[0] += F[0];
+                acc[1] += F[1];
+                acc[2] += F[2];
+                acc[3] += T[0];
+                acc[4] += T[1];
+                acc[5] += T[2];
+                col_j[g] = code;
+                tab_pid_new[g] = p.pid;
+                tab_dt_new[g] = dtx;
+                tab_dt_new[(size_t)cap + g] = dty;
+                tab_dt_new[2 * (size_t)cap + g] = dtz;
             }
-            s_mvbase = b;
-        }
-        __syncthreads();
-        if (moved && s_mvbase != 0xFFFFFFFFu) {
-            const uint32_t rank = (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-            movers[s_mvbase + (w ? s_mv[0] : 0u) + rank] = make_uint2(newkey, i);
-        }
+            ++cnt;
+        };
+        // the exact FP64 predicate on a candidate that passed the pre-filter
+        auto touches = [&](uint32_t c) {
+            const double4 b = xr[c];
+            double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+            if (PER) {
+                double Sx, Sy, Sz;
+                int ky;
+                image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                dx = dx + Sx;
+                dy = dy + Sy;
+                dz = dz + Sz;
+            }
+            return touching(dx, dy, dz, rid + (double)meta_r(b.w));
+        };
+        const uint32_t nw = candidate_ranges<PER>(G, a, rid, cells + J.cell_base, s_win, t);
+        const PreFilter<PER> pre(G, a, J.margin);
+        constexpr uint32_t NONE = 0xFFFFFFFFu;
+        if (nw > 0) {
+            // the detect kernel's walk: branch-free over the ranges, a
+            // sentinel range at the end, four records in flight
+            s_win[nw * TILE + t] = make_uint2(NONE, NONE);
+            uint32_t w = 0;
+            uint2 rg = s_win[t];
+            uint2 rn = s_win[TILE + t];
+            uint32_t j = rg.x;
+            auto next = [&]() -> uint32_t {
+                const uint32_t c = j;
+                const bool live = c != NONE;
+                const bool sw = live && c + 1 == rg.y;
+                j = !live ? NONE : (sw ? rn.x : c + 1);
+                rg.y = sw ? rn.y : rg.y;
+                w += sw ? 1u : 0u;
+                rn = s_win[min(w + 1, nw) * TILE + t];
+                return c;
+            };
+            uint32_t j0 = next(), j1 = next(), j2 = next(), j3 = next();
+            float4 q0 = xf[j0 < ns ? j0 : i], q1 = xf[j1 < ns ? j1 : i];
+            float4 q2 = xf[j2 < ns ? j2 : i], q3 = xf[j3 < ns ? j3 : i];
+#define DEM_FUSED_STEP(Q, JQ)                                       \
+    {                                                               \
+        if (JQ == NONE) break;                                      \
+        if (JQ != i && JQ < ns && pre(Q) && touches(JQ)) contact(JQ); \
+        JQ = next();                                                \
+        Q = xf[JQ < ns ? JQ : i];                                   \
     }
+            for (;;) {
+                DEM_FUSED_STEP(q0, j0)
+                DEM_FUSED_STEP(q1, j1)
+                DEM_FUSED_STEP(q2, j2)
+                DEM_FUSED_STEP(q3, j3)
+            }
+#undef DEM_FUSED_STEP
+        }
+        if (G.walls) {
+            for (int f = 0; f < 6; ++f) {
+                if (!(G.walls & (1u << f))) continue;
+                const int ax = f >> 1;
+                const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+                const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
+                if (dist < rid) contact(FACE + (uint32_t)f);
+            }
+        }
+        if (cnt > slots) {
+            // the slab is too small: the step is redone with wider slabs
+            atomicOr(&st->err, ERR_CAPACITY);
+            atomicMax(&st->need, cnt * (uint32_t)TILE);
+            cnt = 0;
+        }
+        rows[i] = make_uint2((uint32_t)slab, cnt);
+    }
+    finish_tile<R>(P, G, mt, tile, jb, t, i, n, a, a0, a1, a2, mi, acc, matched, orow.y, &cnt,
+                   xr_b, vw_b, mat_b, nullptr, false, keys, vals, fo, oldkeys, movers);
+}
+
+// After the fused kernel: the first particle of each cell of the order the
+// step started from empties that cell's bounds (the reorder writes those of
+// the new order).
+__global__ __launch_bounds__(TILE) void k_clear_cells(PoolView P, const Job* __restrict__ jobs,
+                                                      const double4* __restrict__ xr,
+                                                      uint2* __restrict__ cells) {
+    __shared__ uint32_t s_flag;
+    if (skip_if_error(P.st, &s_flag)) return;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) return;
+    const Geo& G = Jp->g;
+    const uint32_t i = tile * TILE + threadIdx.x;
+    if (i >= Jp->p0 + Jp->n) return;
+    const double4 a = xr[i];
+    uint2* c = cells + Jp->cell_base;
+    const uint32_t lin = key_lin(G, cell_key(G, a.x, a.y, a.z));
+    if (c[lin].x == i) c[lin] = make_uint2(0, 0);
 }
 
 // ------------------------------------------------------------ merge sort
@@ -1352,6 +1647,28 @@ void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X,
                            Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs,
                            oldkeys, movers);
+}
+
+void launch_fused(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
+                  uint2* rows, uint32_t* col_j, const uint2* rows_old, const uint32_t* perm,
+                  const uint32_t* tab_pid_old, const double* tab_dt_old, uint32_t* tab_pid_new,
+                  double* tab_dt_new, uint64_t cap, uint32_t slots, uint2* cells, uint32_t* keys,
+                  uint32_t* vals, void* fo, uint32_t* oldkeys, uint2* movers, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
+#define DEM_FUSED(R, PER)                                                                          \
+    hipLaunchKernelGGL((k_fused<R, PER>), dim3(nb), dim3(TILE), 0, s, P, P.jobs, S.xr, S.xf, X.xr, \
+                       X.vw, X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,  \
+                       tab_dt_old, tab_pid_new, tab_dt_new, cap, slots, cells, keys, vals,        \
+                       (R*)fo, oldkeys, movers)
+    const bool per = P.any_periodic;
+    if (fp64) {
+        if (per) DEM_FUSED(double, true); else DEM_FUSED(double, false);
+    } else {
+        if (per) DEM_FUSED(float, true); else DEM_FUSED(float, false);
+    }
+#undef DEM_FUSED
+    hipLaunchKernelGGL(k_clear_cells, dim3(nb), dim3(TILE), 0, s, P, P.jobs, S.xr, cells);
 }
 
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,

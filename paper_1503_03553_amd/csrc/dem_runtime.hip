@@ -361,6 +361,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
                        uint32_t slots, uint32_t flags, void* stream, dem_pool** out) {
     *out = nullptr;
     if (max_jobs < 1 || slots < 1) return DEM_EINVAL;
+    if (flags & ~(DEM_FLAG_NO_FORCE_OUTPUT | DEM_FLAG_RADIX_SORT | DEM_FLAG_FUSED))
+        return DEM_EINVAL;
     const uint64_t mt = std::max<uint64_t>(1, tiles_of(max_particles));
     if (mt * TILE > MAX_ENTRIES || mt * TILE * slots > MAX_ENTRIES) return DEM_EINVAL;
     dem_pool* s = new (std::nothrow) dem_pool();
@@ -843,17 +845,28 @@ dem_status enqueue_step(dem_pool* s, int o) {
         }
         slot = s->prof_used++;
     }
+    // the fused single loop replaces detect and force (the detect phase is
+    // then empty)
+    const bool fused = (s->flags & DEM_FLAG_FUSED) != 0;
     prof_record(s, slot, 0);
-    launch_detect(P, s->kmax, s->srt, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
+    if (!fused)
+        launch_detect(P, s->kmax, s->srt, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
     prof_record(s, slot, 1);
     prof_record(s, slot, 2);
     // the merge sort unless a recent step had too many cell changes
     const bool merge = s->radix_left == 0 && !(s->flags & DEM_FLAG_RADIX_SORT);
     if (s->radix_left) s->radix_left--;
-    launch_force(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev, s->tab_pid[o],
-                 s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals,
-                 (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo,
-                 merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr, s->stream);
+    void* fo = (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo;
+    if (fused)
+        launch_fused(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
+                     s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->slots,
+                     s->cells, s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
+                     merge ? s->movers : nullptr, s->stream);
+    else
+        launch_force(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
+                     s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells,
+                     s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
+                     merge ? s->movers : nullptr, s->stream);
     prof_record(s, slot, 3);
     prof_record(s, slot, 4);
     uint32_t *ko, *vo;

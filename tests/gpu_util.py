@@ -10,6 +10,7 @@ import sys
 
 import numpy as np
 
+import gen
 import oracle
 from paper_1503_03553_amd import PREC_FP64, PREC_MIXED, Sim
 
@@ -182,3 +183,47 @@ def trajectory_parity(scene, precision, steps=100, tol=1e-4, dt=None, chunk=None
         return out
     finally:
         g.close()
+
+
+def random_history(scene, seed, frac=0.8, scale=None):
+    """A plausible tangential history for most current contacts (and a few
+    stale pairs that no longer touch, which must be dropped)."""
+    i, j = oracle.contacts(scene, mode=1)
+    rng = np.random.default_rng(seed)
+    keep = rng.random(i.size) < frac
+    i, j = i[keep], j[keep]
+    if scale is None:
+        scale = 1e-3 * float(np.median(scene.r))
+    dt = rng.normal(0, scale, size=(i.size, 3))
+    # antisymmetric for particle pairs, as a real history is
+    idx = {(a, b): k for k, (a, b) in enumerate(zip(i.tolist(), j.tolist()))}
+    for (a, b), k in idx.items():
+        if b < FACE and (b, a) in idx and a > b:
+            dt[k] = -dt[idx[(b, a)]]
+    # stale entries
+    n = scene.n
+    si = rng.integers(0, n, 10).astype(np.uint32)
+    sj = ((si + 7) % n).astype(np.uint32)
+    pairs = set(zip(i.tolist(), j.tolist()))
+    extra = [(a, b) for a, b in zip(si.tolist(), sj.tolist()) if a != b and (a, b) not in pairs]
+    extra = list(dict.fromkeys(extra))
+    if extra:
+        ei = np.array([a for a, _ in extra], np.uint32)
+        ej = np.array([b for _, b in extra], np.uint32)
+        i = np.concatenate([i, ei])
+        j = np.concatenate([j, ej])
+        dt = np.concatenate([dt, rng.normal(0, scale, size=(len(extra), 3))])
+    return i.astype(np.uint32), j.astype(np.uint32), dt
+
+
+SCENES = {
+    "cluster64": lambda: gen.scene_cluster(seed=1, n_side=4, vel_sigma=0.2, polydisperse=True),
+    "random3000": lambda: gen.scene_random(seed=21, n=3000, phi=0.22, p_touch=0.7, vel_sigma=0.2),
+    "periodic1500": lambda: gen.scene_random(seed=22, n=1500, phi=0.22, p_touch=0.7, walls=0,
+                                             periodic=7, gravity=(0, 0, 0)),
+    "shear1500": lambda: gen.scene_random(seed=23, n=1500, phi=0.22, p_touch=0.7, walls=0,
+                                          periodic=7, gravity=(0, 0, 0), shear_rate=2000.0),
+    "mixedwall": lambda: gen.scene_random(seed=24, n=1200, phi=0.22, p_touch=0.7,
+                                          walls=gen.WALL_ALL & ~3, periodic=1),
+    "materials": lambda: gen.scene_random(seed=25, n=1000, phi=0.22, p_touch=0.7, n_materials=3),
+}
