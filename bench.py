@@ -106,29 +106,41 @@ def kernels_of(rows):
 
 # ------------------------------------------------------------ single sim
 def run_single(sc, precision, steps, warmup, stream, flags=0):
+    """Warm-up, then `steps` timed steps without instrumentation (the
+    throughput); then the same again from the same initial state with HIP
+    events at the phase boundaries (the per-kernel durations, over the same
+    steps)."""
     import torch
     from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, Sim
-    sim = Sim.from_scene(sc, precision=precision, stream=stream,
-                         flags=FLAG_NO_FORCE_OUTPUT | flags)
-    sim.step(warmup)
-    sim.sync()
-    info0 = sim.info()
-    sim.profile(True)
-    sim.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    sim.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sim.profile_read()
-    info1 = sim.info()
-    sim.close()
+    out = {}
+    for profiled in (False, True):
+        sim = Sim.from_scene(sc, precision=precision, stream=stream,
+                             flags=FLAG_NO_FORCE_OUTPUT | flags)
+        sim.step(warmup)
+        sim.sync()
+        info0 = sim.info()
+        if profiled:
+            sim.profile(True)
+            sim.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if profiled:
+            out["prof"] = sim.profile_read()
+            out["seconds_profiled"] = t1 - t0
+        else:
+            out["seconds"] = t1 - t0
+        info1 = sim.info()
+        sim.close()
     k = max(info1["steps_done"] - info0["steps_done"], 1)
-    return dict(seconds=t1 - t0, steps=steps, prof=prof, info=info1,
-                contacts=(info1["sum_contacts"] - info0["sum_contacts"]) / k,
-                contacts_old=(info1["sum_old"] - info0["sum_old"]) / k,
-                matched=(info1["sum_matched"] - info0["sum_matched"]) / k)
+    out.update(steps=steps, info=info1,
+               contacts=(info1["sum_contacts"] - info0["sum_contacts"]) / k,
+               contacts_old=(info1["sum_old"] - info0["sum_old"]) / k,
+               matched=(info1["sum_matched"] - info0["sum_matched"]) / k)
+    return out
 
 
 # -------------------------------------------------------------- ablation
@@ -345,6 +357,9 @@ def headline(a, sc, stream, log):
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(mixed["seconds"] / a.steps * 1e3, 4),
+        # a second pass of as many steps with HIP events at the phase
+        # boundaries gives the kernel durations below
+        "ms_per_step_with_events": round(mixed["seconds_profiled"] / a.steps * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -371,6 +386,8 @@ def headline(a, sc, stream, log):
         out["fp64_plain"] = {"value": round(n * a.steps / f64["seconds"], 1),
                              "unit": "particle-steps/s",
                              "ms_per_step": round(f64["seconds"] / a.steps * 1e3, 4),
+                             "ms_per_step_with_events":
+                                 round(f64["seconds_profiled"] / a.steps * 1e3, 4),
                              "roofline": roofline_of(rows64, "double"),
                              "kernels": kernels_of(rows64)}
 

@@ -57,8 +57,9 @@ struct Buf {
     size_t bytes = 0;
 };
 
+// Phase boundaries of one step: phase p runs between events p and p + 1.
 struct ProfEv {
-    hipEvent_t e[2 * DEM_NPHASE];
+    hipEvent_t e[DEM_NPHASE + 1];
 };
 
 struct Layout {
@@ -353,7 +354,7 @@ void destroy_pool(dem_pool* s) {
     for (auto& b : s->bufs) (void)hipFree(b.p);
     s->bufs.clear();
     for (auto& pe : s->prof_ev)
-        for (int q = 0; q < 2 * DEM_NPHASE; ++q) (void)hipEventDestroy(pe.e[q]);
+        for (int q = 0; q <= DEM_NPHASE; ++q) (void)hipEventDestroy(pe.e[q]);
     delete s;
 }
 
@@ -840,7 +841,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
     if (s->prof) {
         if (s->prof_used == s->prof_ev.size()) {
             ProfEv pe;
-            for (int q = 0; q < 2 * DEM_NPHASE; ++q) HIPCHK(hipEventCreate(&pe.e[q]));
+            for (int q = 0; q <= DEM_NPHASE; ++q) HIPCHK(hipEventCreate(&pe.e[q]));
             s->prof_ev.push_back(pe);
         }
         slot = s->prof_used++;
@@ -852,7 +853,6 @@ dem_status enqueue_step(dem_pool* s, int o) {
     if (!fused)
         launch_detect(P, s->kmax, s->srt, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
     prof_record(s, slot, 1);
-    prof_record(s, slot, 2);
     // the merge sort unless a recent step had too many cell changes
     const bool merge = s->radix_left == 0 && !(s->flags & DEM_FLAG_RADIX_SORT);
     if (s->radix_left) s->radix_left--;
@@ -867,8 +867,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells,
                      s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
                      merge ? s->movers : nullptr, s->stream);
-    prof_record(s, slot, 3);
-    prof_record(s, slot, 4);
+    prof_record(s, slot, 2);
     uint32_t *ko, *vo;
     if (merge) {
         launch_merge_sort(P, s->keys, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, s->vals_t,
@@ -880,10 +879,9 @@ dem_status enqueue_step(dem_pool* s, int o) {
                           s->lb + seg_bits(s->segs.size()), s->tile_hist, s->digit_tot, &ko, &vo,
                           s->st, s->stream);
     }
-    prof_record(s, slot, 5);
-    prof_record(s, slot, 6);
+    prof_record(s, slot, 3);
     launch_reorder(P, s->jobs_d, s->max_jobs, ko, vo, Y, s->srt, s->prev, s->cells, s->stream);
-    prof_record(s, slot, 7);
+    prof_record(s, slot, 4);
     HIPCHK(hipGetLastError());
     return DEM_OK;
 }
@@ -1390,7 +1388,7 @@ static dem_status profile_read_impl(dem_pool* s, double* ms, uint64_t* launches)
     for (size_t k = 0; k < s->prof_used; ++k) {
         for (int p = 0; p < DEM_NPHASE; ++p) {
             float t = 0.0f;
-            if (hipEventElapsedTime(&t, s->prof_ev[k].e[2 * p], s->prof_ev[k].e[2 * p + 1]) == hipSuccess) {
+            if (hipEventElapsedTime(&t, s->prof_ev[k].e[p], s->prof_ev[k].e[p + 1]) == hipSuccess) {
                 ms[p] += t;
                 launches[p] += 1;
             }
