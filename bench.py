@@ -145,19 +145,21 @@ def run_single(sc, precision, steps, warmup, stream, flags=0):
 
 # -------------------------------------------------------------- ablation
 def run_ablation(sizes, steps, warmup, stream, log):
-    """The fused single loop against the split path (section 3.4; the
-    comparison of section 4) on the grid inputs of gen.config_ablation, in
-    mixed precision.  "collide" is the contact search plus the force kernel:
-    detect + force for the split path, the fused kernel plus the clearing of
-    the old cell bounds for the fused one."""
+    """The fused single loop (section 3.4; the comparison of section 4) and
+    the action-reaction variant (section 3.3) against the split path on the
+    grid inputs of gen.config_ablation, in mixed precision.  "collide" is the
+    contact search plus the force kernels: detect + force for the split path,
+    the fused kernel plus the clearing of the old cell bounds for the fused
+    one, detect + pair forces + sums for action-reaction."""
     import gen
-    from paper_1503_03553_amd import FLAG_FUSED, PREC_MIXED
+    from paper_1503_03553_amd import FLAG_ACTION_REACTION, FLAG_FUSED, PREC_MIXED
     rows = []
     for n in sizes:
         for regime in ("dense", "sparse"):
             sc = gen.config_ablation(n, regime)
             row = {"n": sc.n, "regime": regime}
-            for name, flag in (("split", 0), ("fused", FLAG_FUSED)):
+            for name, flag in (("split", 0), ("fused", FLAG_FUSED),
+                               ("action_reaction", FLAG_ACTION_REACTION)):
                 r = run_single(sc, PREC_MIXED, steps, warmup, stream, flags=flag)
                 ph = {p: ms / c * 1e3 for p, (ms, c) in r["prof"].items() if c}
                 row["contacts_per_particle"] = round(r["contacts"] / sc.n, 3)
@@ -168,6 +170,8 @@ def run_ablation(sizes, steps, warmup, stream, log):
                                                     row["split"]["collide_us"], 3)
             row["step_fused_over_split"] = round(row["fused"]["ms_per_step"] /
                                                  row["split"]["ms_per_step"], 3)
+            row["step_action_reaction_over_split"] = round(
+                row["action_reaction"]["ms_per_step"] / row["split"]["ms_per_step"], 3)
             log("ablation %s" % json.dumps(row))
             rows.append(row)
     return rows
@@ -378,6 +382,15 @@ def headline(a, sc, stream, log):
     step_time = sum(r["avg_us"] for r in rows.values()) * 1e-6
     out["step_roofline_frac"] = round(step_bytes / step_time / 1e9 / HBM_PEAK_GBS, 4)
 
+    from paper_1503_03553_amd import FLAG_ACTION_REACTION
+    ar = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_ACTION_REACTION)
+    rows_ar = phase_rows(ar["prof"], n, ar["contacts"], ar["contacts_old"], False,
+                         ar["info"]["key_bits"])
+    out["action_reaction"] = {"value": round(n * a.steps / ar["seconds"], 1),
+                              "unit": "particle-steps/s",
+                              "ms_per_step": round(ar["seconds"] / a.steps * 1e3, 4),
+                              "phases_us": {k: round(v["avg_us"], 2) for k, v in rows_ar.items()}}
+
     if not a.no_fp64:
         f64 = run_single(sc, PREC_FP64, a.steps, a.warmup, stream)
         rows64 = phase_rows(f64["prof"], n, f64["contacts"], f64["contacts_old"], True,
@@ -433,7 +446,8 @@ def run_others(a, out, sc, batch, serve_in, stream, log):
         sizes = [int(v) for v in a.ablation_sizes.split(",") if v]
         out["ablation_fused_vs_split"] = {
             "what": "collide = contact search + force kernels per step, mixed precision; "
-                    "fused = the single loop before the split of section 3.4",
+                    "fused = the single loop before the split of section 3.4; "
+                    "action_reaction = each pair's force once, applied to both",
             "steps": a.ablation_steps, "warmup": 5,
             "rows": run_ablation(sizes, a.ablation_steps, 5, stream, log)}
 

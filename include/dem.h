@@ -103,6 +103,13 @@ typedef struct {
                                        the split).  Same contact set; the per-particle
                                        sums follow the order the contacts were found
                                        instead of ascending partner id */
+#define DEM_FLAG_ACTION_REACTION 8u /* each particle pair's force computed once, by the
+                                       particle with the lower id, and applied with
+                                       opposite signs to both (the scheme section 3.3
+                                       avoids); sums stay in ascending partner id.  The
+                                       history keeps one displacement per pair;
+                                       dem_get_contacts reports the other direction as
+                                       its negative.  Not with DEM_FLAG_FUSED */
 
 /* Diagnostics of a simulation (dem_get_info). */
 typedef struct {

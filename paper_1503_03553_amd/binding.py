@@ -20,6 +20,7 @@ PREC_MIXED = 1
 FLAG_NO_FORCE_OUTPUT = 1
 FLAG_RADIX_SORT = 2
 FLAG_FUSED = 4
+FLAG_ACTION_REACTION = 8
 NPHASE = 4
 PHASES = ("detect", "force", "sort", "reorder")
 

@@ -769,8 +769,8 @@ __device__ __forceinline__ void idle_tile(const PoolView& P, const Job* __restri
 }
 
 // The end of a step for the TILE particles of a running tile, called by every
-// lane of the workgroup: churn counters (and, when `m` is given, the contact
-// count) into the tile's own slot; per-particle totals, gravity and the
+// lane of the workgroup: with `churn`, the churn counters (and, when `m` is
+// given, the contact count) into the tile's own slot; per-particle totals, gravity and the
 // semi-implicit Euler update in FP64 (section 3.4, "ForceGravity" and
 // "Integrate") into the buffer written; the new cell key ("CalcHash"); the
 // cell-change list.  With clear_cells, the first particle of each old cell
@@ -779,15 +779,15 @@ template <typename R>
 __device__ __forceinline__ void finish_tile(
     const PoolView& P, const Geo& G, const MatTable* __restrict__ mt, uint32_t tile, uint32_t jb,
     int t, uint32_t i, uint32_t n, const double4& a, const double2& a0, const double2& a1,
-    const double2& a2, int mi, const R* acc, uint32_t matched, uint32_t old, const uint32_t* m,
-    double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
+    const double2& a2, int mi, const R* acc, bool churn, uint32_t matched, uint32_t old,
+    const uint32_t* m, double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
     uint2* __restrict__ cells, bool clear_cells, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ vals, R* __restrict__ fo, uint32_t* __restrict__ oldkeys,
     uint2* __restrict__ movers) {
     __shared__ uint32_t s_red[6];
     const uint32_t ns = P.ns;
     Status* st = P.st;
-    {
+    if (churn) {
         uint32_t mv = matched, ov = old, cv = m ? *m : 0u;
         for (int o = 32; o > 0; o >>= 1) {
             mv += __shfl_down(mv, o, 64);
@@ -1022,8 +1022,211 @@ __global__ __launch_bounds__(TILE) void k_force(
         __syncthreads();
     }
     finish_tile<R>(P, G, mt, tile, jb, t, i, n, s_x[t], s_vw[0][t], s_vw[1][t], s_vw[2][t],
-                   s_mat[t], acc, matched, (i < n) ? orow.y : 0u, nullptr, xr_b, vw_b, mat_b,
+                   s_mat[t], acc, true, matched, (i < n) ? orow.y : 0u, nullptr, xr_b, vw_b, mat_b,
                    cells, true, keys, vals, fo, oldkeys, movers);
+}
+
+// ------------------------------------------------------- action-reaction
+// Variant that computes each particle pair once (the scheme section 3.3
+// avoids): the particle with the lower id owns the pair.  First kernel: one
+// lane per compacted contact of the tile, as in the force kernel, but the
+// contact law runs only for owned entries (partner id above the particle's)
+// and faces.  The pair force F and n x F go to the entry's slot of `pf` (six
+// planes of cap values) for both particles' sums; every entry gets its
+// partner id, and the history table keeps the tangential displacement in the
+// owner's entry only (zero in the other).  The churn counters count an owned
+// pair that carried history twice, as both of its directed contacts did.
+template <typename R>
+__global__ __launch_bounds__(TILE) void k_pair_force(
+    const double4* __restrict__ xr, const double2* __restrict__ vw,
+    const uint8_t* __restrict__ mat, const uint2* __restrict__ rows,
+    const uint32_t* __restrict__ col_j, const uint2* __restrict__ rows_old,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ tab_pid_old,
+    const double* __restrict__ tab_dt_old, uint32_t* __restrict__ tab_pid_new,
+    double* __restrict__ tab_dt_new, uint64_t cap, R* __restrict__ pf, PoolView P,
+    const Job* __restrict__ jobs) {
+    __shared__ double4 s_x[TILE];
+    __shared__ double2 s_vw[3][TILE];
+    __shared__ uint2 s_old[TILE];
+    __shared__ uint32_t s_excl[TILE + 1];
+    __shared__ uint8_t s_mat[TILE];
+    __shared__ uint32_t s_base, s_total, s_flag;
+    __shared__ uint32_t s_red[4];
+    Status* st = P.st;
+    if (skip_if_error(st, &s_flag)) return;
+
+    const int t = threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t p0 = tile * TILE;
+    const uint32_t ns = P.ns;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) return;
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const MatTable* __restrict__ mt = P.mats + J.mat;
+    const uint32_t i = p0 + t;
+    const uint32_t n = J.p0 + J.n;
+    const uint32_t nt = (n - p0) < (uint32_t)TILE ? (n - p0) : (uint32_t)TILE;
+    uint2 row = make_uint2(0, 0);
+    uint2 orow = make_uint2(0, 0);
+    if (i < n) {
+        const uint32_t q = perm[i];
+        row = rows[i];
+        orow = rows_old[q];
+        s_x[t] = xr[i];
+        s_vw[0][t] = vw[q];
+        s_vw[1][t] = vw[ns + q];
+        s_vw[2][t] = vw[2 * (size_t)ns + q];
+        s_mat[t] = mat ? mat[q] : (uint8_t)0;
+    }
+    s_old[t] = orow;
+    if (t == 0) s_base = row.x;
+    if ((uint32_t)t == nt - 1) s_total = row.x + row.y;
+    __syncthreads();
+    const uint32_t base = s_base;
+    const uint32_t total = s_total - base;
+    s_excl[t] = (i < n) ? row.x - base : total;
+    if (t == 0) s_excl[TILE] = total;
+    __syncthreads();
+    if ((uint64_t)base + total > cap) {  // cannot happen after a clean detect
+        if (t == 0) atomicOr(&st->err, ERR_CAPACITY);
+        return;
+    }
+    uint32_t matched = 0;
+    for (uint32_t q = t; q < total; q += TILE) {
+        const int o = owner_of(s_excl, q);
+        const uint64_t g = (uint64_t)base + q;
+        const uint32_t code = col_j[g];
+        const double4 a = s_x[o];
+        uint32_t pid = code;
+        bool own = true;
+        if (code < FACE) {
+            pid = meta_pid(xr[code].w);
+            own = pid > meta_pid(a.w);
+        }
+        double dtx = 0.0, dty = 0.0, dtz = 0.0;
+        R F[3] = {0, 0, 0}, nF[3] = {0, 0, 0};
+        if (own) {
+            const int mi = s_mat[o];
+            const PairTerms<R> p = pair_terms<R>(G, mt, code, a, s_vw[0][o], s_vw[1][o],
+                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns);
+            if (history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty, dtz))
+                matched += code < FACE ? 2u : 1u;
+            const int pr = mi * MAXMAT + p.mj;
+            // with a unit radius the torque output is n x F itself
+            contact_law<R>(p.nx, p.ny, p.nz, p.dn, p.vx, p.vy, p.vz, p.rwx, p.rwy, p.rwz, dtx,
+                           dty, dtz, p.rs, p.ms, (R)1, (R)mt->kn_pref[pr], (R)mt->kt_pref[pr],
+                           (R)mt->alpha[pr], (R)mt->mu[pr], G.dt, F, nF);
+        }
+        tab_pid_new[g] = pid;
+        tab_dt_new[g] = dtx;
+        tab_dt_new[cap + g] = dty;
+        tab_dt_new[2 * cap + g] = dtz;
+        pf[g] = F[0];
+        pf[cap + g] = F[1];
+        pf[2 * cap + g] = F[2];
+        pf[3 * cap + g] = nF[0];
+        pf[4 * cap + g] = nF[1];
+        pf[5 * cap + g] = nF[2];
+    }
+    uint32_t mv = matched, ov = (i < n) ? orow.y : 0u;
+    for (int o = 32; o > 0; o >>= 1) {
+        mv += __shfl_down(mv, o, 64);
+        ov += __shfl_down(ov, o, 64);
+    }
+    if ((t & 63) == 0) {
+        s_red[2 * (t >> 6)] = mv;
+        s_red[2 * (t >> 6) + 1] = ov;
+    }
+    __syncthreads();
+    if (t == 0) {
+        P.ts[tile].matched_step = s_red[0] + s_red[2];
+        P.ts[tile].old_step = s_red[1] + s_red[3];
+    }
+}
+
+// Action-reaction variant, second kernel: one lane per particle adds its
+// row in order (ascending partner id, faces last): its own entries' F and
+// r_i (n x F); for a pair the partner owns, minus the force of the partner's
+// entry for this particle (found in the partner's row) and r_i times its
+// n x F (the normal and the force both change sign).  Then the end of the
+// step as in the force kernel.
+template <typename R>
+__global__ __launch_bounds__(TILE) void k_ar_sum(
+    const double4* __restrict__ xr, const double4* __restrict__ xr_x,
+    const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
+    double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
+    const uint2* __restrict__ rows, const uint32_t* __restrict__ col_j,
+    const uint32_t* __restrict__ perm, const uint32_t* __restrict__ tab_pid_new,
+    const R* __restrict__ pf, uint64_t cap, uint2* __restrict__ cells,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals, R* __restrict__ fo, PoolView P,
+    const Job* __restrict__ jobs, uint32_t* __restrict__ oldkeys, uint2* __restrict__ movers) {
+    __shared__ uint32_t s_flag;
+    Status* st = P.st;
+    if (skip_if_error(st, &s_flag)) return;
+    const int t = threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t p0 = tile * TILE;
+    const uint32_t ns = P.ns;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) {
+        idle_tile(P, jobs, tile, jb, t, xr_x, vw, mat, xr_b, vw_b, mat_b, perm, keys, vals, oldkeys,
+                  movers != nullptr);
+        return;
+    }
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const MatTable* __restrict__ mt = P.mats + J.mat;
+    const uint32_t i = p0 + t;
+    const uint32_t n = J.p0 + J.n;
+    if (i >= n) {
+        keys[i] = P.tile_key[tile] | P.lmask;
+        vals[i] = i;
+        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
+    }
+    R acc[6] = {0, 0, 0, 0, 0, 0};
+    double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0;
+    int mi = 0;
+    if (i < n) {
+        const uint32_t q = perm[i];
+        a = xr[i];
+        a0 = vw[q];
+        a1 = vw[ns + q];
+        a2 = vw[2 * (size_t)ns + q];
+        mi = mat ? mat[q] : 0;
+        const R ri = (R)meta_r(a.w);
+        const uint32_t pid_i = meta_pid(a.w);
+        const uint2 row = rows[i];
+        for (uint32_t k = row.x; k < row.x + row.y; ++k) {
+            const uint32_t pj = tab_pid_new[k];
+            uint64_t g = k;
+            R sg = (R)1;
+            if (pj < FACE && pj < pid_i) {
+                // the partner owns the pair: its entry for this particle (the
+                // contact predicate is symmetric, so the partner's row has one)
+                const uint2 rj = rows[col_j[k]];
+                sg = (R)0;
+                for (uint32_t m = rj.x; m < rj.x + rj.y; ++m) {
+                    if (col_j[m] == i) {
+                        g = m;
+                        sg = (R)-1;
+                        break;
+                    }
+                }
+            }
+            acc[0] += sg * pf[g];
+            acc[1] += sg * pf[cap + g];
+            acc[2] += sg * pf[2 * cap + g];
+            acc[3] += ri * ((sg * sg) * pf[3 * cap + g]);
+            acc[4] += ri * ((sg * sg) * pf[4 * cap + g]);
+            acc[5] += ri * ((sg * sg) * pf[5 * cap + g]);
+        }
+    }
+    finish_tile<R>(P, G, mt, tile, jb, t, i, n, a, a0, a1, a2, mi, acc, false, 0u, 0u, nullptr,
+                   xr_b, vw_b, mat_b, cells + J.cell_base, true, keys, vals, fo, oldkeys, movers);
 }
 
 // ------------------------------------------------------------------ fused
@@ -1193,7 +1396,7 @@ __global__ __launch_bounds__(TILE) void k_fused(
         }
         rows[i] = make_uint2((uint32_t)slab, cnt);
     }
-    finish_tile<R>(P, G, mt, tile, jb, t, i, n, a, a0, a1, a2, mi, acc, matched, orow.y, &cnt,
+    finish_tile<R>(P, G, mt, tile, jb, t, i, n, a, a0, a1, a2, mi, acc, true, matched, orow.y, &cnt,
                    xr_b, vw_b, mat_b, nullptr, false, keys, vals, fo, oldkeys, movers);
 }
 
@@ -1669,6 +1872,30 @@ void launch_fused(const PoolView& P, bool fp64, const Sorted& S, const State& X,
     }
 #undef DEM_FUSED
     hipLaunchKernelGGL(k_clear_cells, dim3(nb), dim3(TILE), 0, s, P, P.jobs, S.xr, cells);
+}
+
+void launch_action_reaction(const PoolView& P, bool fp64, const Sorted& S, const State& X,
+                            const State& Y, const uint2* rows, const uint32_t* col_j,
+                            const uint2* rows_old, const uint32_t* perm,
+                            const uint32_t* tab_pid_old, const double* tab_dt_old,
+                            uint32_t* tab_pid_new, double* tab_dt_new, uint64_t cap, void* pf,
+                            uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
+                            uint32_t* oldkeys, uint2* movers, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
+#define DEM_AR(R)                                                                                  \
+    hipLaunchKernelGGL(k_pair_force<R>, dim3(nb), dim3(TILE), 0, s, S.xr, X.vw, X.mat, rows,      \
+                       col_j, rows_old, perm, tab_pid_old, tab_dt_old, tab_pid_new, tab_dt_new,   \
+                       cap, (R*)pf, P, P.jobs);                                                   \
+    hipLaunchKernelGGL(k_ar_sum<R>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat, Y.xr,    \
+                       Y.vw, Y.mat, rows, col_j, perm, tab_pid_new, (const R*)pf, cap, cells,     \
+                       keys, vals, (R*)fo, P, P.jobs, oldkeys, movers)
+    if (fp64) {
+        DEM_AR(double);
+    } else {
+        DEM_AR(float);
+    }
+#undef DEM_AR
 }
 
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,

@@ -137,6 +137,7 @@ struct dem_pool {
     uint32_t* mp = nullptr;               //   movers by position
     uint32_t radix_left = 0;              // steps to take with the radix sort
     void* fo = nullptr;
+    void* pf = nullptr;                   // action-reaction: pair F and n x F per entry
     MatTable* mats = nullptr;
     Job* jobs_d = nullptr;
     uint32_t* job_fail = nullptr;
@@ -331,7 +332,7 @@ dem_status alloc_contacts(dem_pool* s, uint32_t slots, uint32_t** col, uint32_t*
 }
 
 uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, bool fp64,
-                    uint64_t slots) {
+                    uint64_t slots, uint32_t flags) {
     const uint64_t np = max_tiles * TILE;
     uint64_t b = 0;
     b += 2 * np * (32 + 48 + 1);       // two state buffers
@@ -342,6 +343,7 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     b += np * 6 * (fp64 ? 8 : 4);      // per-particle F, T
     b += max_cells * 8;                // cell bounds
     b += np * slots * (4 + 2 * 28);    // partner list and two history tables
+    if (flags & DEM_FLAG_ACTION_REACTION) b += np * slots * 6 * (fp64 ? 8 : 4);  // pair forces
     b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
     b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4);
     b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
@@ -362,8 +364,10 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
                        uint32_t slots, uint32_t flags, void* stream, dem_pool** out) {
     *out = nullptr;
     if (max_jobs < 1 || slots < 1) return DEM_EINVAL;
-    if (flags & ~(DEM_FLAG_NO_FORCE_OUTPUT | DEM_FLAG_RADIX_SORT | DEM_FLAG_FUSED))
+    if (flags & ~(DEM_FLAG_NO_FORCE_OUTPUT | DEM_FLAG_RADIX_SORT | DEM_FLAG_FUSED |
+                  DEM_FLAG_ACTION_REACTION))
         return DEM_EINVAL;
+    if ((flags & DEM_FLAG_FUSED) && (flags & DEM_FLAG_ACTION_REACTION)) return DEM_EINVAL;
     const uint64_t mt = std::max<uint64_t>(1, tiles_of(max_particles));
     if (mt * TILE > MAX_ENTRIES || mt * TILE * slots > MAX_ENTRIES) return DEM_EINVAL;
     dem_pool* s = new (std::nothrow) dem_pool();
@@ -429,6 +433,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc_t(s, 1, &s->st));
     ALLOC_OR_FAIL(alloc_contacts(s, slots, &s->col_j, &s->tab_pid[0], &s->tab_pid[1],
                                  &s->tab_dt[0], &s->tab_dt[1]));
+    if (flags & DEM_FLAG_ACTION_REACTION)
+        ALLOC_OR_FAIL(dalloc(s, 6 * mt * TILE * slots * (fp64 ? 8 : 4), &s->pf));
 #undef ALLOC_OR_FAIL
     s->cap = (uint64_t)mt * TILE * slots;
     hipError_t e = hipMemset(s->st, 0, sizeof(Status));
@@ -857,7 +863,13 @@ dem_status enqueue_step(dem_pool* s, int o) {
     const bool merge = s->radix_left == 0 && !(s->flags & DEM_FLAG_RADIX_SORT);
     if (s->radix_left) s->radix_left--;
     void* fo = (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo;
-    if (fused)
+    if (s->flags & DEM_FLAG_ACTION_REACTION)
+        launch_action_reaction(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o],
+                               s->prev, s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w],
+                               s->cap, s->pf, s->cells, s->keys, s->vals, fo,
+                               merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr,
+                               s->stream);
+    else if (fused)
         launch_fused(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->slots,
                      s->cells, s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
@@ -915,6 +927,17 @@ dem_status regrow(dem_pool* s, uint64_t need_per_tile, int o) {
     uint32_t *col, *p0, *p1;
     double *d0, *d1;
     if (alloc_contacts(s, (uint32_t)ns, &col, &p0, &p1, &d0, &d1) != DEM_OK) return DEM_ECAPACITY;
+    void* pf = nullptr;
+    if (s->flags & DEM_FLAG_ACTION_REACTION) {
+        if (dalloc(s, 6 * nt * TILE * ns * (s->fp64 ? 8 : 4), &pf) != DEM_OK) {
+            dfree(s, col);
+            dfree(s, p0);
+            dfree(s, p1);
+            dfree(s, d0);
+            dfree(s, d1);
+            return DEM_ECAPACITY;
+        }
+    }
     const uint64_t nc = nt * TILE * ns;
     uint32_t* np_[2] = {p0, p1};
     double* nd_[2] = {d0, d1};
@@ -927,6 +950,10 @@ dem_status regrow(dem_pool* s, uint64_t need_per_tile, int o) {
     for (int k = 0; k < 2; ++k) {
         dfree(s, s->tab_pid[k]);
         dfree(s, s->tab_dt[k]);
+    }
+    if (pf) {
+        dfree(s, s->pf);
+        s->pf = pf;
     }
     s->col_j = col;
     s->tab_pid[0] = p0;
@@ -1110,6 +1137,20 @@ dem_status read_contacts(dem_pool* s, int slot, std::vector<Contact>& out) {
     std::sort(out.begin(), out.end(), [](const Contact& a, const Contact& b) {
         return a.i < b.i || (a.i == b.i && a.j < b.j);
     });
+    if (s->flags & DEM_FLAG_ACTION_REACTION) {
+        // a pair's displacement is kept by its owner (the lower id); the other
+        // directed contact carries its negative
+        for (Contact& c : out) {
+            if (c.j >= FACE || c.j > c.i) continue;
+            const Contact key{c.j, c.i, {0, 0, 0}};
+            auto it = std::lower_bound(out.begin(), out.end(), key,
+                                       [](const Contact& a, const Contact& b) {
+                                           return a.i < b.i || (a.i == b.i && a.j < b.j);
+                                       });
+            if (it != out.end() && it->i == c.j && it->j == c.i)
+                for (int a = 0; a < 3; ++a) c.dt[a] = -it->dt[a];
+        }
+    }
     return DEM_OK;
 }
 
@@ -1216,7 +1257,7 @@ uint64_t dem_footprint(const dem_params* P, uint64_t n) {
     const uint64_t np = std::max<uint64_t>(1, tiles_of(n)) * TILE;
     uint64_t slots = 8;
     if (P->max_contacts) slots = std::max<uint64_t>(1, (P->max_contacts + np - 1) / np);
-    return pool_bytes(np / TILE, cells, 1, P->precision == DEM_PREC_FP64, slots);
+    return pool_bytes(np / TILE, cells, 1, P->precision == DEM_PREC_FP64, slots, P->flags);
 }
 
 dem_status dem_create(const dem_params* params, const dem_material* mats, uint32_t n_mats,
@@ -1413,7 +1454,8 @@ dem_status dem_profile_read(dem_sim* s, double* ms, uint64_t* launches) {
 uint64_t dem_pool_footprint(const dem_pool_params* pp) {
     if (!pp) return 0;
     return pool_bytes(std::max<uint64_t>(1, tiles_of(pp->max_particles)), pp->max_cells, pp->max_jobs,
-                      pp->precision == DEM_PREC_FP64, pp->contact_slots ? pp->contact_slots : 8);
+                      pp->precision == DEM_PREC_FP64, pp->contact_slots ? pp->contact_slots : 8,
+                      pp->flags);
 }
 
 dem_status dem_pool_create(const dem_pool_params* pp, void* stream, dem_pool** out) {
