@@ -190,8 +190,9 @@ __device__ inline void merge_range(uint2 c, uint32_t& lo, uint32_t& hi) {
     }
 }
 
-// Candidate ranges of the particle at a (radius ri), written to
-// s_win[k * DTILE + t]; returns their number.  The lane scans the 27 cells
+// Candidate ranges of the particle at a (radius ri), written to col[k * stride]
+// (the lane's column of a range table); returns their number and, with
+// `count`, adds up their lengths there.  The lane scans the 27 cells
 // around the particle as 9 contiguous ranges: in each (y, z) row the three
 // x-neighbouring cells are consecutive cell keys (plus, across a periodic x
 // boundary, one wrapped cell).  All 27 cell bounds are loaded before any is
@@ -199,7 +200,8 @@ __device__ inline void merge_range(uint2 c, uint32_t& lo, uint32_t& hi) {
 template <bool PER>
 __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4& a, double ri,
                                                      const uint2* __restrict__ cells,
-                                                     uint2* s_win, int t) {
+                                                     uint2* col, int stride,
+                                                     uint32_t* count = nullptr) {
     const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
     // without periodic jobs in the pool the wrap and shear code compiles away
     const bool px = PER && (G.periodic & 1u), py = PER && (G.periodic & 2u),
@@ -304,8 +306,14 @@ __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4
         merge_range(m, lo, hi);
         if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
         if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
-        if (hi > lo) s_win[(nw++) * DTILE + t] = make_uint2(lo, hi);
-        if (PER && hi2 > lo2) s_win[(nw++) * DTILE + t] = make_uint2(lo2, hi2);
+        if (hi > lo) {
+            col[(nw++) * stride] = make_uint2(lo, hi);
+            if (count) *count += hi - lo;
+        }
+        if (PER && hi2 > lo2) {
+            col[(nw++) * stride] = make_uint2(lo2, hi2);
+            if (count) *count += hi2 - lo2;
+        }
     }
     return nw;
 }
@@ -348,6 +356,157 @@ struct PreFilter {
     }
 };
 
+// Exact FP64 re-walk of a lane's `nw` candidate ranges (win(k) gives range
+// k) into its column of s_j; returns the number of contacts found.
+template <int KMAX, bool PER, typename Win>
+__device__ __forceinline__ uint32_t rewalk_exact(const PoolView& P, const Geo& G, const double4& a,
+                                                 double ri, uint32_t i, int t, uint32_t nw,
+                                                 Win win, const double4* __restrict__ xr,
+                                                 uint32_t* s_j) {
+    // more survivors than the row holds (a particle far from the box, whose
+    // FP32 record passes every comparison, or a tight clump): walk the
+    // candidates again with the exact FP64 test, so only more real contacts
+    // than the row holds are an error
+    uint32_t sc = 0;
+    for (uint32_t w2 = 0; w2 < nw; ++w2) {
+        const uint2 rg2 = win(w2);
+        for (uint32_t jx = rg2.x; jx < rg2.y; ++jx) {
+            if (jx == i || jx >= P.ns) continue;
+            const double4 b = xr[jx];
+            double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+            if (PER) {
+                double Sx, Sy, Sz;
+                int ky;
+                image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                dx = dx + Sx;
+                dy = dy + Sy;
+                dz = dz + Sz;
+            }
+            if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
+                s_j[min(sc, (uint32_t)KMAX) * DTILE + t] = jx;
+                ++sc;
+            }
+        }
+    }
+    return sc;
+}
+
+// The end of one lane's contact search, after pass 1 left `sc` survivors in
+// its column of s_j: an exact re-walk of its `nw` candidate ranges (win(k)
+// gives range k) when the survivors overflow the row, the exact FP64 test of the survivors with
+// insertion by partner id, then the box faces.  Returns the row length (0
+// after reporting a row overflow).  The partner ids live in the .x half of
+// the lane's column pcol[k * pstride] of a range table.
+template <int KMAX, bool PER, typename Win>
+__device__ __forceinline__ uint32_t detect_row(const PoolView& P, const Geo& G, const double4& a,
+                                               double ri, uint32_t i, int t, uint32_t sc,
+                                               uint32_t nw, Win win,
+                                               const double4* __restrict__ xr, uint32_t* s_j,
+                                               uint2* pcol, int pstride) {
+    auto pid_at = [&](int k) -> uint32_t& { return pcol[k * pstride].x; };
+    uint32_t cnt = 0;
+    if (sc > KMAX) sc = rewalk_exact<KMAX, PER>(P, G, a, ri, i, t, nw, win, xr, s_j);
+    if (sc > KMAX) {
+        cnt = KMAX + 1;  // row buffer too small: reported below
+    } else {
+        // pass 2: exact FP64 test of the survivors, four loads in flight;
+        // a hit goes into the row in partner-id order (a group's partner
+        // indices are read before any insertion, and insertion only
+        // writes slots up to the hit count)
+        for (uint32_t q0 = 0; q0 < sc; q0 += 4) {
+            uint32_t jj[4];
+            double4 bb[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) jj[m] = q0 + m < sc ? s_j[(q0 + m) * DTILE + t] : 0xFFFFFFFFu;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) bb[m] = xr[jj[m] < P.ns ? jj[m] : i];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (jj[m] == 0xFFFFFFFFu) continue;
+                const double4 b = bb[m];
+                double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                if (PER) {
+                    double Sx, Sy, Sz;
+                    int ky;
+                    image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                    dx = dx + Sx;
+                    dy = dy + Sy;
+                    dz = dz + Sz;
+                }
+                if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
+                    const uint32_t pj = meta_pid(b.w);
+                    int k = (int)cnt;
+                    while (k > 0 && pid_at(k - 1) > pj) {
+                        pid_at(k) = pid_at(k - 1);
+                        s_j[k * DTILE + t] = s_j[(k - 1) * DTILE + t];
+                        --k;
+                    }
+                    pid_at(k) = pj;
+                    s_j[k * DTILE + t] = jj[m];
+                    ++cnt;
+                }
+            }
+        }
+    }
+    // box faces last, in face order (their ids sort after every particle)
+    if (G.walls && cnt <= KMAX) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            if (!(G.walls & (1u << f))) continue;
+            const int ax = f >> 1;
+            const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+            const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
+            if (dist < ri) {
+                if (cnt < KMAX) {
+                    pid_at((int)cnt) = FACE + (uint32_t)f;
+                    s_j[cnt * DTILE + t] = FACE + (uint32_t)f;
+                }
+                ++cnt;
+            }
+        }
+    }
+    if (cnt > KMAX) {
+        atomicOr(&P.st->err, ERR_ROW);
+        cnt = 0;
+    }
+    return cnt;
+}
+
+// Row lengths of the workgroup's lanes into one contiguous region of the
+// contact list (the tile's own region: no device-wide counter), partner
+// positions from the lanes' columns of s_j.  Called by every lane.
+template <int KMAX>
+__device__ __forceinline__ void write_rows(const PoolView& P, uint32_t tile, int t, uint32_t i,
+                                           bool act, uint32_t cnt, const uint32_t* s_j,
+                                           uint32_t* s_excl, uint32_t* s_w, uint32_t* s_base,
+                                           uint2* __restrict__ rows,
+                                           uint32_t* __restrict__ col_j, uint32_t slots) {
+    uint32_t total;
+    const uint32_t excl = block_excl_scan<DTILE / 64>(cnt, s_w, total);
+    s_excl[t] = excl;
+    if (t == 0) {
+        // the workgroup's own region of the contact list: no device-wide counter
+        s_excl[DTILE] = total;
+        uint32_t base = tile * (uint32_t)DTILE * slots;
+        if (total > (uint32_t)DTILE * slots) {
+            atomicOr(&P.st->err, ERR_CAPACITY);
+            atomicMax(&P.st->need, total);
+            base = 0xFFFFFFFFu;
+        } else {
+            P.ts[tile].m_step = total;
+        }
+        *s_base = base;
+    }
+    __syncthreads();
+    const uint32_t base = *s_base;
+    if (base == 0xFFFFFFFFu) return;
+    if (act) rows[i] = make_uint2(base + excl, cnt);
+    for (uint32_t q = t; q < total; q += DTILE) {
+        const int o = owner_of<DTILE>(s_excl, q);
+        col_j[base + q] = s_j[(q - s_excl[o]) * DTILE + o];
+    }
+}
+
 // One lane per particle, DTILE consecutive particles (cell order) per
 // workgroup; the lane walks the candidate ranges of its particle.
 //
@@ -379,7 +538,6 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
     constexpr int NSLOT = (NWIN + 1) > KMAX ? (NWIN + 1) : KMAX;
     __shared__ uint2 s_winpid[NSLOT * DTILE];
     uint2* const s_win = s_winpid;
-    auto pid_at = [&](int k) -> uint32_t& { return s_winpid[k * DTILE + threadIdx.x].x; };
     __shared__ uint32_t s_excl[DTILE + 1];
     __shared__ uint32_t s_w[NW];
     __shared__ uint32_t s_base, s_flag;
@@ -403,7 +561,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
     if (act) {
         const double4 a = xr[i];
         const double ri = (double)meta_r(a.w);
-        nw = candidate_ranges<PER>(G, a, ri, cells, s_win, t);
+        nw = candidate_ranges<PER>(G, a, ri, cells, s_win + t, DTILE);
 
         // FP32 pre-filter: never rejects a pair that touches in FP64 (NaN
         // records of particles far from the box always pass)
@@ -458,121 +616,11 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
             }
 #undef DEM_PRE_STEP
         }
-        if (sc > KMAX) {
-            // more survivors than the row holds (a particle far from the box,
-            // whose FP32 record passes every comparison, or a tight clump):
-            // walk the candidates again with the exact FP64 test, so only
-            // more real contacts than the row holds are an error
-            sc = 0;
-            for (uint32_t w2 = 0; w2 < nw; ++w2) {
-                const uint2 rg2 = s_win[w2 * DTILE + t];
-                for (uint32_t jx = rg2.x; jx < rg2.y; ++jx) {
-                    if (jx == i || jx >= P.ns) continue;
-                    const double4 b = xr[jx];
-                    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                    if (PER) {
-                        double Sx, Sy, Sz;
-                        int ky;
-                        image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
-                        dx = dx + Sx;
-                        dy = dy + Sy;
-                        dz = dz + Sz;
-                    }
-                    if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
-                        s_j[min(sc, (uint32_t)KMAX) * DTILE + t] = jx;
-                        ++sc;
-                    }
-                }
-            }
-        }
-        if (sc > KMAX) {
-            cnt = KMAX + 1;  // row buffer too small: reported below
-        } else {
-            // pass 2: exact FP64 test of the survivors, four loads in flight;
-            // a hit goes into the row in partner-id order (a group's partner
-            // indices are read before any insertion, and insertion only
-            // writes slots up to the hit count)
-            for (uint32_t q0 = 0; q0 < sc; q0 += 4) {
-                uint32_t jj[4];
-                double4 bb[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) jj[m] = q0 + m < sc ? s_j[(q0 + m) * DTILE + t] : 0xFFFFFFFFu;
-#pragma unroll
-                for (int m = 0; m < 4; ++m) bb[m] = xr[jj[m] < P.ns ? jj[m] : i];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    if (jj[m] == 0xFFFFFFFFu) continue;
-                    const double4 b = bb[m];
-                    double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                    if (PER) {
-                        double Sx, Sy, Sz;
-                        int ky;
-                        image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
-                        dx = dx + Sx;
-                        dy = dy + Sy;
-                        dz = dz + Sz;
-                    }
-                    if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
-                        const uint32_t pj = meta_pid(b.w);
-                        int k = (int)cnt;
-                        while (k > 0 && pid_at(k - 1) > pj) {
-                            pid_at(k) = pid_at(k - 1);
-                            s_j[k * DTILE + t] = s_j[(k - 1) * DTILE + t];
-                            --k;
-                        }
-                        pid_at(k) = pj;
-                        s_j[k * DTILE + t] = jj[m];
-                        ++cnt;
-                    }
-                }
-            }
-        }
-        // box faces last, in face order (their ids sort after every particle)
-        if (G.walls && cnt <= KMAX) {
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                if (!(G.walls & (1u << f))) continue;
-                const int ax = f >> 1;
-                const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
-                const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
-                if (dist < ri) {
-                    if (cnt < KMAX) {
-                        pid_at((int)cnt) = FACE + (uint32_t)f;
-                        s_j[cnt * DTILE + t] = FACE + (uint32_t)f;
-                    }
-                    ++cnt;
-                }
-            }
-        }
-        if (cnt > KMAX) {
-            atomicOr(&st->err, ERR_ROW);
-            cnt = 0;
-        }
+        cnt = detect_row<KMAX, PER>(P, G, a, ri, i, t, sc, nw,
+                                    [&](uint32_t w2) { return s_win[w2 * DTILE + t]; }, xr, s_j,
+                                    s_winpid + t, DTILE);
     }
-    uint32_t total;
-    const uint32_t excl = block_excl_scan<NW>(cnt, s_w, total);
-    s_excl[t] = excl;
-    if (t == 0) {
-        // the workgroup's own region of the contact list: no device-wide counter
-        s_excl[DTILE] = total;
-        uint32_t base = tile * (uint32_t)DTILE * slots;
-        if (total > (uint32_t)DTILE * slots) {
-            atomicOr(&st->err, ERR_CAPACITY);
-            atomicMax(&st->need, total);
-            base = 0xFFFFFFFFu;
-        } else {
-            P.ts[tile].m_step = total;
-        }
-        s_base = base;
-    }
-    __syncthreads();
-    const uint32_t base = s_base;
-    if (base == 0xFFFFFFFFu) return;
-    if (act) rows[i] = make_uint2(base + excl, cnt);
-    for (uint32_t q = t; q < total; q += DTILE) {
-        const int o = owner_of<DTILE>(s_excl, q);
-        col_j[base + q] = s_j[(q - s_excl[o]) * DTILE + o];
-    }
+    write_rows<KMAX>(P, tile, t, i, act, cnt, s_j, s_excl, s_w, &s_base, rows, col_j, slots);
 }
 
 // ------------------------------------------------------------- contact law
@@ -1340,7 +1388,7 @@ __global__ __launch_bounds__(TILE) void k_fused(
             }
             return touching(dx, dy, dz, rid + (double)meta_r(b.w));
         };
-        const uint32_t nw = candidate_ranges<PER>(G, a, rid, cells + J.cell_base, s_win, t);
+        const uint32_t nw = candidate_ranges<PER>(G, a, rid, cells + J.cell_base, s_win + t, TILE);
         const PreFilter<PER> pre(G, a, J.margin);
         constexpr uint32_t NONE = 0xFFFFFFFFu;
         if (nw > 0) {
