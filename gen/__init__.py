@@ -65,6 +65,20 @@ class Material:
 
 
 @dataclass
+class Wall:
+    """A static wall inside the box besides its faces: kind RECT is the
+    rectangle p + s u + t v (u orthogonal to v), kind SEGMENT the segment
+    p + s u; s, t in [0, 1].  Lengths in metres."""
+    kind: int
+    p: tuple
+    u: tuple
+    v: tuple = (0.0, 0.0, 0.0)
+
+
+RECT, SEGMENT = 0, 1
+
+
+@dataclass
 class Scene:
     """One simulation's inputs, in SI units.  Arrays are in particle-id order."""
     lo: np.ndarray
@@ -82,6 +96,7 @@ class Scene:
     dt: float = 0.0          # 0 = simulator's own rule
     steps: int = 1
     kn_form: int = 0         # 0 = as printed, 1 = textbook Hertz
+    extra_walls: list = field(default_factory=list)   # Wall entries, at most 10
     name: str = ""
     meta: dict = field(default_factory=dict)
 

@@ -18,6 +18,7 @@ _SO = os.path.join(_HERE, "liboracle.so")
 _LIB = None
 MAXMAT = 8
 FACE_ID = 0xFFFFFFF0  # partner id of box face f is FACE_ID + f
+MAX_WALLS = 10        # extra wall k has partner id FACE_ID + 6 + k
 
 
 def build(force: bool = False) -> str:
@@ -30,6 +31,11 @@ def build(force: bool = False) -> str:
     return _SO
 
 
+class Wall(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad", ctypes.c_int32), ("p", ctypes.c_double * 3),
+                ("u", ctypes.c_double * 3), ("v", ctypes.c_double * 3)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("walls", ctypes.c_uint32), ("periodic", ctypes.c_uint32),
@@ -38,7 +44,9 @@ class Params(ctypes.Structure):
                 ("kn_form", ctypes.c_int32), ("n_mats", ctypes.c_int32),
                 ("E", ctypes.c_double * MAXMAT), ("poisson", ctypes.c_double * MAXMAT),
                 ("G", ctypes.c_double * MAXMAT), ("density", ctypes.c_double * MAXMAT),
-                ("restitution", ctypes.c_double * MAXMAT), ("mu", ctypes.c_double * MAXMAT)]
+                ("restitution", ctypes.c_double * MAXMAT), ("mu", ctypes.c_double * MAXMAT),
+                ("n_extra", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("extra", Wall * MAX_WALLS)]
 
 
 _P = ctypes.POINTER(Params)
@@ -98,6 +106,15 @@ def params(scene, time=0.0, dt=None) -> Params:
     for k, m in enumerate(scene.materials):
         P.E[k], P.poisson[k], P.G[k] = m.E, m.poisson, m.G
         P.density[k], P.restitution[k], P.mu[k] = m.density, m.restitution, m.mu
+    walls = list(getattr(scene, "extra_walls", []) or [])
+    assert len(walls) <= MAX_WALLS
+    P.n_extra = len(walls)
+    for k, wl in enumerate(walls):
+        P.extra[k].kind = int(wl.kind)
+        for a in range(3):
+            P.extra[k].p[a] = float(wl.p[a])
+            P.extra[k].u[a] = float(wl.u[a])
+            P.extra[k].v[a] = float(wl.v[a])
     if dt is None:
         dt = scene.dt if scene.dt else dt_rule(scene, P)
     P.dt = float(dt)

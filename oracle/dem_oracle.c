@@ -33,6 +33,12 @@
  *     exactly eps;
  *   - pair restitution and friction are the means of the two materials';
  *     a box face takes the particle's own material, infinite radius and mass;
+ *   - extra walls (kernel list: "CollideRectangle", "CollideLine") are
+ *     static closed rectangles or segments acting like a box face; the
+ *     contact point is the wall's point closest to the centre, the normal
+ *     points from the centre to it, the overlap is r_i minus that distance;
+ *     a centre exactly on a rectangle takes the normal u x v, a centre
+ *     exactly on a segment makes no contact;
  *   - solid spheres: m = rho 4/3 pi r^3, I = 2/5 m r^2;
  *   - Lees-Edwards shear along x with gradient along y when shear_rate != 0.
  *
@@ -48,6 +54,15 @@
 
 #define ORC_MAXMAT 8
 #define ORC_FACE_ID 0xFFFFFFF0u /* partner id of box face f is ORC_FACE_ID + f */
+#define ORC_MAX_WALLS 10        /* extra wall k has partner id ORC_FACE_ID + 6 + k */
+
+/* An extra wall: kind 0 the rectangle p + s u + t v (u and v orthogonal),
+ * kind 1 the segment p + s u; s, t in [0, 1]. */
+typedef struct {
+    int32_t kind;
+    int32_t pad;
+    double p[3], u[3], v[3];
+} orc_wall;
 
 typedef struct {
     double lo[3], hi[3];
@@ -61,6 +76,9 @@ typedef struct {
     int32_t n_mats;
     double E[ORC_MAXMAT], poisson[ORC_MAXMAT], G[ORC_MAXMAT];
     double density[ORC_MAXMAT], restitution[ORC_MAXMAT], mu[ORC_MAXMAT];
+    int32_t n_extra;
+    int32_t pad;
+    orc_wall extra[ORC_MAX_WALLS];
 } orc_params;
 
 /* ------------------------------------------------------------ constants */
@@ -134,6 +152,47 @@ static void cross3(const double *a, const double *b, double *c) {
     c[0] = a[1] * b[2] - a[2] * b[1];
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Extra wall W and a centre c: w = q - c for the wall's point q closest to
+ * c (the parameters s, t of the rectangle or segment clamped to [0, 1]);
+ * returns |w|^2.  No fused multiply-add anywhere, so the contact decision
+ * |w|^2 < r^2 is reproducible bit for bit. */
+static double orc_wall_gap(const orc_wall *W, const double *c, double *wv) {
+    double d[3], q[3];
+    for (int a = 0; a < 3; ++a) d[a] = c[a] - W->p[a];
+    double s = dot3(d, W->u) / dot3(W->u, W->u);
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    for (int a = 0; a < 3; ++a) q[a] = W->p[a] + s * W->u[a];
+    if (W->kind == 0) {
+        double t = dot3(d, W->v) / dot3(W->v, W->v);
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        for (int a = 0; a < 3; ++a) q[a] = q[a] + t * W->v[a];
+    }
+    for (int a = 0; a < 3; ++a) wv[a] = q[a] - c[a];
+    double d2 = wv[0] * wv[0] + wv[1] * wv[1];
+    return d2 + wv[2] * wv[2];
+}
+
+/* Whether a sphere of radius ri centred at c touches extra wall W. */
+static int orc_wall_touch(const orc_wall *W, const double *c, double ri) {
+    double wv[3];
+    double d2 = orc_wall_gap(W, c, wv);
+    return d2 < ri * ri && (W->kind == 0 || d2 > 0.0);
+}
+
+/* Unit normal from the centre c towards extra wall W and the overlap. */
+static void orc_wall_normal(const orc_wall *W, const double *c, double ri, double *n, double *dn) {
+    double wv[3];
+    double d = sqrt(orc_wall_gap(W, c, wv));
+    if (d > 0.0) {
+        for (int a = 0; a < 3; ++a) n[a] = wv[a] / d;
+    } else {
+        cross3(W->u, W->v, n);
+        double l = sqrt(dot3(n, n));
+        for (int a = 0; a < 3; ++a) n[a] = n[a] / l;
+    }
+    *dn = ri - d;
 }
 
 /*
@@ -377,6 +436,13 @@ static int orc_find(const orc_params *P, long n, const double *x, const double *
             hits[m].j = ORC_FACE_ID + (uint32_t)f; hits[m].img = 0; ++m;
         }
     }
+    /* then the extra walls, in order */
+    for (int k = 0; k < P->n_extra; ++k) {
+        if (orc_wall_touch(&P->extra[k], xi, r[i])) {
+            if (m >= cap) return -1;
+            hits[m].j = ORC_FACE_ID + 6u + (uint32_t)k; hits[m].img = 0; ++m;
+        }
+    }
     return m;
 }
 
@@ -410,7 +476,8 @@ done:
 
 /* ---------------------------------------------------------- one pair */
 /* Public: the force law for one contact, for unit checks.  Geometry from
- * positions: partner j (face < 0) or box face `face` (0..5).  */
+ * positions: partner j (face < 0), box face `face` (0..5) or extra wall
+ * face - 6.  */
 void orc_pair(const orc_params *P, const double *xi, const double *vi, const double *wi, double ri,
               int mi, const double *xj, const double *vj, const double *wj, double rj, int mj,
               int face, const double *dt_old, double *F, double *T, double *dt_new, double *dn_out,
@@ -433,11 +500,15 @@ void orc_pair(const orc_params *P, const double *xi, const double *vi, const dou
         double massj = orc_mass(P->density[mj], rj);
         ms = massi * massj / (massi + massj);
     } else {
-        int a0 = face >> 1;
-        double dist = (face & 1) ? P->hi[a0] - xi[a0] : xi[a0] - P->lo[a0];
-        for (int a = 0; a < 3; ++a) n[a] = 0.0;
-        n[a0] = (face & 1) ? 1.0 : -1.0;
-        dn = ri - dist;
+        if (face < 6) {
+            int a0 = face >> 1;
+            double dist = (face & 1) ? P->hi[a0] - xi[a0] : xi[a0] - P->lo[a0];
+            for (int a = 0; a < 3; ++a) n[a] = 0.0;
+            n[a0] = (face & 1) ? 1.0 : -1.0;
+            dn = ri - dist;
+        } else {
+            orc_wall_normal(&P->extra[face - 6], xi, ri, n, &dn);
+        }
         for (int a = 0; a < 3; ++a) {
             v[a] = vi[a];
             rw[a] = ri * wi[a];
@@ -554,10 +625,14 @@ int orc_step(const orc_params *P, long n, double *x, double *v, double *w, const
                 ms = massi * massj / (massi + massj);
             } else {
                 int f = (int)(h.j - ORC_FACE_ID), a0 = f >> 1;
-                double dist = (f & 1) ? P->hi[a0] - x[3 * i + a0] : x[3 * i + a0] - P->lo[a0];
-                n_[0] = n_[1] = n_[2] = 0.0;
-                n_[a0] = (f & 1) ? 1.0 : -1.0;
-                dn = r[i] - dist;
+                if (f < 6) {
+                    double dist = (f & 1) ? P->hi[a0] - x[3 * i + a0] : x[3 * i + a0] - P->lo[a0];
+                    n_[0] = n_[1] = n_[2] = 0.0;
+                    n_[a0] = (f & 1) ? 1.0 : -1.0;
+                    dn = r[i] - dist;
+                } else {
+                    orc_wall_normal(&P->extra[f - 6], x + 3 * i, r[i], n_, &dn);
+                }
                 for (int a = 0; a < 3; ++a) {
                     vrel[a] = v[3 * i + a];
                     rw[a] = r[i] * w[3 * i + a];

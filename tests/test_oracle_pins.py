@@ -494,3 +494,126 @@ def test_dt_rule_closed_form():
     kn = textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, r, r) * 0.91 / 1.91
     want = hertz_time_constant() * (m / 2 / kn) ** 0.4 * 0.1 ** -0.2 / 50
     assert abs(oracle.dt_rule(sc) - want) / want < 1e-9
+
+
+# --------------------------------------------------------------- extra walls
+def _one_sphere(x, v, r=5e-6, L=100e-6, walls=gen.WALL_ALL, extra=(), gravity=(0.0, 0.0, 0.0)):
+    mat = gen.Material.make()
+    return gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([x], float),
+                     v=np.array([v], float), w=np.zeros((1, 3)), r=gen.f32([r]),
+                     mat=np.zeros(1, np.uint16), materials=[mat], walls=walls, gravity=gravity,
+                     extra_walls=list(extra))
+
+
+def test_rectangle_on_a_face_plane_acts_as_that_face():
+    # A rectangle covering the low z face, with that face switched off, gives
+    # the bounce (with friction and spin) of the face itself, which the
+    # head-on and sliding pins above fix.
+    L, r = 100e-6, 5e-6
+    rect = gen.Wall(gen.RECT, (0.0, 0.0, 0.0), (L, 0.0, 0.0), (0.0, L, 0.0))
+    x, v = (0.37 * L, 0.61 * L, r + 1e-13), (0.02, -0.01, -0.1)
+    a = _one_sphere(x, v, gravity=(0, 0, -9.81))
+    b = _one_sphere(x, v, walls=gen.WALL_ALL & ~(1 << 4), extra=[rect], gravity=(0, 0, -9.81))
+    dt = oracle.Sim(a).dt
+    sa, sb = oracle.Sim(a, dt=dt, mode=0), oracle.Sim(b, dt=dt, mode=0)
+    steps_in = 0
+    for _ in range(300):
+        sa.step()
+        sb.step()
+        assert len(sa.hist) == len(sb.hist)
+        if len(sa.hist):
+            steps_in += 1
+            assert int(sa.hist.j[0]) == oracle.FACE_ID + 4
+            assert int(sb.hist.j[0]) == oracle.FACE_ID + 6
+    assert 20 < steps_in < 300
+    for k in ("x", "v", "w"):
+        ref = getattr(sa, k)
+        assert np.abs(getattr(sb, k) - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-300), k
+    assert np.abs(sa.w).max() > 0  # friction did act
+
+
+def test_rectangle_edge_contact_closed_form():
+    # Centre beside an edge: the contact point is on the edge, the normal
+    # points from the centre to it, and at rest without history the force is
+    # the Hertz normal force with the face stiffness (r* = r).
+    r = 5e-6
+    rect = gen.Wall(gen.RECT, (30e-6, 20e-6, 50e-6), (40e-6, 0.0, 0.0), (0.0, 60e-6, 0.0))
+    e, h = 3e-6, 2e-6
+    x = np.array([30e-6 - e, 50e-6, 50e-6 + h])
+    sc = _one_sphere(x, (0, 0, 0), walls=0, extra=[rect])
+    r = float(sc.r[0])
+    P = oracle.params(sc, dt=1e-9)
+    F, T, _, dn, _ = oracle.pair(P, x, np.zeros(3), np.zeros(3), r, 0, face=6)
+    d = math.hypot(e, h)
+    n = np.array([e, 0.0, -h]) / d
+    kn = oracle.kn(P, 0, 0, r, 0)
+    assert abs(dn - (r - d)) <= 1e-14 * r
+    np.testing.assert_allclose(F, -kn * (r - d) ** 1.5 * n, rtol=1e-12, atol=1e-25)
+    assert np.abs(T).max() <= 1e-12 * r * np.abs(F).max()  # F along n: no torque
+    # inside and outside the radius along the same direction
+    for scale, touching in ((0.999, True), (1.001, False)):
+        y = np.array([30e-6, 50e-6, 50e-6]) + (x - np.array([30e-6, 50e-6, 50e-6])) * (r * scale / d)
+        sc2 = _one_sphere(y, (0, 0, 0), walls=0, extra=[rect])
+        i, j = oracle.contacts(sc2, mode=0)
+        assert (len(i) == 1) == touching
+
+
+def test_segment_contact_closed_form():
+    r = 5e-6
+    seg = gen.Wall(gen.SEGMENT, (20e-6, 50e-6, 50e-6), (60e-6, 0.0, 0.0))
+    cases = [
+        # beside the middle: normal perpendicular to the segment
+        (np.array([50e-6, 54e-6, 50e-6]), np.array([0.0, -4e-6, 0.0])),
+        # beyond the far end: normal towards the end point
+        (np.array([83e-6, 50e-6, 52e-6]), np.array([-3e-6, 0.0, -2e-6])),
+    ]
+    for x, w in cases:
+        sc = _one_sphere(x, (0, 0, 0), walls=0, extra=[seg])
+        rr = float(sc.r[0])
+        P = oracle.params(sc, dt=1e-9)
+        F, _, _, dn, _ = oracle.pair(P, x, np.zeros(3), np.zeros(3), rr, 0, face=6)
+        d = np.linalg.norm(w)
+        kn = oracle.kn(P, 0, 0, rr, 0)
+        assert abs(dn - (rr - d)) <= 1e-14 * rr
+        np.testing.assert_allclose(F, -kn * (rr - d) ** 1.5 * w / d, rtol=1e-12, atol=1e-25)
+        i, j = oracle.contacts(sc, mode=0)
+        assert list(j) == [oracle.FACE_ID + 6]
+    # a centre on the segment, and one just beyond the radius: no contact
+    for x in (np.array([40e-6, 50e-6, 50e-6]), np.array([40e-6, 50e-6 + 1.0001 * r, 50e-6])):
+        i, j = oracle.contacts(_one_sphere(x, (0, 0, 0), walls=0, extra=[seg]), mode=0)
+        assert len(i) == 0
+
+
+def _rotation(axis, angle):
+    a = np.asarray(axis, float) / np.linalg.norm(axis)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(angle) * K + (1 - math.cos(angle)) * K @ K
+
+
+def test_tilted_rectangle_is_a_rotated_floor():
+    # The same oblique bounce (friction, spin) on an axis-aligned rectangle and
+    # on the rectangle rotated by R about the box centre: the motion is R
+    # times the other at every step, and the contact begins and ends on the
+    # same steps.
+    r = 5e-6
+    C = np.full(3, 50e-6)
+    p, u, v = np.array([30e-6, 30e-6, 40e-6]), np.array([40e-6, 0, 0]), np.array([0, 40e-6, 0])
+    x0, v0 = np.array([52e-6, 47e-6, 40e-6 + r + 1e-12]), np.array([0.03, 0.01, -0.1])
+    R = _rotation((1.0, 2.0, 3.0), 0.7)
+    flat = _one_sphere(x0, v0, walls=0, extra=[gen.Wall(gen.RECT, tuple(p), tuple(u), tuple(v))])
+    tilt = _one_sphere(C + R @ (x0 - C), R @ v0, walls=0,
+                       extra=[gen.Wall(gen.RECT, tuple(C + R @ (p - C)), tuple(R @ u),
+                                       tuple(R @ v))])
+    dt = oracle.Sim(flat).dt
+    sa, sb = oracle.Sim(flat, dt=dt, mode=0), oracle.Sim(tilt, dt=dt, mode=0)
+    steps_in = 0
+    for _ in range(200):
+        sa.step()
+        sb.step()
+        assert len(sa.hist) == len(sb.hist)
+        steps_in += len(sa.hist)
+    assert 20 < steps_in < 200
+    np.testing.assert_allclose(sb.x[0] - C, R @ (sa.x[0] - C), rtol=0, atol=1e-12 * 50e-6)
+    np.testing.assert_allclose(sb.v[0], R @ sa.v[0], rtol=0, atol=1e-9 * np.abs(v0).max())
+    np.testing.assert_allclose(sb.w[0], R @ sa.w[0], rtol=0, atol=1e-9 * np.abs(sa.w).max())
+    assert sa.v[0, 2] > 0 and np.abs(sa.w).max() > 0
