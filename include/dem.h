@@ -74,6 +74,25 @@ typedef struct {
     double E, poisson, G, density, restitution, mu;
 } dem_material;
 
+/* A static wall inside the box besides its faces (section 3.2, kernel list:
+ * "CollideRectangle", "CollideLine"): kind DEM_WALL_RECT is the closed
+ * rectangle p + s u + t v (u and v orthogonal and non-zero), kind
+ * DEM_WALL_SEGMENT the closed segment p + s u; s, t in [0, 1], lengths in
+ * metres.  Like a box face it is a body of infinite radius and mass with the
+ * particle's material.  The contact point is the wall's point closest to
+ * the particle centre; the particle touches the wall when that point is
+ * nearer than its radius (a centre exactly on a segment makes no contact; a
+ * centre exactly on a rectangle takes the normal u x v).  Extra wall k has
+ * partner id DEM_FACE_ID + 6 + k in the contact history. */
+typedef struct {
+    int32_t kind;
+    uint32_t reserved;
+    double p[3], u[3], v[3];
+} dem_wall;
+#define DEM_WALL_RECT 0
+#define DEM_WALL_SEGMENT 1
+#define DEM_MAX_WALLS 10
+
 typedef struct {
     double lo[3], hi[3]; /* box [m] */
     uint32_t walls;      /* bit 2a: low face of axis a is a wall; bit 2a+1: high face */
@@ -90,7 +109,8 @@ typedef struct {
                             >= 2 r_max. */
     uint64_t max_contacts; /* initial contact-table capacity; 0 = automatic */
     uint32_t flags;        /* DEM_FLAG_* */
-    uint32_t reserved;
+    uint32_t n_extra_walls;          /* entries of extra_walls, at most DEM_MAX_WALLS */
+    const dem_wall *extra_walls;     /* copied at creation; may be null when none */
 } dem_params;
 
 #define DEM_FLAG_NO_FORCE_OUTPUT 1u /* do not store per-particle F, T each step */

@@ -53,6 +53,11 @@ class Material(ctypes.Structure):
                 ("mu", ctypes.c_double)]
 
 
+class Wall(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_uint32),
+                ("p", ctypes.c_double * 3), ("u", ctypes.c_double * 3), ("v", ctypes.c_double * 3)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
                 ("walls", ctypes.c_uint32), ("periodic", ctypes.c_uint32),
@@ -60,7 +65,8 @@ class Params(ctypes.Structure):
                 ("dt", ctypes.c_double), ("time", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("kn_form", ctypes.c_int32),
                 ("cell_size", ctypes.c_double), ("max_contacts", ctypes.c_uint64),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("n_extra_walls", ctypes.c_uint32),
+                ("extra_walls", ctypes.c_void_p)]
 
 
 class Info(ctypes.Structure):
@@ -200,7 +206,9 @@ def _stream_handle(stream):
 
 def make_params(lo, hi, walls=0x3F, periodic=0, gravity=(0.0, 0.0, -9.81), shear_rate=0.0,
                 dt=0.0, time=0.0, precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0,
-                flags=0) -> Params:
+                flags=0, extra_walls=()) -> Params:
+    """dem_params; extra_walls holds objects with kind, p, u, v (e.g. gen.Wall),
+    kept alive by the returned structure."""
     P = Params()
     for a in range(3):
         P.lo[a] = float(lo[a])
@@ -216,6 +224,17 @@ def make_params(lo, hi, walls=0x3F, periodic=0, gravity=(0.0, 0.0, -9.81), shear
     P.cell_size = float(cell_size)
     P.max_contacts = int(max_contacts)
     P.flags = int(flags)
+    ws = list(extra_walls or ())
+    arr = (Wall * max(1, len(ws)))()
+    for k, wl in enumerate(ws):
+        arr[k].kind = int(wl.kind)
+        for a in range(3):
+            arr[k].p[a] = float(wl.p[a])
+            arr[k].u[a] = float(wl.u[a])
+            arr[k].v[a] = float(wl.v[a])
+    P._walls = arr
+    P.n_extra_walls = len(ws)
+    P.extra_walls = ctypes.addressof(arr) if ws else None
     return P
 
 
@@ -229,10 +248,10 @@ class Sim:
     def __init__(self, lo, hi, x, v, w, r, materials, mat=None, walls=0x3F, periodic=0,
                  gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
                  precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0, flags=0,
-                 stream=None):
+                 stream=None, extra_walls=()):
         L = lib()
         self.params = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time,
-                                  precision, kn_form, cell_size, max_contacts, flags)
+                                  precision, kn_form, cell_size, max_contacts, flags, extra_walls)
         x = _c(x, np.float64, (-1, 3))
         n = x.shape[0]
         v = _c(v, np.float64, (n, 3))
@@ -258,7 +277,8 @@ class Sim:
         args = dict(lo=sc.lo, hi=sc.hi, x=sc.x, v=sc.v, w=sc.w, r=sc.r, materials=sc.materials,
                     mat=sc.mat if len(sc.materials) > 1 else None, walls=sc.walls,
                     periodic=sc.periodic, gravity=sc.gravity, shear_rate=sc.shear_rate, dt=sc.dt,
-                    kn_form=sc.kn_form, precision=precision)
+                    kn_form=sc.kn_form, precision=precision,
+                    extra_walls=getattr(sc, "extra_walls", ()))
         args.update(kw)
         return cls(**args)
 
@@ -388,9 +408,9 @@ class PreparedJob:
 
     def __init__(self, lo, hi, x, v, w, r, materials, precision, mat=None, walls=0x3F,
                  periodic=0, gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
-                 kn_form=0, cell_size=0.0):
+                 kn_form=0, cell_size=0.0, extra_walls=()):
         P = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time, precision,
-                        kn_form, cell_size)
+                        kn_form, cell_size, extra_walls=extra_walls)
         x = _c(x, np.float64, (-1, 3))
         n = x.shape[0]
         v = _c(v, np.float64, (n, 3))
@@ -412,7 +432,7 @@ class PreparedJob:
         args = dict(lo=sc.lo, hi=sc.hi, x=sc.x, v=sc.v, w=sc.w, r=sc.r, materials=sc.materials,
                     mat=sc.mat if len(sc.materials) > 1 else None, walls=sc.walls,
                     periodic=sc.periodic, gravity=sc.gravity, shear_rate=sc.shear_rate, dt=sc.dt,
-                    kn_form=sc.kn_form)
+                    kn_form=sc.kn_form, extra_walls=getattr(sc, "extra_walls", ()))
         args.update(kw)
         return cls(precision=precision, **args)
 
@@ -451,9 +471,9 @@ class Pool:
 
     def add(self, lo, hi, x, v, w, r, materials, steps, mat=None, walls=0x3F, periodic=0,
             gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0, kn_form=0,
-            cell_size=0.0) -> int:
+            cell_size=0.0, extra_walls=()) -> int:
         P = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time, self.precision,
-                        kn_form, cell_size)
+                        kn_form, cell_size, extra_walls=extra_walls)
         x = _c(x, np.float64, (-1, 3))
         n = x.shape[0]
         v = _c(v, np.float64, (n, 3))
@@ -475,7 +495,7 @@ class Pool:
         args = dict(lo=sc.lo, hi=sc.hi, x=sc.x, v=sc.v, w=sc.w, r=sc.r, materials=sc.materials,
                     mat=sc.mat if len(sc.materials) > 1 else None, walls=sc.walls,
                     periodic=sc.periodic, gravity=sc.gravity, shear_rate=sc.shear_rate, dt=sc.dt,
-                    kn_form=sc.kn_form)
+                    kn_form=sc.kn_form, extra_walls=getattr(sc, "extra_walls", ()))
         args.update(kw)
         return self.add(steps=steps, **args)
 

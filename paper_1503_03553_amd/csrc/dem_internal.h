@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/dem.h"
+
 namespace dem {
 
 constexpr int TILE = 128;                 // particles per force workgroup (2 waves)
@@ -72,8 +74,9 @@ struct Job {
     uint32_t mat;
     uint32_t status;               // JOB_*
     uint32_t steps_left;
-    uint32_t pad;
+    uint32_t nxw;                  // extra walls of the job
     unsigned long long steps_done;
+    const dem_wall* xw;            // its extra walls (device memory)
 };
 
 // Device-side status word (one per pool).

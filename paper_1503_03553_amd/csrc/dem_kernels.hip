@@ -128,6 +128,41 @@ __device__ inline bool touching(double dx, double dy, double dz, double s) {
     return d2 < s * s;
 }
 
+// Extra wall W and a centre c: w = q - c for the wall's point q closest to c
+// (the rectangle's or segment's parameters clamped to [0, 1]); returns
+// |w|^2.  Written out with no fused multiply-add, so that the contact
+// decision |w|^2 < r^2 is bit-exact.
+__device__ inline double wall_gap(const dem_wall& W, double cx, double cy, double cz, double& wx,
+                                  double& wy, double& wz) {
+#pragma clang fp contract(off)
+    const double dx = cx - W.p[0], dy = cy - W.p[1], dz = cz - W.p[2];
+    double s = (dx * W.u[0] + dy * W.u[1] + dz * W.u[2]) /
+               (W.u[0] * W.u[0] + W.u[1] * W.u[1] + W.u[2] * W.u[2]);
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    double qx = W.p[0] + s * W.u[0], qy = W.p[1] + s * W.u[1], qz = W.p[2] + s * W.u[2];
+    if (W.kind == DEM_WALL_RECT) {
+        double t = (dx * W.v[0] + dy * W.v[1] + dz * W.v[2]) /
+                   (W.v[0] * W.v[0] + W.v[1] * W.v[1] + W.v[2] * W.v[2]);
+        t = t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
+        qx = qx + t * W.v[0];
+        qy = qy + t * W.v[1];
+        qz = qz + t * W.v[2];
+    }
+    wx = qx - cx;
+    wy = qy - cy;
+    wz = qz - cz;
+    const double d2 = wx * wx + wy * wy;
+    return d2 + wz * wz;
+}
+
+// Whether a sphere of radius r centred at c touches extra wall W (a centre
+// exactly on a segment makes no contact).
+__device__ inline bool wall_touch(const dem_wall& W, double cx, double cy, double cz, double r) {
+    double wx, wy, wz;
+    const double d2 = wall_gap(W, cx, cy, cz, wx, wy, wz);
+    return d2 < r * r && (W.kind == DEM_WALL_RECT || d2 > 0.0);
+}
+
 __device__ inline uint32_t skip_if_error(const Status* st, uint32_t* s_flag) {
     if (threadIdx.x == 0) *s_flag = __atomic_load_n(&st->err, __ATOMIC_RELAXED);
     __syncthreads();
@@ -402,7 +437,8 @@ __device__ __forceinline__ uint32_t detect_row(const PoolView& P, const Geo& G, 
                                                double ri, uint32_t i, int t, uint32_t sc,
                                                uint32_t nw, Win win,
                                                const double4* __restrict__ xr, uint32_t* s_j,
-                                               uint2* pcol, int pstride) {
+                                               uint2* pcol, int pstride,
+                                               const dem_wall* __restrict__ xw, uint32_t nxw) {
     auto pid_at = [&](int k) -> uint32_t& { return pcol[k * pstride].x; };
     uint32_t cnt = 0;
     if (sc > KMAX) sc = rewalk_exact<KMAX, PER>(P, G, a, ri, i, t, nw, win, xr, s_j);
@@ -463,6 +499,16 @@ __device__ __forceinline__ uint32_t detect_row(const PoolView& P, const Geo& G, 
                 }
                 ++cnt;
             }
+        }
+    }
+    // then the extra walls, in order
+    for (uint32_t k = 0; k < nxw && cnt <= KMAX; ++k) {
+        if (wall_touch(xw[k], a.x, a.y, a.z, ri)) {
+            if (cnt < KMAX) {
+                pid_at((int)cnt) = FACE + 6u + k;
+                s_j[cnt * DTILE + t] = FACE + 6u + k;
+            }
+            ++cnt;
         }
     }
     if (cnt > KMAX) {
@@ -618,7 +664,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
         }
         cnt = detect_row<KMAX, PER>(P, G, a, ri, i, t, sc, nw,
                                     [&](uint32_t w2) { return s_win[w2 * DTILE + t]; }, xr, s_j,
-                                    s_winpid + t, DTILE);
+                                    s_winpid + t, DTILE, J.xw, J.nxw);
     }
     write_rows<KMAX>(P, tile, t, i, act, cnt, s_j, s_excl, s_w, &s_base, rows, col_j, slots);
 }
@@ -689,7 +735,8 @@ __device__ __forceinline__ PairTerms<R> pair_terms(
     const Geo& G, const MatTable* __restrict__ mt, uint32_t code, const double4& a,
     const double2& a0, const double2& a1, const double2& a2, int mi,
     const double4* __restrict__ xr, const double2* __restrict__ vw,
-    const uint8_t* __restrict__ mat, const uint32_t* __restrict__ perm, uint32_t ns) {
+    const uint8_t* __restrict__ mat, const uint32_t* __restrict__ perm, uint32_t ns,
+    const dem_wall* __restrict__ xw) {
     PairTerms<R> p;
     const R ri = (R)meta_r(a.w);
     const double rid = (double)meta_r(a.w);
@@ -743,13 +790,35 @@ __device__ __forceinline__ PairTerms<R> pair_terms(
         const int f = (int)(code - FACE), ax = f >> 1;
         p.pid = code;
         p.mj = mi;
-        const double q = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
-        const double dist = (f & 1) ? G.hi[ax] - q : q - G.lo[ax];
-        const R sg = (f & 1) ? (R)1 : (R)-1;
-        p.nx = ax == 0 ? sg : (R)0;
-        p.ny = ax == 1 ? sg : (R)0;
-        p.nz = ax == 2 ? sg : (R)0;
-        p.dn = (R)(rid - dist);
+        if (f < 6) {
+            const double q = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+            const double dist = (f & 1) ? G.hi[ax] - q : q - G.lo[ax];
+            const R sg = (f & 1) ? (R)1 : (R)-1;
+            p.nx = ax == 0 ? sg : (R)0;
+            p.ny = ax == 1 ? sg : (R)0;
+            p.nz = ax == 2 ? sg : (R)0;
+            p.dn = (R)(rid - dist);
+        } else {
+            // extra wall: normal from the centre to the wall's closest point
+            const dem_wall& W = xw[f - 6];
+            double wx, wy, wz;
+            const double d = sqrt(wall_gap(W, a.x, a.y, a.z, wx, wy, wz));
+            if (!(d > 0.0)) {
+                // centre on the rectangle: its normal u x v
+                wx = W.u[1] * W.v[2] - W.u[2] * W.v[1];
+                wy = W.u[2] * W.v[0] - W.u[0] * W.v[2];
+                wz = W.u[0] * W.v[1] - W.u[1] * W.v[0];
+                const double l = sqrt(wx * wx + wy * wy + wz * wz);
+                p.nx = (R)(wx / l);
+                p.ny = (R)(wy / l);
+                p.nz = (R)(wz / l);
+            } else {
+                p.nx = (R)(wx / d);
+                p.ny = (R)(wy / d);
+                p.nz = (R)(wz / d);
+            }
+            p.dn = (R)(rid - d);
+        }
         p.vx = (R)a0.x;
         p.vy = (R)a0.y;
         p.vz = (R)a1.x;
@@ -1039,7 +1108,7 @@ __global__ __launch_bounds__(TILE) void k_force(
             const double4 a = s_x[o];
             const int mi = s_mat[o];
             const PairTerms<R> p = pair_terms<R>(G, mt, col_j[g], a, s_vw[0][o], s_vw[1][o],
-                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns);
+                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns, J.xw);
             double dtx, dty, dtz;
             matched += history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
                                         dtz) ? 1u : 0u;
@@ -1158,7 +1227,7 @@ __global__ __launch_bounds__(TILE) void k_pair_force(
         if (own) {
             const int mi = s_mat[o];
             const PairTerms<R> p = pair_terms<R>(G, mt, code, a, s_vw[0][o], s_vw[1][o],
-                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns);
+                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns, J.xw);
             if (history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty, dtz))
                 matched += code < FACE ? 2u : 1u;
             const int pr = mi * MAXMAT + p.mj;
@@ -1351,7 +1420,7 @@ __global__ __launch_bounds__(TILE) void k_fused(
             if (cnt < slots) {
                 const uint64_t g = slab + cnt;
                 const PairTerms<R> p =
-                    pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr, vw, mat, perm, ns);
+                    pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr, vw, mat, perm, ns, J.xw);
                 double dtx, dty, dtz;
                 matched += history_of<false>(orow, p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
                                              dtz) ? 1u : 0u;
@@ -1436,6 +1505,8 @@ __global__ __launch_bounds__(TILE) void k_fused(
                 if (dist < rid) contact(FACE + (uint32_t)f);
             }
         }
+        for (uint32_t k = 0; k < J.nxw; ++k)
+            if (wall_touch(J.xw[k], a.x, a.y, a.z, rid)) contact(FACE + 6u + k);
         if (cnt > slots) {
             // the slab is too small: the step is redone with wider slabs
             atomicOr(&st->err, ERR_CAPACITY);

@@ -88,6 +88,7 @@ struct HostJob {
     bool reported = false;    // finished/failed status already returned by poll
     std::vector<float> r;
     std::vector<uint16_t> mat;
+    std::vector<dem_wall> walls;  // extra walls (P.extra_walls is not kept)
 };
 
 uint64_t tiles_of(uint64_t n) { return (n + TILE - 1) / TILE; }
@@ -140,6 +141,7 @@ struct dem_pool {
     void* pf = nullptr;                   // action-reaction: pair F and n x F per entry
     MatTable* mats = nullptr;
     Job* jobs_d = nullptr;
+    dem_wall* walls_d = nullptr;          // DEM_MAX_WALLS extra walls per job slot
     uint32_t* job_fail = nullptr;
     uint32_t* tile_job = nullptr;
     uint32_t* tile_key = nullptr;
@@ -297,6 +299,19 @@ dem_status validate(const dem_params* P, const dem_material* mats, uint32_t n_ma
     if (P->precision != DEM_PREC_FP64 && P->precision != DEM_PREC_MIXED) return DEM_EINVAL;
     if (P->kn_form != 0 && P->kn_form != 1) return DEM_EINVAL;
     if (!(P->cell_size >= 0.0) || !std::isfinite(P->cell_size)) return DEM_EINVAL;
+    if (P->n_extra_walls > DEM_MAX_WALLS || (P->n_extra_walls && !P->extra_walls)) return DEM_EINVAL;
+    for (uint32_t k = 0; k < P->n_extra_walls; ++k) {
+        const dem_wall& W = P->extra_walls[k];
+        if (W.kind != DEM_WALL_RECT && W.kind != DEM_WALL_SEGMENT) return DEM_EINVAL;
+        if (!finite3(W.p) || !finite3(W.u) || !finite3(W.v)) return DEM_EINVAL;
+        const double uu = W.u[0] * W.u[0] + W.u[1] * W.u[1] + W.u[2] * W.u[2];
+        if (!(uu > 0.0)) return DEM_EINVAL;
+        if (W.kind == DEM_WALL_RECT) {
+            const double vv = W.v[0] * W.v[0] + W.v[1] * W.v[1] + W.v[2] * W.v[2];
+            const double uv = W.u[0] * W.v[0] + W.u[1] * W.v[1] + W.u[2] * W.v[2];
+            if (!(vv > 0.0) || !(std::fabs(uv) <= 1e-12 * std::sqrt(uu * vv))) return DEM_EINVAL;
+        }
+    }
     for (uint32_t k = 0; k < n_mats; ++k) {
         const dem_material& m = mats[k];
         if (!(m.E > 0) || !(m.G > 0) || !(m.density > 0) || !std::isfinite(m.E) ||
@@ -345,7 +360,7 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     b += np * slots * (4 + 2 * 28);    // partner list and two history tables
     if (flags & DEM_FLAG_ACTION_REACTION) b += np * slots * 6 * (fp64 ? 8 : 4);  // pair forces
     b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
-    b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4);
+    b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4 + DEM_MAX_WALLS * sizeof(dem_wall));
     b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
     return b;
 }
@@ -426,6 +441,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc(s, 6 * np * (fp64 ? 8 : 4), &s->fo));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->mats));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->jobs_d));
+    ALLOC_OR_FAIL(dalloc_t(s, (size_t)max_jobs * DEM_MAX_WALLS, &s->walls_d));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->job_fail));
     ALLOC_OR_FAIL(dalloc_t(s, mt, &s->tile_job));
     ALLOC_OR_FAIL(dalloc_t(s, mt, &s->tile_key));
@@ -673,6 +689,10 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     jd.mat = (uint32_t)slot;
     jd.status = JOB_ACTIVE;
     jd.steps_left = steps;
+    jd.nxw = (uint32_t)J.walls.size();
+    jd.xw = s->walls_d + (size_t)slot * DEM_MAX_WALLS;
+    if (!J.walls.empty()) up(s->walls_d + (size_t)slot * DEM_MAX_WALLS, J.walls.data(),
+                             J.walls.size() * sizeof(dem_wall));
     up(s->jobs_d + slot, &jd, sizeof(Job));
     const uint32_t zero = 0;
     up(s->job_fail + slot, &zero, sizeof(zero));
@@ -711,6 +731,8 @@ dem_status prepare_job(const dem_params* params, const dem_material* mats, uint3
     HostJob& J = pj.J;
     J = HostJob();
     J.P = *params;
+    J.walls.assign(params->extra_walls, params->extra_walls + params->n_extra_walls);
+    J.P.extra_walls = nullptr;
     J.mats.assign(mats, mats + n_mats);
     J.n = n;
     J.ntiles = (uint32_t)tiles_of(n);
@@ -1166,7 +1188,7 @@ dem_status write_contacts(dem_pool* s, int slot, std::vector<Contact>& c) {
     for (size_t k = 0; k < c.size(); ++k) {
         if (c[k].i >= n) return DEM_EINVAL;
         if (c[k].j >= n && c[k].j < FACE) return DEM_EINVAL;
-        if (c[k].j >= FACE + 6) return DEM_EINVAL;
+        if (c[k].j >= FACE + 6 + (uint32_t)J.walls.size()) return DEM_EINVAL;
         if (c[k].j == c[k].i) return DEM_EINVAL;
         if (k && c[k].i == c[k - 1].i && c[k].j == c[k - 1].j) return DEM_EINVAL;
         if (!finite3(c[k].dt)) return DEM_EINVAL;

@@ -86,11 +86,22 @@ def contact_overlaps(scene, x, i, j, time):
     out[~face] = r[pi] + r[pj] - np.linalg.norm(d, axis=1)
     f = (j[face] - FACE).astype(np.int64)
     fi = i[face]
-    ax = f // 2
+    box = f < 6
+    ax = np.where(box, f // 2, 0)
     p = x[fi, ax]
     lo = np.asarray(scene.lo, float)[ax]
     hi = np.asarray(scene.hi, float)[ax]
-    out[face] = r[fi] - np.where(f % 2 == 1, hi - p, p - lo)
+    ov = r[fi] - np.where(f % 2 == 1, hi - p, p - lo)
+    # extra walls: distance to the closest point of the rectangle or segment
+    for k in np.nonzero(~box)[0]:
+        wl = scene.extra_walls[f[k] - 6]
+        c = x[fi[k]]
+        pw, u, v = (np.asarray(a, float) for a in (wl.p, wl.u, wl.v))
+        q = pw + np.clip(np.dot(c - pw, u) / np.dot(u, u), 0, 1) * u
+        if wl.kind == 0:
+            q = q + np.clip(np.dot(c - pw, v) / np.dot(v, v), 0, 1) * v
+        ov[k] = r[fi[k]] - np.linalg.norm(q - c)
+    out[face] = ov
     return out
 
 

@@ -47,15 +47,19 @@ def test_status_strings_and_footprint_without_gpu():
 def test_ctypes_layouts_match_the_header(tmp_path):
     prog = tmp_path / "sizes.c"
     prog.write_text('#include "dem.h"\n#include <stdio.h>\n#include <stddef.h>\n'
-                    'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dem_params),'
-                    ' sizeof(dem_material), sizeof(dem_info), offsetof(dem_params, precision),'
-                    ' offsetof(dem_params, max_contacts), offsetof(dem_info, cells));return 0;}\n')
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n",'
+                    ' sizeof(dem_params), sizeof(dem_material), sizeof(dem_info),'
+                    ' offsetof(dem_params, precision), offsetof(dem_params, max_contacts),'
+                    ' offsetof(dem_info, cells), sizeof(dem_wall), offsetof(dem_wall, v),'
+                    ' offsetof(dem_params, extra_walls));return 0;}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [ctypes.sizeof(binding.Params), ctypes.sizeof(binding.Material),
             ctypes.sizeof(binding.Info), binding.Params.precision.offset,
-            binding.Params.max_contacts.offset, binding.Info.cells.offset]
+            binding.Params.max_contacts.offset, binding.Info.cells.offset,
+            ctypes.sizeof(binding.Wall), binding.Wall.v.offset,
+            binding.Params.extra_walls.offset]
     assert got == want
 
 
