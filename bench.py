@@ -91,17 +91,63 @@ def measured_traffic(kernel, precision_tag):
     return None
 
 
+# Peak VALU issue rate: each CU's four SIMDs issue one wave64 VALU
+# instruction every four cycles (16 lanes per cycle), so a CU issues one per
+# cycle: 256 CUs x 2.4 GHz.
+VALU_PEAK = 256 * 2.4e9
+PHASE_KERNELS = {"detect": ("k_detect",), "force": ("k_force",),
+                 "sort": ("k_mov_sort", "k_place"), "reorder": ("k_reorder", "k_tick")}
+
+
+def valu_insts(phase, precision_tag):
+    """VALU wave-instructions per step of a phase (its kernels' SQ_INSTS_VALU
+    per launch, summed) from the committed counter summary, or None when the
+    kernels have changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "valu_dilute_1m.json")
+    src = os.path.join(ROOT, "paper_1503_03553_amd", "csrc", "dem_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernels_source_sha256") != sha:
+        return None
+    tot, found = 0.0, False
+    for k, v in rec["per_launch"].items():
+        base = k.split("<")[0]
+        if base in PHASE_KERNELS.get(phase, ()) and (base != "k_force" or precision_tag in k):
+            tot += v["SQ_INSTS_VALU"]
+            found = True
+    return tot if found else None
+
+
+def valu_of(phase, avg_us, precision_tag):
+    n = valu_insts(phase, precision_tag)
+    if n is None:
+        return None
+    rate = n / (avg_us * 1e-6)
+    return {"insts_per_launch": int(n), "achieved": round(rate / 1e9, 2), "peak": VALU_PEAK / 1e9,
+            "unit": "G wave-instr/s", "frac": round(rate / VALU_PEAK, 4)}
+
+
 def roofline_of(rows, precision_tag="float"):
     dom = max(rows, key=lambda p: rows[p]["avg_us"])
     r = rows[dom]
     return {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(r["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("k_" + dom, precision_tag),
-            "bytes_per_launch": int(r["bytes"]), "avg_launch_us": round(r["avg_us"], 2)}
+            "bytes_per_launch": int(r["bytes"]), "avg_launch_us": round(r["avg_us"], 2),
+            "valu_issue": valu_of(dom, r["avg_us"], precision_tag)}
 
 
-def kernels_of(rows):
-    return {k: {"avg_us": round(v["avg_us"], 2), "GBps": round(v["gbs"], 1)} for k, v in rows.items()}
+def kernels_of(rows, precision_tag="float"):
+    out = {}
+    for k, v in rows.items():
+        va = valu_of(k, v["avg_us"], precision_tag)
+        out[k] = {"avg_us": round(v["avg_us"], 2), "GBps": round(v["gbs"], 1),
+                  "valu_frac": None if va is None else va["frac"]}
+    return out
 
 
 # ------------------------------------------------------------ single sim
@@ -402,7 +448,7 @@ def headline(a, sc, stream, log):
                              "ms_per_step_with_events":
                                  round(f64["seconds_profiled"] / a.steps * 1e3, 4),
                              "roofline": roofline_of(rows64, "double"),
-                             "kernels": kernels_of(rows64)}
+                             "kernels": kernels_of(rows64, "double")}
 
     return out
 
