@@ -234,31 +234,60 @@ def pool_for(scenes, precision, stream, slack_jobs=0, flags=0):
 
 
 def run_batched(scenes, steps, warmup, stream, tune_steps, log):
+    """Autotune, then `steps` timed steps of the whole pool without
+    instrumentation (the throughput), then the same again in a fresh pool
+    with HIP events at the phase boundaries (the kernel durations)."""
     import torch
     from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, PREC_MIXED, tune
     make = lambda c: pool_for(scenes, PREC_MIXED, stream, flags=FLAG_NO_FORCE_OUTPUT)
     t = time.perf_counter()
     best, table = tune.autotune(make, scenes, steps=tune_steps, warmup=2, log=log)
     tune_s = time.perf_counter() - t
-    pool = make(best)
-    tune.fill_pool(pool, scenes, warmup + steps, best)
-    pool.step(warmup)
-    pool.sync()
-    pool.profile(True)
-    pool.profile_read()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pool.step(steps)
-    pool.sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = pool.profile_read()
-    done = pool.poll()
-    pool.close()
-    n = sum(s.n for s in scenes)
-    sec = t1 - t0
-    return dict(seconds=sec, n=n, prof=prof, finished=len(done), best=best, tune_s=tune_s,
-                table=[(c, round(s * 1e3, 4)) for c, s in table])
+    out = {}
+    for profiled in (False, True):
+        pool = make(best)
+        tune.fill_pool(pool, scenes, warmup + steps, best)
+        pool.step(warmup)
+        pool.sync()
+        if profiled:
+            pool.profile(True)
+            pool.profile_read()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pool.step(steps)
+        pool.sync()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if profiled:
+            out["prof"] = pool.profile_read()
+            out["seconds_profiled"] = t1 - t0
+        else:
+            out["seconds"] = t1 - t0
+            out["finished"] = len(pool.poll())
+        pool.close()
+    out.update(n=sum(s.n for s in scenes), best=best, tune_s=tune_s,
+               table=[(c, round(s * 1e3, 4)) for c, s in table])
+    return out
+
+
+def run_one_at_a_time(scenes, precision, steps, warmup, stream):
+    """The same jobs through the plain single-simulation path, one after
+    another: seconds per step of each job alone (no instrumentation), summed."""
+    import torch
+    from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, Sim
+    total = 0.0
+    for sc in scenes:
+        sim = Sim.from_scene(sc, precision=precision, stream=stream, flags=FLAG_NO_FORCE_OUTPUT)
+        sim.step(warmup)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        torch.cuda.synchronize()
+        total += (time.perf_counter() - t0) / steps
+        sim.close()
+    return total
 
 
 # --------------------------------------------------------------- serving
@@ -315,6 +344,8 @@ def main():
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--tune-steps", type=int, default=10)
+    ap.add_argument("--alone-steps", type=int, default=100,
+                    help="steps per job when the batched jobs run one at a time (0 = skip)")
     ap.add_argument("--serve-horizon", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget", type=int, default=8_000_000)
@@ -455,19 +486,32 @@ def headline(a, sc, stream, log):
 
 def run_others(a, out, sc, batch, serve_in, stream, log):
     if batch:
+        from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
         b = run_batched(batch, a.batch_steps, a.warmup, stream, a.tune_steps, log)
         brows = phase_rows(b["prof"], b["n"], 0, 0, False, 24)
-        out["batched"] = {"value": round(b["n"] * a.batch_steps / b["seconds"], 1),
+        value = b["n"] * a.batch_steps / b["seconds"]
+        out["batched"] = {"value": round(value, 1),
                           "unit": "particle-steps/s",
                           "jobs": len(batch), "particles": b["n"], "steps": a.batch_steps,
                           "ms_per_step": round(b["seconds"] / a.batch_steps * 1e3, 4),
+                          "ms_per_step_with_events":
+                              round(b["seconds_profiled"] / a.batch_steps * 1e3, 4),
                           "finished": b["finished"],
                           "autotuned": b["best"], "tune_seconds": round(b["tune_s"], 2),
                           "tune_table_ms_per_step": b["table"],
                           "kernels_avg_us": {k: round(v["avg_us"], 2) for k, v in brows.items()}}
         if "fp64_plain" in out:
-            out["batched"]["vs_fp64_plain"] = round(out["batched"]["value"] /
-                                                    out["fp64_plain"]["value"], 3)
+            out["batched"]["vs_fp64_plain"] = round(value / out["fp64_plain"]["value"], 3)
+        if a.alone_steps:
+            # the same 256 jobs through the plain single-simulation path
+            alone = {}
+            for name, prec in (("fp64", PREC_FP64), ("mixed", PREC_MIXED)):
+                sec = run_one_at_a_time(batch, prec, a.alone_steps, 5, stream)
+                alone[name] = {"value": round(b["n"] / sec, 1), "unit": "particle-steps/s",
+                               "ms_per_step_all_jobs": round(sec * 1e3, 4)}
+                log("alone %s: %.3f ms per step of all jobs" % (name, sec * 1e3))
+            out["batched"]["same_jobs_one_at_a_time"] = dict(alone, steps=a.alone_steps)
+            out["batched"]["vs_fp64_plain_same_jobs"] = round(value / alone["fp64"]["value"], 3)
 
     if serve_in is not None:
         templates, arr, tmpl, steps = serve_in
