@@ -141,10 +141,12 @@ def roofline_of(rows, precision_tag="float"):
             "valu_issue": valu_of(dom, r["avg_us"], precision_tag)}
 
 
-def kernels_of(rows, precision_tag="float"):
+def kernels_of(rows, precision_tag="float", headline=True):
+    """Per-phase duration and algorithmic GB/s; VALU issue utilisation only
+    for the headline workload, whose instruction counts were taken."""
     out = {}
     for k, v in rows.items():
-        va = valu_of(k, v["avg_us"], precision_tag)
+        va = valu_of(k, v["avg_us"], precision_tag) if headline else None
         out[k] = {"avg_us": round(v["avg_us"], 2), "GBps": round(v["gbs"], 1),
                   "valu_frac": None if va is None else va["frac"]}
     return out
@@ -355,9 +357,12 @@ def main():
                     help="first run a plain device-to-device copy of this many MiB 5 times "
                          "(reference reads/writes for HBM traffic counters)")
     ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--dense-n", type=int, default=8_000_000)
+    ap.add_argument("--dense-steps", type=int, default=100)
     ap.add_argument("--ablation-sizes", default="131072,524288,2097152")
     ap.add_argument("--ablation-steps", type=int, default=20)
-    ap.add_argument("--only", choices=("all", "single", "batch", "serve", "ablation"),
+    ap.add_argument("--only", choices=("all", "single", "batch", "serve", "ablation", "dense"),
                     default="all",
                     help="run one part only (for profiling); the JSON line then lacks the others")
     ap.add_argument("--verbose", action="store_true")
@@ -368,6 +373,7 @@ def main():
         a.no_batch = a.only != "batch"
         a.no_serve = a.only != "serve"
         a.no_ablation = a.only != "ablation"
+        a.no_dense = a.only != "dense"
     if a.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(got --gpus %d)" % a.gpus, file=sys.stderr)
@@ -392,6 +398,11 @@ def main():
                                   [(0, m, int(sizes[m])) for m in range(a.batch_jobs)])
         log("batched input: %d jobs, %d spheres in %.1fs" % (len(batch), sum(s.n for s in batch),
                                                               time.perf_counter() - t))
+    dense = None
+    if not a.no_dense:
+        t = time.perf_counter()
+        dense = gen.config_dense_shear(n=a.dense_n)
+        log("dense input: %d spheres in %.1fs" % (dense.n, time.perf_counter() - t))
     serve_in = None
     if not a.no_serve:
         t = time.perf_counter()
@@ -417,7 +428,7 @@ def main():
     out = {}
     if a.only in ("all", "single"):
         out = headline(a, sc, stream, log)
-    run_others(a, out, sc, batch, serve_in, stream, log)
+    run_others(a, out, sc, batch, serve_in, stream, log, dense)
     print(json.dumps(out), flush=True)
 
 
@@ -484,7 +495,25 @@ def headline(a, sc, stream, log):
     return out
 
 
-def run_others(a, out, sc, batch, serve_in, stream, log):
+def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
+    if dense is not None:
+        # the 8M dense sheared pack: throughput and contact-table churn
+        from paper_1503_03553_amd import PREC_MIXED
+        r = run_single(dense, PREC_MIXED, a.dense_steps, a.warmup, stream)
+        rows = phase_rows(r["prof"], dense.n, r["contacts"], r["contacts_old"], False,
+                          r["info"]["key_bits"])
+        m = r["contacts"]
+        out["dense_shear_8m"] = {
+            "value": round(dense.n * a.dense_steps / r["seconds"], 1), "unit": "particle-steps/s",
+            "particles": dense.n, "steps": a.dense_steps,
+            "ms_per_step": round(r["seconds"] / a.dense_steps * 1e3, 4),
+            "workload": "%d spheres, phi %.2f, Lees-Edwards shear %g/s, mixed precision" % (
+                dense.n, dense.meta.get("phi", 0.0), dense.shear_rate),
+            "contacts_per_particle": round(m / dense.n, 4),
+            "churn_per_step": {"created": round(m - r["matched"], 1),
+                               "broken": round(r["contacts_old"] - r["matched"], 1),
+                               "created_frac": round((m - r["matched"]) / max(m, 1), 5)},
+            "kernels": kernels_of(rows, headline=False)}
     if batch:
         from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
         b = run_batched(batch, a.batch_steps, a.warmup, stream, a.tune_steps, log)
