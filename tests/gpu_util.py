@@ -238,3 +238,16 @@ SCENES = {
                                           walls=gen.WALL_ALL & ~3, periodic=1),
     "materials": lambda: gen.scene_random(seed=25, n=1000, phi=0.22, p_touch=0.7, n_materials=3),
 }
+
+
+def symmetric_history(sc, seed):
+    """random_history with both directions of every particle pair present:
+    the lower id's entry is kept and the other direction carries its
+    negative, as in a history the method itself builds."""
+    i, j, dt = random_history(sc, seed)
+    part = j < FACE
+    own = part & (i < j)
+    keep_i = np.concatenate([i[~part], i[own], j[own]])
+    keep_j = np.concatenate([j[~part], j[own], i[own]])
+    keep_dt = np.concatenate([dt[~part], dt[own], -dt[own]])
+    return keep_i.astype(np.uint32), keep_j.astype(np.uint32), keep_dt

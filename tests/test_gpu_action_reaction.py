@@ -14,26 +14,13 @@ import pytest
 
 import gen
 import oracle
-from gpu_util import FACE, SCENES, random_history, say, step_parity, trajectory_parity
+from gpu_util import SCENES, say, step_parity, symmetric_history, trajectory_parity
 from paper_1503_03553_amd import (FLAG_ACTION_REACTION, FLAG_FUSED, PREC_FP64, PREC_MIXED,
                                   DemError, Pool, Sim)
 
 pytestmark = pytest.mark.gpu
 
 PRECS = [("fp64", PREC_FP64), ("mixed", PREC_MIXED)]
-
-
-def symmetric_history(sc, seed):
-    """random_history with both directions of every particle pair present:
-    the lower id's entry is kept and the other direction carries its
-    negative, as in a history the method itself builds."""
-    i, j, dt = random_history(sc, seed)
-    part = j < FACE
-    own = part & (i < j)
-    keep_i = np.concatenate([i[~part], i[own], j[own]])
-    keep_j = np.concatenate([j[~part], j[own], i[own]])
-    keep_dt = np.concatenate([dt[~part], dt[own], -dt[own]])
-    return keep_i.astype(np.uint32), keep_j.astype(np.uint32), keep_dt
 
 
 @pytest.mark.parametrize("prec_name,prec", PRECS)

@@ -12,7 +12,8 @@ import pytest
 
 import gen
 import oracle
-from gpu_util import FACE, random_history, say, step_parity, trajectory_parity
+from gpu_util import (FACE, random_history, say, step_parity, symmetric_history,
+                      trajectory_parity)
 from paper_1503_03553_amd import FLAG_FUSED, PREC_FP64, PREC_MIXED, DemError, Pool, Sim
 
 pytestmark = pytest.mark.gpu
@@ -147,3 +148,11 @@ def test_malformed_walls_are_rejected():
     sc = base.copy()
     sc.extra_walls = [good] * 10
     Sim.from_scene(sc, precision=PREC_MIXED).close()
+
+
+def test_walls_action_reaction_one_step_parity():
+    say("case walls action-reaction")
+    from paper_1503_03553_amd import FLAG_ACTION_REACTION
+    sc = wall_scene(36)
+    step_parity(sc, PREC_FP64, history=symmetric_history(sc, seed=8), tol=1e-9,
+                flags=FLAG_ACTION_REACTION)
