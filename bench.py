@@ -200,13 +200,15 @@ def run_ablation(sizes, steps, warmup, stream, log):
     the fused kernel plus the clearing of the old cell bounds for the fused
     one, detect + pair forces + sums for action-reaction."""
     import gen
-    from paper_1503_03553_amd import FLAG_ACTION_REACTION, FLAG_FUSED, PREC_MIXED
+    from paper_1503_03553_amd import (FLAG_ACTION_REACTION, FLAG_FUSED, FLAG_THREAD_SPLIT,
+                                      PREC_MIXED)
     rows = []
     for n in sizes:
         for regime in ("dense", "sparse"):
             sc = gen.config_ablation(n, regime)
             row = {"n": sc.n, "regime": regime}
             for name, flag in (("split", 0), ("fused", FLAG_FUSED),
+                               ("thread_split", FLAG_THREAD_SPLIT),
                                ("action_reaction", FLAG_ACTION_REACTION)):
                 r = run_single(sc, PREC_MIXED, steps, warmup, stream, flags=flag)
                 ph = {p: ms / c * 1e3 for p, (ms, c) in r["prof"].items() if c}
@@ -218,6 +220,8 @@ def run_ablation(sizes, steps, warmup, stream, log):
                                                     row["split"]["collide_us"], 3)
             row["step_fused_over_split"] = round(row["fused"]["ms_per_step"] /
                                                  row["split"]["ms_per_step"], 3)
+            row["collide_thread_split_over_split"] = round(row["thread_split"]["collide_us"] /
+                                                           row["split"]["collide_us"], 3)
             row["step_action_reaction_over_split"] = round(
                 row["action_reaction"]["ms_per_step"] / row["split"]["ms_per_step"], 3)
             log("ablation %s" % json.dumps(row))
@@ -566,6 +570,7 @@ def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
         out["ablation_fused_vs_split"] = {
             "what": "collide = contact search + force kernels per step, mixed precision; "
                     "fused = the single loop before the split of section 3.4; "
+                    "thread_split = that split within each particle's thread; "
                     "action_reaction = each pair's force once, applied to both",
             "steps": a.ablation_steps, "warmup": 5,
             "rows": run_ablation(sizes, a.ablation_steps, 5, stream, log)}

@@ -130,6 +130,12 @@ typedef struct {
                                        history keeps one displacement per pair;
                                        dem_get_contacts reports the other direction as
                                        its negative.  Not with DEM_FLAG_FUSED */
+#define DEM_FLAG_THREAD_SPLIT 16u   /* the split as section 3.4 has it: each particle's
+                                       thread runs the contact law over the contacts
+                                       its first loop found, with no compaction across
+                                       the workgroup; same results as the default path.
+                                       For comparison; at most one of DEM_FLAG_FUSED,
+                                       DEM_FLAG_ACTION_REACTION and this flag */
 
 /* Diagnostics of a simulation (dem_get_info). */
 typedef struct {

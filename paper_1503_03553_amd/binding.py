@@ -21,6 +21,7 @@ FLAG_NO_FORCE_OUTPUT = 1
 FLAG_RADIX_SORT = 2
 FLAG_FUSED = 4
 FLAG_ACTION_REACTION = 8
+FLAG_THREAD_SPLIT = 16
 NPHASE = 4
 PHASES = ("detect", "force", "sort", "reorder")
 

@@ -176,6 +176,14 @@ void launch_action_reaction(const PoolView& P, bool fp64, const Sorted& S, const
                             uint32_t* tab_pid_new, double* tab_dt_new, uint64_t cap, void* pf,
                             uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
                             uint32_t* oldkeys, uint2* movers, hipStream_t s);
+// The split as the paper has it: each particle's thread runs over its own
+// contacts (no compaction across the workgroup).
+void launch_force_thread(const PoolView& P, bool fp64, const Sorted& S, const State& X,
+                         const State& Y, const uint2* rows, const uint32_t* col_j,
+                         const uint2* rows_old, const uint32_t* perm, const uint32_t* tab_pid_old,
+                         const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
+                         uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
+                         uint32_t* oldkeys, uint2* movers, hipStream_t s);
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
                        const uint2* movers, unsigned long long* mk, uint32_t* mp,
                        uint32_t* keys_s, uint32_t* vals_s, hipStream_t s);

@@ -1143,6 +1143,95 @@ __global__ __launch_bounds__(TILE) void k_force(
                    cells, true, keys, vals, fo, oldkeys, movers);
 }
 
+// The split as the paper has it (section 3.4): the second loop runs in the
+// particle's own thread over the contacts its first loop found, with no
+// compaction across the workgroup, so a wavefront takes as long as its lane
+// with the most contacts.  Kept as the comparison for the compacted force
+// kernel; the per-contact terms and the summation order are the same.
+template <typename R>
+__global__ __launch_bounds__(TILE) void k_force_thread(
+    const double4* __restrict__ xr, const double4* __restrict__ xr_x,
+    const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
+    double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
+    const uint2* __restrict__ rows, const uint32_t* __restrict__ col_j,
+    const uint2* __restrict__ rows_old, const uint32_t* __restrict__ perm,
+    const uint32_t* __restrict__ tab_pid_old, const double* __restrict__ tab_dt_old,
+    uint32_t* __restrict__ tab_pid_new, double* __restrict__ tab_dt_new, uint64_t cap,
+    uint2* __restrict__ cells, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    R* __restrict__ fo, PoolView P, const Job* __restrict__ jobs, uint32_t* __restrict__ oldkeys,
+    uint2* __restrict__ movers) {
+    __shared__ uint32_t s_flag;
+    Status* st = P.st;
+    if (skip_if_error(st, &s_flag)) return;
+    const int t = threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t p0 = tile * TILE;
+    const uint32_t ns = P.ns;
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) {
+        idle_tile(P, jobs, tile, jb, t, xr_x, vw, mat, xr_b, vw_b, mat_b, perm, keys, vals, oldkeys,
+                  movers != nullptr);
+        return;
+    }
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    const MatTable* __restrict__ mt = P.mats + J.mat;
+    const uint32_t i = p0 + t;
+    const uint32_t n = J.p0 + J.n;
+    if (i >= n) {
+        keys[i] = P.tile_key[tile] | P.lmask;
+        vals[i] = i;
+        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
+    }
+    R acc[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t matched = 0;
+    double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0;
+    int mi = 0;
+    uint2 orow = make_uint2(0, 0);
+    if (i < n) {
+        const uint32_t q = perm[i];
+        const uint2 row = rows[i];
+        orow = rows_old[q];
+        a = xr[i];
+        a0 = vw[q];
+        a1 = vw[ns + q];
+        a2 = vw[2 * (size_t)ns + q];
+        mi = mat ? mat[q] : 0;
+        if ((uint64_t)row.x + row.y > cap) {  // cannot happen after a clean detect
+            atomicOr(&st->err, ERR_CAPACITY);
+        } else {
+            for (uint32_t k = row.x; k < row.x + row.y; ++k) {
+                const uint32_t code = col_j[k];
+                const PairTerms<R> p = pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr, vw, mat,
+                                                     perm, ns, J.xw);
+                double dtx, dty, dtz;
+                matched += history_of<true>(orow, p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
+                                            dtz) ? 1u : 0u;
+                const int pr = mi * MAXMAT + p.mj;
+                R F[3], T[3];
+                contact_law<R>(p.nx, p.ny, p.nz, p.dn, p.vx, p.vy, p.vz, p.rwx, p.rwy, p.rwz, dtx,
+                               dty, dtz, p.rs, p.ms, (R)meta_r(a.w), (R)mt->kn_pref[pr],
+                               (R)mt->kt_pref[pr], (R)mt->alpha[pr], (R)mt->mu[pr], G.dt, F, T);
+                tab_pid_new[k] = p.pid;
+                tab_dt_new[k] = dtx;
+                tab_dt_new[cap + k] = dty;
+                tab_dt_new[2 * cap + k] = dtz;
+                acc[0] += F[0];
+                acc[1] += F[1];
+                acc[2] += F[2];
+                acc[3] += T[0];
+                acc[4] += T[1];
+                acc[5] += T[2];
+            }
+        }
+    }
+    finish_tile<R>(P, G, mt, tile, jb, t, i, n, a, a0, a1, a2, mi, acc, true, matched, orow.y,
+                   nullptr, xr_b, vw_b, mat_b, cells + J.cell_base, true, keys, vals, fo, oldkeys,
+                   movers);
+}
+
 // ------------------------------------------------------- action-reaction
 // Variant that computes each particle pair once (the scheme section 3.3
 // avoids): the particle with the lower id owns the pair.  First kernel: one
@@ -2015,6 +2104,26 @@ void launch_action_reaction(const PoolView& P, bool fp64, const Sorted& S, const
         DEM_AR(float);
     }
 #undef DEM_AR
+}
+
+void launch_force_thread(const PoolView& P, bool fp64, const Sorted& S, const State& X,
+                         const State& Y, const uint2* rows, const uint32_t* col_j,
+                         const uint2* rows_old, const uint32_t* perm, const uint32_t* tab_pid_old,
+                         const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
+                         uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
+                         uint32_t* oldkeys, uint2* movers, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
+    if (fp64)
+        hipLaunchKernelGGL(k_force_thread<double>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw,
+                           X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,
+                           tab_dt_old, tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo,
+                           P, P.jobs, oldkeys, movers);
+    else
+        hipLaunchKernelGGL(k_force_thread<float>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw,
+                           X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,
+                           tab_dt_old, tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo,
+                           P, P.jobs, oldkeys, movers);
 }
 
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,

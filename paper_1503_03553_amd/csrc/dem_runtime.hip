@@ -380,9 +380,13 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     *out = nullptr;
     if (max_jobs < 1 || slots < 1) return DEM_EINVAL;
     if (flags & ~(DEM_FLAG_NO_FORCE_OUTPUT | DEM_FLAG_RADIX_SORT | DEM_FLAG_FUSED |
-                  DEM_FLAG_ACTION_REACTION))
+                  DEM_FLAG_ACTION_REACTION | DEM_FLAG_THREAD_SPLIT))
         return DEM_EINVAL;
-    if ((flags & DEM_FLAG_FUSED) && (flags & DEM_FLAG_ACTION_REACTION)) return DEM_EINVAL;
+    {
+        // at most one force-path variant
+        const uint32_t v = flags & (DEM_FLAG_FUSED | DEM_FLAG_ACTION_REACTION | DEM_FLAG_THREAD_SPLIT);
+        if (v & (v - 1)) return DEM_EINVAL;
+    }
     const uint64_t mt = std::max<uint64_t>(1, tiles_of(max_particles));
     if (mt * TILE > MAX_ENTRIES || mt * TILE * slots > MAX_ENTRIES) return DEM_EINVAL;
     dem_pool* s = new (std::nothrow) dem_pool();
@@ -891,6 +895,11 @@ dem_status enqueue_step(dem_pool* s, int o) {
                                s->cap, s->pf, s->cells, s->keys, s->vals, fo,
                                merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr,
                                s->stream);
+    else if (s->flags & DEM_FLAG_THREAD_SPLIT)
+        launch_force_thread(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
+                            s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap,
+                            s->cells, s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
+                            merge ? s->movers : nullptr, s->stream);
     else if (fused)
         launch_fused(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->slots,

@@ -127,3 +127,37 @@ def test_fused_pool_jobs_equal_jobs_alone():
                 assert np.array_equal(got[key], ref[key]), "job n=%d: %s" % (s.n, key)
     finally:
         pool.close()
+
+
+# ------------------------------------------------ the paper's per-thread split
+@pytest.mark.parametrize("prec_name,prec", PRECS)
+@pytest.mark.parametrize("name", ["random3000", "shear1500", "materials"])
+def test_thread_split_equals_compacted_split(name, prec_name, prec):
+    # the same per-contact terms summed in the same order: the per-thread
+    # second loop gives the compacted force kernel's results up to the
+    # rounding the compiler's contraction choices may change
+    say("case thread split", name, prec_name)
+    from paper_1503_03553_amd import FLAG_THREAD_SPLIT
+    sc = SCENES[name]()
+    dt = oracle.Sim(sc, mode=1).dt
+    runs = []
+    for flags in (0, FLAG_THREAD_SPLIT):
+        g = Sim.from_scene(sc, precision=prec, dt=dt, flags=flags)
+        g.step(25)
+        runs.append((g.get_state(), g.get_contacts()))
+        g.close()
+    (a, ca), (b, cb) = runs
+    assert np.array_equal(ca[0], cb[0]) and np.array_equal(ca[1], cb[1])
+    tol = 1e-9 if prec == PREC_FP64 else 1e-5
+    assert np.abs(ca[2] - cb[2]).max(initial=0.0) <= tol * max(np.abs(ca[2]).max(), 1e-300)
+    for k in ("x", "v", "w", "F", "T"):
+        scale = max(np.abs(a[k]).max(), 1e-300)
+        assert np.abs(a[k] - b[k]).max() <= tol * scale, k
+
+
+def test_thread_split_one_step_parity():
+    say("case thread split oracle")
+    from paper_1503_03553_amd import FLAG_THREAD_SPLIT
+    sc = SCENES["random3000"]()
+    step_parity(sc, PREC_MIXED, history=random_history(sc, seed=9), tol=1e-5,
+                allow_cap_flips=0.01, flags=FLAG_THREAD_SPLIT)
