@@ -35,9 +35,15 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s at 1M (FP32 batched vs FP64 plain); p50/p99 job latency"
 
 
-def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False):
-    """Algorithmic HBM bytes of one launch (each record counted once)."""
+def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True):
+    """Algorithmic HBM bytes of one launch (each record counted once); `half`:
+    the default half search, whose lists the force kernel turns into rows
+    (else the full search writes the rows)."""
     if phase == "detect":
+        if half:
+            # own FP32 record 16 + FP64 position 32, cell bounds 8 (as
+            # below); per contact: list entry 8 and its counter 4
+            return 56 * n + 12 * m
         # own FP32 record 16 + FP64 position 32, 9 cell-row bounds read as
         # 27 cells x 8 (cache-resident, counted once per particle: 8), row
         # write 8; partner index 4 per contact
@@ -47,9 +53,12 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False):
         # permutation 4, new row 8, cell bound 4; writes: integrated state 80,
         # key, index and key before the step 12, F/T 24 (48 in FP64) when
         # stored; per contact: partner index 4, partner permutation 4, new
-        # history 28; per old contact 28
+        # history 28; per old contact 28.  With the half search also the list
+        # counter read and reset 8 per particle, and per contact the list
+        # entry 8 and the partner index written 4.
         fo = (48 if fp64 else 24) if force_out else 0
-        return (104 + 92 + fo) * n + 36 * m + 28 * m_old
+        extra = 8 * n + 12 * m if half else 0
+        return (104 + 92 + fo) * n + 36 * m + 28 * m_old + extra
     if phase == "sort":
         passes = max(1, (key_bits + 7) // 8)
         return 20 * n * passes
@@ -60,13 +69,13 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False):
     return 0
 
 
-def phase_rows(prof, n, m, m_old, fp64, key_bits):
+def phase_rows(prof, n, m, m_old, fp64, key_bits, half=True):
     rows = {}
     for ph, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
         avg_s = ms / cnt * 1e-3
-        b = kernel_bytes(ph, n, m, m_old, fp64, key_bits)
+        b = kernel_bytes(ph, n, m, m_old, fp64, key_bits, half=half)
         rows[ph] = dict(avg_us=avg_s * 1e6, bytes=b, gbs=b / avg_s / 1e9)
     return rows
 
@@ -95,7 +104,7 @@ def measured_traffic(kernel, precision_tag):
 # instruction every four cycles (16 lanes per cycle), so a CU issues one per
 # cycle: 256 CUs x 2.4 GHz.
 VALU_PEAK = 256 * 2.4e9
-PHASE_KERNELS = {"detect": ("k_detect",), "force": ("k_force",),
+PHASE_KERNELS = {"detect": ("k_detect", "k_detect_half"), "force": ("k_force",),
                  "sort": ("k_mov_sort", "k_place"), "reorder": ("k_reorder", "k_tick")}
 
 
@@ -195,19 +204,23 @@ def run_single(sc, precision, steps, warmup, stream, flags=0):
 def run_ablation(sizes, steps, warmup, stream, log):
     """The fused single loop (section 3.4; the comparison of section 4) and
     the action-reaction variant (section 3.3) against the split path on the
-    grid inputs of gen.config_ablation, in mixed precision.  "collide" is the
-    contact search plus the force kernels: detect + force for the split path,
-    the fused kernel plus the clearing of the old cell bounds for the fused
-    one, detect + pair forces + sums for action-reaction."""
+    grid inputs of gen.config_ablation, in mixed precision.  "split" is the
+    split with the full per-particle search of Algorithm 1, as the variants
+    have it; "half_search" the default path (each pair tested once).
+    "collide" is the contact search plus the force kernels: detect + force
+    for the split paths, the fused kernel plus the clearing of the old cell
+    bounds for the fused one, detect + pair forces + sums for
+    action-reaction."""
     import gen
-    from paper_1503_03553_amd import (FLAG_ACTION_REACTION, FLAG_FUSED, FLAG_THREAD_SPLIT,
-                                      PREC_MIXED)
+    from paper_1503_03553_amd import (FLAG_ACTION_REACTION, FLAG_FULL_DETECT, FLAG_FUSED,
+                                      FLAG_THREAD_SPLIT, PREC_MIXED)
     rows = []
     for n in sizes:
         for regime in ("dense", "sparse"):
             sc = gen.config_ablation(n, regime)
             row = {"n": sc.n, "regime": regime}
-            for name, flag in (("split", 0), ("fused", FLAG_FUSED),
+            for name, flag in (("split", FLAG_FULL_DETECT), ("half_search", 0),
+                               ("fused", FLAG_FUSED),
                                ("thread_split", FLAG_THREAD_SPLIT),
                                ("action_reaction", FLAG_ACTION_REACTION)):
                 r = run_single(sc, PREC_MIXED, steps, warmup, stream, flags=flag)
@@ -222,6 +235,8 @@ def run_ablation(sizes, steps, warmup, stream, log):
                                                  row["split"]["ms_per_step"], 3)
             row["collide_thread_split_over_split"] = round(row["thread_split"]["collide_us"] /
                                                            row["split"]["collide_us"], 3)
+            row["step_half_search_over_split"] = round(row["half_search"]["ms_per_step"] /
+                                                       row["split"]["ms_per_step"], 3)
             row["step_action_reaction_over_split"] = round(
                 row["action_reaction"]["ms_per_step"] / row["split"]["ms_per_step"], 3)
             log("ablation %s" % json.dumps(row))
@@ -477,11 +492,20 @@ def headline(a, sc, stream, log):
     from paper_1503_03553_amd import FLAG_ACTION_REACTION
     ar = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_ACTION_REACTION)
     rows_ar = phase_rows(ar["prof"], n, ar["contacts"], ar["contacts_old"], False,
-                         ar["info"]["key_bits"])
+                         ar["info"]["key_bits"], half=False)
     out["action_reaction"] = {"value": round(n * a.steps / ar["seconds"], 1),
                               "unit": "particle-steps/s",
                               "ms_per_step": round(ar["seconds"] / a.steps * 1e3, 4),
                               "phases_us": {k: round(v["avg_us"], 2) for k, v in rows_ar.items()}}
+    # the full per-particle search of Algorithm 1 in place of the half search
+    from paper_1503_03553_amd import FLAG_FULL_DETECT
+    fd = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_FULL_DETECT)
+    rows_fd = phase_rows(fd["prof"], n, fd["contacts"], fd["contacts_old"], False,
+                         fd["info"]["key_bits"], half=False)
+    out["full_detect"] = {"value": round(n * a.steps / fd["seconds"], 1),
+                          "unit": "particle-steps/s",
+                          "ms_per_step": round(fd["seconds"] / a.steps * 1e3, 4),
+                          "kernels": kernels_of(rows_fd, headline=False)}
 
     if not a.no_fp64:
         f64 = run_single(sc, PREC_FP64, a.steps, a.warmup, stream)

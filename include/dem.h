@@ -136,6 +136,14 @@ typedef struct {
                                        the workgroup; same results as the default path.
                                        For comparison; at most one of DEM_FLAG_FUSED,
                                        DEM_FLAG_ACTION_REACTION and this flag */
+#define DEM_FLAG_FULL_DETECT 32u    /* contact search as Algorithm 1 (section 3.3) has
+                                       it: each particle scans its whole 27-cell stencil
+                                       and writes its own row.  The default scans the upper half of the
+                                       stencil, so each pair is tested once, and enters
+                                       each contact in both particles' rows; both give
+                                       the same rows.  DEM_FLAG_FUSED,
+                                       DEM_FLAG_ACTION_REACTION and DEM_FLAG_THREAD_SPLIT
+                                       always use the full search */
 
 /* Diagnostics of a simulation (dem_get_info). */
 typedef struct {

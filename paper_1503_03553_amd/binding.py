@@ -22,6 +22,7 @@ FLAG_RADIX_SORT = 2
 FLAG_FUSED = 4
 FLAG_ACTION_REACTION = 8
 FLAG_THREAD_SPLIT = 16
+FLAG_FULL_DETECT = 32
 NPHASE = 4
 PHASES = ("detect", "force", "sort", "reorder")
 

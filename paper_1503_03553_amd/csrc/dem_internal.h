@@ -184,6 +184,23 @@ void launch_force_thread(const PoolView& P, bool fp64, const Sorted& S, const St
                          const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
                          uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
                          uint32_t* oldkeys, uint2* movers, hipStream_t s);
+// Contact search testing each pair once (the upper half of each particle's
+// cell stencil), appending (position, partner id) to both particles'
+// adjacency lists: slot k of particle p at adj[k * P.ns + p], kmax slots
+// (8, 16 or 32; adj holds kmax * P.ns entries), deg[p] the list length (zero
+// on entry; launch_force_half reads and resets it).
+void launch_detect_half(const PoolView& P, int kmax, const Sorted& S, const uint2* cells,
+                        uint32_t* deg, uint2* adj, hipStream_t s);
+// The force kernel over the lists of launch_detect_half: writes the rows and
+// partner list of the step (rows, col_j with `slots` entries per particle of
+// a tile's region) from the lists, then runs as launch_force.
+void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, const State& X,
+                       const State& Y, uint32_t* deg, const uint2* adj, uint2* rows,
+                       uint32_t* col_j, uint32_t slots, const uint2* rows_old,
+                       const uint32_t* perm, const uint32_t* tab_pid_old,
+                       const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
+                       uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
+                       uint32_t* oldkeys, uint2* movers, hipStream_t s);
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
                        const uint2* movers, unsigned long long* mk, uint32_t* mp,
                        uint32_t* keys_s, uint32_t* vals_s, hipStream_t s);

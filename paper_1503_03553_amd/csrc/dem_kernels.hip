@@ -227,16 +227,25 @@ __device__ inline void merge_range(uint2 c, uint32_t& lo, uint32_t& hi) {
 
 // Candidate ranges of the particle at a (radius ri), written to col[k * stride]
 // (the lane's column of a range table); returns their number and, with
-// `count`, adds up their lengths there.  The lane scans the 27 cells
-// around the particle as 9 contiguous ranges: in each (y, z) row the three
+// `count`, adds up their lengths there.  The lane scans the 27 cells around
+// the particle as 9 contiguous ranges: in each (y, z) row the three
 // x-neighbouring cells are consecutive cell keys (plus, across a periodic x
 // boundary, one wrapped cell).  All 27 cell bounds are loaded before any is
 // used.
-template <bool PER>
+//
+// HALF: only the upper half of the stencil, so that a pair of cells is
+// scanned from one of its two cells: the rows one cell up in z, the row one
+// cell up in y in the particle's own z layer, and in its own row the cell one
+// up in x and the positions of its own cell above `self` (the particle's own
+// position).  Cell offsets between two particles are exact negatives of each
+// other, so every pair of particles in neighbouring cells is scanned from
+// exactly one of its two particles.
+template <bool PER, bool HALF = false>
 __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4& a, double ri,
                                                      const uint2* __restrict__ cells,
                                                      uint2* col, int stride,
-                                                     uint32_t* count = nullptr) {
+                                                     uint32_t* count = nullptr,
+                                                     uint32_t self = 0) {
     const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
     // without periodic jobs in the pool the wrap and shear code compiles away
     const bool px = PER && (G.periodic & 1u), py = PER && (G.periodic & 2u),
@@ -296,7 +305,9 @@ __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4
     for (int k = 0; k < 9; ++k) {
         const int oz = k / 3, oy = k % 3;
         const double rx2 = reach2 - gy2[oy] - gz2[oz];
-        const bool ok = oky[oy] && okz[oz] && rx2 > 0.0;
+        const bool upper = oz == 2 || (oz == 1 && oy == 2);
+        const bool own = oz == 1 && oy == 1;
+        const bool ok = oky[oy] && okz[oz] && rx2 > 0.0 && (!HALF || upper || own);
         int cxq = cx;
         bool xprune = true;
         if (le && ky[oy] != 0) {
@@ -311,7 +322,7 @@ __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4
         }
         int xl = cxq - 1, xh = cxq + 1;
         okm[k] = ok;
-        okl[k] = ok && !(xprune && dl2 >= rx2);
+        okl[k] = ok && !(xprune && dl2 >= rx2) && !(HALF && own);
         okh[k] = ok && !(xprune && dh2 >= rx2);
         wrl[k] = wrh[k] = false;
         if (xl < 0) {
@@ -341,6 +352,9 @@ __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4
         merge_range(m, lo, hi);
         if (wrl[k]) merge_range(l, lo2, hi2); else merge_range(l, lo, hi);
         if (wrh[k]) merge_range(h, lo2, hi2); else merge_range(h, lo, hi);
+        // own row of the half stencil: the own cell and, consecutive after
+        // it, the unwrapped cell up in x; the wrapped one is in lo2..hi2
+        if (HALF && k == 4) lo = lo < self + 1 ? self + 1 : lo;
         if (hi > lo) {
             col[(nw++) * stride] = make_uint2(lo, hi);
             if (count) *count += hi - lo;
@@ -667,6 +681,150 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
                                     s_winpid + t, DTILE, J.xw, J.nxw);
     }
     write_rows<KMAX>(P, tile, t, i, act, cnt, s_j, s_excl, s_w, &s_base, rows, col_j, slots);
+}
+
+// ------------------------------------------------------------ half detect
+// Contact search that tests each pair once: the lane of a particle walks the
+// upper half of its cell stencil (the half-shell of candidate_ranges, about
+// 13.5 of the 27 cells for every particle alike, so the lanes of a wave stay
+// balanced).  The contact test is symmetric in the two particles (the image
+// shift is odd in the separation, the distance test even), so every touching
+// pair is found exactly once, from one of its two particles.  Each contact goes into
+// both particles' adjacency lists as (position, partner id) with an atomic
+// slot counter per particle; slot k of every particle's list is one array
+// (adj[k * ns + p], KMAX slots), so the lists of neighbouring particles share
+// cache lines and are read coalesced.  Box faces and extra walls go into the
+// particle's own list.  The force kernel (k_force with HK) turns the lists
+// into rows ordered by partner id: the rows of the full search.
+template <int KMAX, bool PER>
+__global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __restrict__ jobs,
+                                                       const double4* __restrict__ xr,
+                                                       const float4* __restrict__ xf,
+                                                       const uint2* __restrict__ cells,
+                                                       uint32_t* __restrict__ deg,
+                                                       uint2* __restrict__ adj) {
+    __shared__ uint32_t s_j[(KMAX + 1) * DTILE];
+    constexpr int NWIN = PER ? 18 : 9;
+    __shared__ uint2 s_win[(NWIN + 1) * DTILE];
+    __shared__ uint32_t s_flag;
+    Status* st = P.st;
+    if (skip_if_error(st, &s_flag)) return;
+    const int t = threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    uint32_t jb;
+    const Job* Jp = tile_job(jobs, P, tile, jb);
+    if (!Jp) return;
+    const Job& J = *Jp;
+    const Geo& G = J.g;
+    cells += J.cell_base;
+    const uint32_t i = tile * DTILE + t;
+    if (i >= J.p0 + J.n) return;
+    const uint32_t nsz = P.ns;
+    auto append = [&](uint32_t p, uint32_t q, uint32_t pid) {
+        const uint32_t k = atomicAdd(&deg[p], 1u);
+        if (k < (uint32_t)KMAX) adj[(size_t)k * nsz + p] = make_uint2(q, pid);
+    };
+    const double4 a = xr[i];
+    const double ri = (double)meta_r(a.w);
+    const uint32_t pi = meta_pid(a.w);
+    const uint32_t nw = candidate_ranges<PER, true>(G, a, ri, cells, s_win + t, DTILE, nullptr, i);
+    const PreFilter<PER> pre(G, a, J.margin);
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    uint32_t sc = 0;
+    if (nw > 0) {
+        // the plain kernel's walk: branch-free over the ranges with a
+        // sentinel range at the end, four records in flight
+        s_win[nw * DTILE + t] = make_uint2(NONE, NONE);
+        uint32_t w = 0;
+        uint2 rg = s_win[t];
+        uint2 rn = s_win[DTILE + t];
+        uint32_t j = rg.x;
+        auto next = [&]() -> uint32_t {
+            const uint32_t c = j;
+            const bool live = c != NONE;
+            const bool sw = live && c + 1 == rg.y;
+            j = !live ? NONE : (sw ? rn.x : c + 1);
+            rg.y = sw ? rn.y : rg.y;
+            w += sw ? 1u : 0u;
+            rn = s_win[min(w + 1, nw) * DTILE + t];
+            return c;
+        };
+        uint32_t j0 = next(), j1 = next(), j2 = next(), j3 = next();
+        float4 q0 = xf[j0 < nsz ? j0 : i], q1 = xf[j1 < nsz ? j1 : i];
+        float4 q2 = xf[j2 < nsz ? j2 : i], q3 = xf[j3 < nsz ? j3 : i];
+#define DEM_HALF_STEP(Q, JQ)                                       \
+    {                                                              \
+        if (JQ == NONE) break;                                     \
+        const bool hit = pre(Q);                                   \
+        s_j[min(sc, (uint32_t)KMAX) * DTILE + t] = JQ;             \
+        sc += hit ? 1u : 0u;                                       \
+        JQ = next();                                               \
+        Q = xf[JQ < nsz ? JQ : i];                                 \
+    }
+        for (;;) {
+            DEM_HALF_STEP(q0, j0)
+            DEM_HALF_STEP(q1, j1)
+            DEM_HALF_STEP(q2, j2)
+            DEM_HALF_STEP(q3, j3)
+        }
+#undef DEM_HALF_STEP
+    }
+    if (sc > KMAX) {
+        // more survivors than the buffer holds: the exact re-walk finds the
+        // contacts themselves
+        sc = rewalk_exact<KMAX, PER>(P, G, a, ri, i, t, nw,
+                                     [&](uint32_t w2) { return s_win[w2 * DTILE + t]; }, xr, s_j);
+        if (sc > KMAX) {
+            atomicOr(&st->err, ERR_ROW);
+            return;
+        }
+        for (uint32_t k = 0; k < sc; ++k) {
+            const uint32_t jx = s_j[k * DTILE + t];
+            if (jx >= nsz) continue;
+            append(i, jx, meta_pid(xr[jx].w));
+            append(jx, i, pi);
+        }
+    } else {
+        // exact FP64 test of the survivors, four loads in flight
+        for (uint32_t k0 = 0; k0 < sc; k0 += 4) {
+            uint32_t jj[4];
+            double4 bb[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) jj[m] = k0 + m < sc ? s_j[(k0 + m) * DTILE + t] : NONE;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) bb[m] = xr[jj[m] < nsz ? jj[m] : i];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (jj[m] >= nsz) continue;
+                const double4 b = bb[m];
+                double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                if (PER) {
+                    double Sx, Sy, Sz;
+                    int ky;
+                    image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                    dx = dx + Sx;
+                    dy = dy + Sy;
+                    dz = dz + Sz;
+                }
+                if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
+                    append(i, jj[m], meta_pid(b.w));
+                    append(jj[m], i, pi);
+                }
+            }
+        }
+    }
+    // box faces, then extra walls: the particle's own list
+    if (G.walls) {
+        for (int f = 0; f < 6; ++f) {
+            if (!(G.walls & (1u << f))) continue;
+            const int ax = f >> 1;
+            const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+            const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
+            if (dist < ri) append(i, FACE + (uint32_t)f, FACE + (uint32_t)f);
+        }
+    }
+    for (uint32_t k = 0; k < J.nxw; ++k)
+        if (wall_touch(J.xw[k], a.x, a.y, a.z, ri)) append(i, FACE + 6u + k, FACE + 6u + k);
 }
 
 // ------------------------------------------------------------- contact law
@@ -1024,7 +1182,13 @@ __device__ __forceinline__ void finish_tile(
 // the tile.  Velocities come through the permutation, history is matched by
 // partner id, the contact law runs, and each particle then adds its own
 // contacts in row order (ascending partner id, faces last) from LDS.
-template <typename R>
+//
+// HK > 0: the contacts come as the adjacency lists of the half search
+// (k_detect_half, HK slots per particle) instead of rows.  The workgroup first
+// turns its particles' lists into their rows, ordered by partner id, in the
+// tile's region of the contact list (what the full search writes), then runs
+// as above; the lists' counters are reset, also when the step is abandoned.
+template <typename R, int HK = 0>
 __global__ __launch_bounds__(TILE) void k_force(
     const double4* __restrict__ xr, const double4* __restrict__ xr_x,
     const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
@@ -1035,19 +1199,31 @@ __global__ __launch_bounds__(TILE) void k_force(
     uint32_t* __restrict__ tab_pid_new, double* __restrict__ tab_dt_new, uint64_t cap,
     uint2* __restrict__ cells, uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
     R* __restrict__ fo, PoolView P, const Job* __restrict__ jobs, uint32_t* __restrict__ oldkeys,
-    uint2* __restrict__ movers) {
+    uint2* __restrict__ movers, uint32_t* __restrict__ deg, const uint2* __restrict__ adj,
+    uint2* __restrict__ rows_out, uint32_t* __restrict__ col_out, uint32_t slots) {
     __shared__ double4 s_x[TILE];
-    __shared__ double2 s_vw[3][TILE];
+    // the velocities and the chunk's forces; with HK, first the partner ids
+    // of the lists (HK slots per particle)
+    constexpr size_t VWF = sizeof(double2) * 3 * TILE + sizeof(R) * 6 * TILE;
+    constexpr size_t LST = (size_t)HK * TILE * 4;
+    __shared__ __align__(16) unsigned char s_u[VWF > LST ? VWF : LST];
+    double2(*const s_vw)[TILE] = reinterpret_cast<double2(*)[TILE]>(s_u);
+    R(*const s_f)[TILE] = reinterpret_cast<R(*)[TILE]>(s_u + sizeof(double2) * 3 * TILE);
     __shared__ uint2 s_old[TILE];
     __shared__ uint32_t s_excl[TILE + 1];
-    __shared__ R s_f[6][TILE];
     __shared__ uint8_t s_mat[TILE];
+    __shared__ uint32_t s_w[TILE / 64];
     __shared__ uint32_t s_base, s_total, s_flag;
     Status* st = P.st;
-    if (skip_if_error(st, &s_flag)) return;
-
     const int t = threadIdx.x;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    uint32_t d = 0;
+    if (HK) {
+        d = deg[tile * TILE + t];
+        if (d) deg[tile * TILE + t] = 0;
+    }
+    if (skip_if_error(st, &s_flag)) return;
+
     const uint32_t p0 = tile * TILE;
     const uint32_t ns = P.ns;
     uint32_t jb;
@@ -1072,7 +1248,70 @@ __global__ __launch_bounds__(TILE) void k_force(
     const uint32_t nt = (n - p0) < (uint32_t)TILE ? (n - p0) : (uint32_t)TILE;
     uint2 row = make_uint2(0, 0);
     uint2 orow = make_uint2(0, 0);
-    if (i < n) {
+    if (HK) {
+        // own state: the velocities into registers while the lists are
+        // ranked in s_u, the rest to its place
+        const bool mine = i < n;
+        const bool over = mine && d > (uint32_t)HK;
+        const uint32_t cnt = (mine && !over) ? d : 0u;
+        uint2 e0[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            e0[m] = (uint32_t)m < cnt ? adj[(size_t)m * ns + i] : make_uint2(0u, 0u);
+        double2 v0 = make_double2(0, 0), v1 = v0, v2 = v0;
+        if (mine) {
+            const uint32_t q = perm[i];
+            orow = rows_old[q];
+            s_x[t] = xr[i];
+            v0 = vw[q];
+            v1 = vw[ns + q];
+            v2 = vw[2 * (size_t)ns + q];
+            s_mat[t] = mat ? mat[q] : (uint8_t)0;
+        }
+        if (over) atomicOr(&st->err, ERR_ROW);
+        if (__syncthreads_or(over)) return;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan<TILE / 64>(cnt, s_w, tot);
+        const uint32_t rbase = tile * (uint32_t)TILE * slots;
+        if (tot > (uint32_t)TILE * slots) {
+            if (t == 0) {
+                atomicOr(&st->err, ERR_CAPACITY);
+                atomicMax(&st->need, tot);
+            }
+            return;
+        }
+        row = make_uint2(rbase + ex, cnt);
+        if (mine) rows_out[i] = row;
+        if (t == 0) P.ts[tile].m_step = tot;
+        // the list's partner ids into the lane's column of s_u; each entry
+        // then goes to the place its rank by partner id gives it in the row
+        // (ties, which distinct ids never make, by list order)
+        uint32_t* const s_lp = reinterpret_cast<uint32_t*>(s_u);
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if ((uint32_t)m < cnt) s_lp[m * TILE + t] = e0[m].y;
+        for (uint32_t k = 4; k < cnt; ++k) s_lp[k * TILE + t] = adj[(size_t)k * ns + i].y;
+        auto place = [&](const uint2 e, uint32_t k) {
+            uint32_t rank = 0;
+            for (uint32_t m = 0; m < cnt; ++m) {
+                const uint32_t pm = s_lp[m * TILE + t];
+                rank += (pm < e.y || (pm == e.y && m < k)) ? 1u : 0u;
+            }
+            col_out[rbase + ex + rank] = e.x;
+        };
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            if ((uint32_t)m < cnt) place(e0[m], (uint32_t)m);
+        for (uint32_t k = 4; k < cnt; ++k) place(adj[(size_t)k * ns + i], k);
+        s_excl[t] = ex;
+        if (t == 0) s_excl[TILE] = tot;
+        __syncthreads();  // s_u turns into the velocities and forces
+        if (mine) {
+            s_vw[0][t] = v0;
+            s_vw[1][t] = v1;
+            s_vw[2][t] = v2;
+        }
+    } else if (i < n) {
         // own position in sorted order; velocities through the permutation
         const uint32_t q = perm[i];
         row = rows[i];
@@ -1107,8 +1346,9 @@ __global__ __launch_bounds__(TILE) void k_force(
             const uint32_t g = base + q;
             const double4 a = s_x[o];
             const int mi = s_mat[o];
-            const PairTerms<R> p = pair_terms<R>(G, mt, col_j[g], a, s_vw[0][o], s_vw[1][o],
-                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns, J.xw);
+            const PairTerms<R> p = pair_terms<R>(G, mt, HK ? col_out[g] : col_j[g], a, s_vw[0][o],
+                                                 s_vw[1][o], s_vw[2][o], mi, xr, vw, mat, perm, ns,
+                                                 J.xw);
             double dtx, dty, dtz;
             matched += history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
                                         dtz) ? 1u : 0u;
@@ -2052,12 +2292,38 @@ void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X,
         hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat,
                            Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, P, P.jobs,
-                           oldkeys, movers);
+                           oldkeys, movers, nullptr, nullptr, nullptr, nullptr, 0u);
     else
         hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat,
                            Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs,
-                           oldkeys, movers);
+                           oldkeys, movers, nullptr, nullptr, nullptr, nullptr, 0u);
+}
+
+void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, const State& X,
+                       const State& Y, uint32_t* deg, const uint2* adj, uint2* rows,
+                       uint32_t* col_j, uint32_t slots, const uint2* rows_old,
+                       const uint32_t* perm, const uint32_t* tab_pid_old,
+                       const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
+                       uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
+                       uint32_t* oldkeys, uint2* movers, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
+#define DEM_FORCE_HALF(R, K)                                                                      \
+    hipLaunchKernelGGL((k_force<R, K>), dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat, Y.xr, \
+                       Y.vw, Y.mat, nullptr, nullptr, rows_old, perm, tab_pid_old, tab_dt_old,    \
+                       tab_pid_new, tab_dt_new, cap, cells, keys, vals, (R*)fo, P, P.jobs,        \
+                       oldkeys, movers, deg, adj, rows, col_j, slots)
+    if (fp64) {
+        if (kmax <= 8) DEM_FORCE_HALF(double, 8);
+        else if (kmax <= 16) DEM_FORCE_HALF(double, 16);
+        else DEM_FORCE_HALF(double, 32);
+    } else {
+        if (kmax <= 8) DEM_FORCE_HALF(float, 8);
+        else if (kmax <= 16) DEM_FORCE_HALF(float, 16);
+        else DEM_FORCE_HALF(float, 32);
+    }
+#undef DEM_FORCE_HALF
 }
 
 void launch_fused(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
@@ -2124,6 +2390,24 @@ void launch_force_thread(const PoolView& P, bool fp64, const Sorted& S, const St
                            X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,
                            tab_dt_old, tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo,
                            P, P.jobs, oldkeys, movers);
+}
+
+void launch_detect_half(const PoolView& P, int kmax, const Sorted& S, const uint2* cells,
+                        uint32_t* deg, uint2* adj, hipStream_t s) {
+    if (P.ntiles == 0) return;
+    const uint32_t nb = P.ntiles;
+#define DEM_HALF(K, PER)                                                                           \
+    hipLaunchKernelGGL((k_detect_half<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs, S.xr,    \
+                       S.xf, cells, deg, adj)
+    const bool per = P.any_periodic;
+    if (kmax <= 8) {
+        if (per) { DEM_HALF(8, true); } else { DEM_HALF(8, false); }
+    } else if (kmax <= 16) {
+        if (per) { DEM_HALF(16, true); } else { DEM_HALF(16, false); }
+    } else {
+        if (per) { DEM_HALF(32, true); } else { DEM_HALF(32, false); }
+    }
+#undef DEM_HALF
 }
 
 void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,

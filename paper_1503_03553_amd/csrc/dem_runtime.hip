@@ -139,6 +139,9 @@ struct dem_pool {
     uint32_t radix_left = 0;              // steps to take with the radix sort
     void* fo = nullptr;
     void* pf = nullptr;                   // action-reaction: pair F and n x F per entry
+    uint32_t* deg = nullptr;              // half search: list length per particle
+    uint2* adj = nullptr;                 //   and adjacency lists (adj_slots entries each)
+    int adj_slots = 0;
     MatTable* mats = nullptr;
     Job* jobs_d = nullptr;
     dem_wall* walls_d = nullptr;          // DEM_MAX_WALLS extra walls per job slot
@@ -346,6 +349,13 @@ dem_status alloc_contacts(dem_pool* s, uint32_t slots, uint32_t** col, uint32_t*
     return DEM_OK;
 }
 
+// Whether a pool's contact search is the half search (the default for the
+// plain force kernel; the force-path variants use the full search).
+bool half_search(uint32_t flags) {
+    return !(flags & (DEM_FLAG_FULL_DETECT | DEM_FLAG_FUSED | DEM_FLAG_ACTION_REACTION |
+                      DEM_FLAG_THREAD_SPLIT));
+}
+
 uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, bool fp64,
                     uint64_t slots, uint32_t flags) {
     const uint64_t np = max_tiles * TILE;
@@ -359,6 +369,7 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     b += max_cells * 8;                // cell bounds
     b += np * slots * (4 + 2 * 28);    // partner list and two history tables
     if (flags & DEM_FLAG_ACTION_REACTION) b += np * slots * 6 * (fp64 ? 8 : 4);  // pair forces
+    if (half_search(flags)) b += np * (4 + 8 * 8);  // adjacency lists (8 slots; more in a clump)
     b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
     b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4 + DEM_MAX_WALLS * sizeof(dem_wall));
     b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
@@ -380,7 +391,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     *out = nullptr;
     if (max_jobs < 1 || slots < 1) return DEM_EINVAL;
     if (flags & ~(DEM_FLAG_NO_FORCE_OUTPUT | DEM_FLAG_RADIX_SORT | DEM_FLAG_FUSED |
-                  DEM_FLAG_ACTION_REACTION | DEM_FLAG_THREAD_SPLIT))
+                  DEM_FLAG_ACTION_REACTION | DEM_FLAG_THREAD_SPLIT | DEM_FLAG_FULL_DETECT))
         return DEM_EINVAL;
     {
         // at most one force-path variant
@@ -455,6 +466,11 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
                                  &s->tab_dt[0], &s->tab_dt[1]));
     if (flags & DEM_FLAG_ACTION_REACTION)
         ALLOC_OR_FAIL(dalloc(s, 6 * mt * TILE * slots * (fp64 ? 8 : 4), &s->pf));
+    if (half_search(flags)) {
+        ALLOC_OR_FAIL(dalloc_t(s, np, &s->deg));
+        ALLOC_OR_FAIL(dalloc_t(s, np * 8, &s->adj));
+        s->adj_slots = 8;
+    }
 #undef ALLOC_OR_FAIL
     s->cap = (uint64_t)mt * TILE * slots;
     hipError_t e = hipMemset(s->st, 0, sizeof(Status));
@@ -463,6 +479,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     if (e == hipSuccess) e = hipMemset(s->rows[0], 0, np * sizeof(uint2));
     if (e == hipSuccess) e = hipMemset(s->rows[1], 0, np * sizeof(uint2));
     if (e == hipSuccess) e = hipMemset(s->fo, 0, 6 * np * (fp64 ? 8 : 4));
+    if (e == hipSuccess && s->deg) e = hipMemset(s->deg, 0, np * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(s->jobs_d, 0, max_jobs * sizeof(Job));
     if (e == hipSuccess) e = hipMemset(s->job_fail, 0, max_jobs * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(s->S[0].mat, 0, np);
@@ -882,7 +899,10 @@ dem_status enqueue_step(dem_pool* s, int o) {
     // then empty)
     const bool fused = (s->flags & DEM_FLAG_FUSED) != 0;
     prof_record(s, slot, 0);
-    if (!fused)
+    const bool half = half_search(s->flags);
+    if (half)
+        launch_detect_half(P, s->kmax, s->srt, s->cells, s->deg, s->adj, s->stream);
+    else if (!fused)
         launch_detect(P, s->kmax, s->srt, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
     prof_record(s, slot, 1);
     // the merge sort unless a recent step had too many cell changes
@@ -905,6 +925,11 @@ dem_status enqueue_step(dem_pool* s, int o) {
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->slots,
                      s->cells, s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
                      merge ? s->movers : nullptr, s->stream);
+    else if (half)
+        launch_force_half(P, s->fp64, s->kmax, s->srt, X, Y, s->deg, s->adj, s->rows[w], s->col_j,
+                          s->slots, s->rows[o], s->prev, s->tab_pid[o], s->tab_dt[o],
+                          s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals, fo,
+                          merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr, s->stream);
     else
         launch_force(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells,
@@ -1018,6 +1043,19 @@ dem_status sync_impl(dem_pool* s) {
                 return DEM_ECAPACITY;
             }
             s->kmax = s->kmax <= 8 ? 16 : 32;
+            if (s->adj && s->adj_slots < s->kmax) {
+                // longer adjacency lists for the half search (their contents
+                // live within one step)
+                uint2* a2 = nullptr;
+                r = dalloc_t(s, (size_t)s->max_tiles * TILE * s->kmax, &a2);
+                if (r != DEM_OK) {
+                    s->failed = r;
+                    return r;
+                }
+                dfree(s, s->adj);
+                s->adj = a2;
+                s->adj_slots = s->kmax;
+            }
         }
         if (h.err & ERR_MOVERS) s->radix_left = 16 + (uint32_t)s->pending.size();
         if (h.err & ERR_CAPACITY) {
