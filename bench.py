@@ -95,16 +95,27 @@ def measured_traffic(kernel, precision_tag):
     if rec.get("kernels_source_sha256") != sha:
         return None
     for k, v in rec["per_launch_bytes"].items():
-        if k.split("<")[0] == kernel and (kernel != "k_force" or precision_tag in k):
+        if kernel_is(k, kernel, precision_tag):
             return int(v)
     return None
+
+
+def kernel_is(name, kernel, precision_tag):
+    """Whether a profiled kernel name ("k_force<float, 8>") is the headline
+    path's instantiation of `kernel`: the force kernel in the given precision
+    over the half search's lists (list slots after the type, not 0)."""
+    if name.split("<")[0] != kernel:
+        return False
+    if kernel == "k_force":
+        return precision_tag in name and not name.replace(" ", "").endswith(",0>")
+    return True
 
 
 # Peak VALU issue rate: each CU's four SIMDs issue one wave64 VALU
 # instruction every four cycles (16 lanes per cycle), so a CU issues one per
 # cycle: 256 CUs x 2.4 GHz.
 VALU_PEAK = 256 * 2.4e9
-PHASE_KERNELS = {"detect": ("k_detect", "k_detect_half"), "force": ("k_force",),
+PHASE_KERNELS = {"detect": ("k_detect_half",), "force": ("k_force",),
                  "sort": ("k_mov_sort", "k_place"), "reorder": ("k_reorder", "k_tick")}
 
 
@@ -124,8 +135,7 @@ def valu_insts(phase, precision_tag):
         return None
     tot, found = 0.0, False
     for k, v in rec["per_launch"].items():
-        base = k.split("<")[0]
-        if base in PHASE_KERNELS.get(phase, ()) and (base != "k_force" or precision_tag in k):
+        if any(kernel_is(k, b, precision_tag) for b in PHASE_KERNELS.get(phase, ())):
             tot += v["SQ_INSTS_VALU"]
             found = True
     return tot if found else None
@@ -143,9 +153,10 @@ def valu_of(phase, avg_us, precision_tag):
 def roofline_of(rows, precision_tag="float"):
     dom = max(rows, key=lambda p: rows[p]["avg_us"])
     r = rows[dom]
-    return {"bound": "hbm", "kernel": "k_" + dom, "achieved": round(r["gbs"], 1),
+    kern = PHASE_KERNELS[dom][0] if dom in PHASE_KERNELS else "k_" + dom
+    return {"bound": "hbm", "kernel": kern, "achieved": round(r["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("k_" + dom, precision_tag),
+            "traffic": measured_traffic(kern, precision_tag),
             "bytes_per_launch": int(r["bytes"]), "avg_launch_us": round(r["avg_us"], 2),
             "valu_issue": valu_of(dom, r["avg_us"], precision_tag)}
 
@@ -359,6 +370,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the action-reaction and full-search legs beside the headline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
@@ -489,23 +502,24 @@ def headline(a, sc, stream, log):
     step_time = sum(r["avg_us"] for r in rows.values()) * 1e-6
     out["step_roofline_frac"] = round(step_bytes / step_time / 1e9 / HBM_PEAK_GBS, 4)
 
-    from paper_1503_03553_amd import FLAG_ACTION_REACTION
-    ar = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_ACTION_REACTION)
-    rows_ar = phase_rows(ar["prof"], n, ar["contacts"], ar["contacts_old"], False,
-                         ar["info"]["key_bits"], half=False)
-    out["action_reaction"] = {"value": round(n * a.steps / ar["seconds"], 1),
+    if not a.no_variants:
+        from paper_1503_03553_amd import FLAG_ACTION_REACTION
+        ar = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_ACTION_REACTION)
+        rows_ar = phase_rows(ar["prof"], n, ar["contacts"], ar["contacts_old"], False,
+                             ar["info"]["key_bits"], half=False)
+        out["action_reaction"] = {"value": round(n * a.steps / ar["seconds"], 1),
+                                  "unit": "particle-steps/s",
+                                  "ms_per_step": round(ar["seconds"] / a.steps * 1e3, 4),
+                                  "phases_us": {k: round(v["avg_us"], 2) for k, v in rows_ar.items()}}
+        # the full per-particle search of Algorithm 1 in place of the half search
+        from paper_1503_03553_amd import FLAG_FULL_DETECT
+        fd = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_FULL_DETECT)
+        rows_fd = phase_rows(fd["prof"], n, fd["contacts"], fd["contacts_old"], False,
+                             fd["info"]["key_bits"], half=False)
+        out["full_detect"] = {"value": round(n * a.steps / fd["seconds"], 1),
                               "unit": "particle-steps/s",
-                              "ms_per_step": round(ar["seconds"] / a.steps * 1e3, 4),
-                              "phases_us": {k: round(v["avg_us"], 2) for k, v in rows_ar.items()}}
-    # the full per-particle search of Algorithm 1 in place of the half search
-    from paper_1503_03553_amd import FLAG_FULL_DETECT
-    fd = run_single(sc, PREC_MIXED, a.steps, a.warmup, stream, flags=FLAG_FULL_DETECT)
-    rows_fd = phase_rows(fd["prof"], n, fd["contacts"], fd["contacts_old"], False,
-                         fd["info"]["key_bits"], half=False)
-    out["full_detect"] = {"value": round(n * a.steps / fd["seconds"], 1),
-                          "unit": "particle-steps/s",
-                          "ms_per_step": round(fd["seconds"] / a.steps * 1e3, 4),
-                          "kernels": kernels_of(rows_fd, headline=False)}
+                              "ms_per_step": round(fd["seconds"] / a.steps * 1e3, 4),
+                              "kernels": kernels_of(rows_fd, headline=False)}
 
     if not a.no_fp64:
         f64 = run_single(sc, PREC_FP64, a.steps, a.warmup, stream)
