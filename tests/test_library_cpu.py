@@ -101,3 +101,15 @@ def test_binding_raises_without_gpu_instead_of_falling_back():
     sc = gen.scene_cluster(seed=1, n_side=2)
     with pytest.raises(DemError):
         Sim.from_scene(sc)
+
+
+def test_binding_constants_match_the_header():
+    # flags, precisions, wall kinds and limits: every DEM_* integer constant
+    # the header defines has the binding's value under the same name
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+DEM_([A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?\b", src))
+    names = {"FLAG_" + k[5:]: v for k, v in defs.items() if k.startswith("FLAG_")}
+    assert {"FLAG_FUSED", "FLAG_ACTION_REACTION", "FLAG_THREAD_SPLIT",
+            "FLAG_FULL_DETECT"} <= set(names)
+    for name, v in names.items():
+        assert getattr(binding, name) == int(v, 0), name
