@@ -1217,10 +1217,32 @@ __global__ __launch_bounds__(TILE) void k_force(
     Status* st = P.st;
     const int t = threadIdx.x;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    // with HK the lane's list length and entries and its own state are read
+    // before the job lookup, so that they are in flight together; every
+    // index is a position (a stale permutation entry is clamped), and lanes
+    // outside a running job ignore what they read
     uint32_t d = 0;
+    uint2 e0[4];
+    double4 xi0 = make_double4(0, 0, 0, 0);
+    double2 v0 = make_double2(0, 0), v1 = v0, v2 = v0;
+    uint2 orow0 = make_uint2(0, 0);
+    uint8_t m80 = 0;
     if (HK) {
-        d = deg[tile * TILE + t];
-        if (d) deg[tile * TILE + t] = 0;
+        const uint32_t ip = tile * TILE + t;
+        d = deg[ip];
+        if (d) deg[ip] = 0;
+        const uint32_t c0 = d <= (uint32_t)HK ? d : 0u;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+            e0[m] = (uint32_t)m < c0 ? adj[(size_t)m * P.ns + ip] : make_uint2(0u, 0u);
+        const uint32_t pq = perm[ip];
+        const uint32_t q = pq < P.ns ? pq : ip;
+        xi0 = xr[ip];
+        v0 = vw[q];
+        v1 = vw[P.ns + q];
+        v2 = vw[2 * (size_t)P.ns + q];
+        orow0 = rows_old[q];
+        m80 = mat ? mat[q] : (uint8_t)0;
     }
     if (skip_if_error(st, &s_flag)) return;
 
@@ -1249,24 +1271,16 @@ __global__ __launch_bounds__(TILE) void k_force(
     uint2 row = make_uint2(0, 0);
     uint2 orow = make_uint2(0, 0);
     if (HK) {
-        // own state: the velocities into registers while the lists are
-        // ranked in s_u, the rest to its place
+        // own state: the velocities stay in registers while the lists are
+        // ranked in s_u, the rest goes to its place (a lane of a running job
+        // has at most its own list: no list outside one)
         const bool mine = i < n;
         const bool over = mine && d > (uint32_t)HK;
         const uint32_t cnt = (mine && !over) ? d : 0u;
-        uint2 e0[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m)
-            e0[m] = (uint32_t)m < cnt ? adj[(size_t)m * ns + i] : make_uint2(0u, 0u);
-        double2 v0 = make_double2(0, 0), v1 = v0, v2 = v0;
         if (mine) {
-            const uint32_t q = perm[i];
-            orow = rows_old[q];
-            s_x[t] = xr[i];
-            v0 = vw[q];
-            v1 = vw[ns + q];
-            v2 = vw[2 * (size_t)ns + q];
-            s_mat[t] = mat ? mat[q] : (uint8_t)0;
+            orow = orow0;
+            s_x[t] = xi0;
+            s_mat[t] = m80;
         }
         if (over) atomicOr(&st->err, ERR_ROW);
         if (__syncthreads_or(over)) return;
