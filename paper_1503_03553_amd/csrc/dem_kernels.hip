@@ -708,23 +708,25 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     __shared__ uint2 s_win[(NWIN + 1) * DTILE];
     __shared__ uint32_t s_flag;
     Status* st = P.st;
-    if (skip_if_error(st, &s_flag)) return;
     const int t = threadIdx.x;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = tile * DTILE + t;
+    // the own record is read before the error check and the job lookup (it
+    // is a position whatever the tile holds)
+    const double4 a = xr[i];
+    if (skip_if_error(st, &s_flag)) return;
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
     if (!Jp) return;
     const Job& J = *Jp;
     const Geo& G = J.g;
     cells += J.cell_base;
-    const uint32_t i = tile * DTILE + t;
     if (i >= J.p0 + J.n) return;
     const uint32_t nsz = P.ns;
     auto append = [&](uint32_t p, uint32_t q, uint32_t pid) {
         const uint32_t k = atomicAdd(&deg[p], 1u);
         if (k < (uint32_t)KMAX) adj[(size_t)k * nsz + p] = make_uint2(q, pid);
     };
-    const double4 a = xr[i];
     const double ri = (double)meta_r(a.w);
     const uint32_t pi = meta_pid(a.w);
     const uint32_t nw = candidate_ranges<PER, true>(G, a, ri, cells, s_win + t, DTILE, nullptr, i);
@@ -1977,13 +1979,15 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __re
     __shared__ unsigned long long s_ok[TILE];
     __shared__ uint32_t s_c[4];
     __shared__ uint32_t s_flag;
-    if (skip_if_error(P.st, &s_flag)) return;
+    // the mover count and the lane's keys are read before the error check,
+    // so that they are in flight together
     const uint32_t M = P.st->movers;
     const int t = threadIdx.x;
     const uint32_t N = P.ntiles * TILE;
     const uint32_t p0 = blockIdx.x * TILE, i = p0 + t;
     const uint32_t ok = oldkeys[i];
     const bool moved = keys[i] != ok;
+    if (skip_if_error(P.st, &s_flag)) return;
     auto key_of = [](uint32_t k, uint32_t p) { return ((unsigned long long)k << 32) | p; };
     if (M == 0) {
         keys_s[i] = ok;
@@ -2195,9 +2199,18 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
                                                   uint32_t* __restrict__ perm,
                                                   uint2* __restrict__ cells) {
     __shared__ uint32_t s_flag;
-    if (skip_if_error(P.st, &s_flag)) return;
     const uint32_t tile = blockIdx.x;
     const uint32_t i = tile * TILE + threadIdx.x;
+    // the sorted key and source index, the gathered position and the
+    // neighbours' keys are read before the error check and the job lookup,
+    // so that all are in flight together (every index is a position; a lane
+    // outside a running job ignores what it read)
+    const uint32_t key = keys_s[i];
+    const uint32_t src = vals_s[i] < P.ns ? vals_s[i] : i;
+    const double4 p = xr_y[src];
+    const uint32_t key_lo = i > 0 ? keys_s[i - 1] : 0u;
+    const uint32_t key_hi = i + 1 < P.ns ? keys_s[i + 1] : 0u;
+    if (skip_if_error(P.st, &s_flag)) return;
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
     if (!Jp) {
@@ -2215,17 +2228,14 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     }
     const uint32_t end = J.p0 + J.n;
     if (i >= end) return;
-    // a source index is a position by construction; checked so that a sort
-    // defect can never read outside the arrays
-    const uint32_t src = vals_s[i] < P.ns ? vals_s[i] : i;
-    const double4 p = xr_y[src];
+    // a source index is a position by construction; checked (above) so that
+    // a sort defect can never read outside the arrays
     xs[i] = p;
     xf[i] = far_record(G, p);
     perm[i] = src;
-    const uint32_t key = keys_s[i];
     const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
-    if (i == J.p0 || keys_s[i - 1] != key) cells[lin].x = i;
-    if (i == end - 1 || keys_s[i + 1] != key) cells[lin].y = i + 1;
+    if (i == J.p0 || key_lo != key) cells[lin].x = i;
+    if (i == end - 1 || key_hi != key) cells[lin].y = i + 1;
 }
 
 // Cell bounds of the current sorted order, from the sorted positions: after
