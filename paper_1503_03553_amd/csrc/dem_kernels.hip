@@ -1897,44 +1897,59 @@ __global__ __launch_bounds__(TILE) void k_clear_cells(PoolView P, const Job* __r
 __global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ movers,
                                                    unsigned long long* __restrict__ mk,
                                                    uint32_t* __restrict__ mp, const Status* st) {
-    __shared__ unsigned long long s[MAX_MOVERS];
+    // both orders at once: (key, position) in s_k, position in s_p, each
+    // compare-exchange stage of the bitonic network applied to both arrays
+    __shared__ unsigned long long s_k[MAX_MOVERS];
+    __shared__ uint32_t s_p[MAX_MOVERS];
     __shared__ uint32_t s_flag;
-    if (skip_if_error(st, &s_flag)) return;
+    const int t = threadIdx.x;
+    // the count and the first movers are read before the error check
     const uint32_t M = st->movers;
+    const uint2 e0 = movers[t];  // t < 1024 <= MAX_MOVERS
+    if (skip_if_error(st, &s_flag)) return;
     if (M == 0) return;
     uint32_t n2 = 1;
     while (n2 < M) n2 <<= 1;
-    const int t = threadIdx.x;
-    for (int pass = 0; pass < 2; ++pass) {
-        for (uint32_t q = t; q < n2; q += 1024) {
-            if (q < M) {
-                const uint2 e = movers[q];
-                s[q] = pass == 0 ? (((unsigned long long)e.x << 32) | e.y) : (unsigned long long)e.y;
-            } else {
-                s[q] = ~0ull;
-            }
+    for (uint32_t q = t; q < n2; q += 1024) {
+        if (q < M) {
+            const uint2 e = q == (uint32_t)t ? e0 : movers[q];
+            s_k[q] = ((unsigned long long)e.x << 32) | e.y;
+            s_p[q] = e.y;
+        } else {
+            s_k[q] = ~0ull;
+            s_p[q] = 0xFFFFFFFFu;
         }
-        __syncthreads();
-        for (uint32_t k = 2; k <= n2; k <<= 1) {
-            for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
-                for (uint32_t q = t; q < n2 / 2; q += 1024) {
-                    const uint32_t lo = 2 * q - (q & (jj - 1));
-                    const uint32_t hi = lo + jj;
-                    const bool up = (lo & k) == 0;
-                    const unsigned long long u = s[lo], v = s[hi];
+    }
+    __syncthreads();
+    const uint32_t half = n2 / 2;
+    for (uint32_t k = 2; k <= n2; k <<= 1) {
+        for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
+            // items [0, half) exchange in s_k, [half, n2) in s_p
+            for (uint32_t w = t; w < n2; w += 1024) {
+                const uint32_t q = w < half ? w : w - half;
+                const uint32_t lo = 2 * q - (q & (jj - 1));
+                const uint32_t hi = lo + jj;
+                const bool up = (lo & k) == 0;
+                if (w < half) {
+                    const unsigned long long u = s_k[lo], v = s_k[hi];
                     if ((u > v) == up) {
-                        s[lo] = v;
-                        s[hi] = u;
+                        s_k[lo] = v;
+                        s_k[hi] = u;
+                    }
+                } else {
+                    const uint32_t u = s_p[lo], v = s_p[hi];
+                    if ((u > v) == up) {
+                        s_p[lo] = v;
+                        s_p[hi] = u;
                     }
                 }
-                __syncthreads();
             }
+            __syncthreads();
         }
-        for (uint32_t q = t; q < M; q += 1024) {
-            if (pass == 0) mk[q] = s[q];
-            else mp[q] = (uint32_t)s[q];
-        }
-        __syncthreads();
+    }
+    for (uint32_t q = t; q < M; q += 1024) {
+        mk[q] = s_k[q];
+        mp[q] = s_p[q];
     }
 }
 
