@@ -704,7 +704,9 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
                                                        uint32_t* __restrict__ deg,
                                                        uint2* __restrict__ adj) {
     __shared__ uint32_t s_j[(KMAX + 1) * DTILE];
-    constexpr int NWIN = PER ? 18 : 9;
+    // the half stencil has 5 rows: at most 5 ranges (10 with the wrapped x
+    // neighbours of a periodic box), plus the sentinel
+    constexpr int NWIN = PER ? 10 : 5;
     __shared__ uint2 s_win[(NWIN + 1) * DTILE];
     __shared__ uint32_t s_flag;
     Status* st = P.st;
