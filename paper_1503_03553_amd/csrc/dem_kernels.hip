@@ -703,7 +703,12 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
                                                        const uint2* __restrict__ cells,
                                                        uint32_t* __restrict__ deg,
                                                        uint2* __restrict__ adj) {
-    __shared__ uint32_t s_j[(KMAX + 1) * DTILE];
+    // survivors of the FP32 pre-filter, SB per lane (slot SB takes the
+    // writes of a lane whose buffer is full; such a lane re-walks with the
+    // exact test and enters its contacts directly, so the buffer need not
+    // hold a whole row)
+    constexpr int SB = 8;
+    __shared__ uint32_t s_j[(SB + 1) * DTILE];
     // the half stencil has 5 rows: at most 5 ranges (10 with the wrapped x
     // neighbours of a periodic box), plus the sentinel
     constexpr int NWIN = PER ? 10 : 5;
@@ -760,7 +765,7 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     {                                                              \
         if (JQ == NONE) break;                                     \
         const bool hit = pre(Q);                                   \
-        s_j[min(sc, (uint32_t)KMAX) * DTILE + t] = JQ;             \
+        s_j[min(sc, (uint32_t)SB) * DTILE + t] = JQ;               \
         sc += hit ? 1u : 0u;                                       \
         JQ = next();                                               \
         Q = xf[JQ < nsz ? JQ : i];                                 \
@@ -773,20 +778,29 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
         }
 #undef DEM_HALF_STEP
     }
-    if (sc > KMAX) {
-        // more survivors than the buffer holds: the exact re-walk finds the
-        // contacts themselves
-        sc = rewalk_exact<KMAX, PER>(P, G, a, ri, i, t, nw,
-                                     [&](uint32_t w2) { return s_win[w2 * DTILE + t]; }, xr, s_j);
-        if (sc > KMAX) {
-            atomicOr(&st->err, ERR_ROW);
-            return;
-        }
-        for (uint32_t k = 0; k < sc; ++k) {
-            const uint32_t jx = s_j[k * DTILE + t];
-            if (jx >= nsz) continue;
-            append(i, jx, meta_pid(xr[jx].w));
-            append(jx, i, pi);
+    if (sc > SB) {
+        // more survivors than the buffer holds: walk the candidates again
+        // with the exact FP64 test and enter each contact at once (a list
+        // that outgrows its slots is reported by the force kernel)
+        for (uint32_t w2 = 0; w2 < nw; ++w2) {
+            const uint2 rg2 = s_win[w2 * DTILE + t];
+            for (uint32_t jx = rg2.x; jx < rg2.y; ++jx) {
+                if (jx >= nsz) continue;
+                const double4 b = xr[jx];
+                double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
+                if (PER) {
+                    double Sx, Sy, Sz;
+                    int ky;
+                    image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                    dx = dx + Sx;
+                    dy = dy + Sy;
+                    dz = dz + Sz;
+                }
+                if (touching(dx, dy, dz, ri + (double)meta_r(b.w))) {
+                    append(i, jx, meta_pid(b.w));
+                    append(jx, i, pi);
+                }
+            }
         }
     } else {
         // exact FP64 test of the survivors, four loads in flight
