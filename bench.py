@@ -492,6 +492,7 @@ def headline(a, sc, stream, log):
         "config": {"workload": "dilute-1m: %d polydisperse spheres, phi 0.1, walls, gravity, "
                                "one simulation, %d steps" % (n, a.steps),
                    "precision": "mixed: fp32 contact force, fp64 overlap/history/integration",
+                   "contact_search": "half stencil, each pair tested once",
                    "contacts_per_particle": round(mixed["contacts"] / n, 4),
                    "history_matched_per_step": round(mixed["matched"], 1),
                    "cells": list(mixed["info"]["cells"]), "key_bits": mixed["info"]["key_bits"]},
