@@ -134,3 +134,21 @@ def test_half_detect_pool_jobs_equal_full_detect_pool():
     for a, b in zip(*states):
         for k in ("x", "v", "w"):
             assert np.array_equal(a[k], b[k]), k
+
+
+def test_full_detect_flag_with_variants_changes_nothing():
+    # the force-path variants always run the full search: adding the flag
+    # gives bitwise the same run
+    from paper_1503_03553_amd import FLAG_ACTION_REACTION, FLAG_FUSED
+    say("case full flag with variants")
+    sc = SCENES["random3000"]()
+    dt = oracle.Sim(sc, mode=1).dt
+    for v in (FLAG_FUSED, FLAG_ACTION_REACTION):
+        states = []
+        for flags in (v, v | FLAG_FULL_DETECT):
+            g = Sim.from_scene(sc, precision=PREC_MIXED, dt=dt, flags=flags)
+            g.step(10)
+            states.append(g.get_state())
+            g.close()
+        for k in ("x", "v", "w", "F", "T"):
+            assert np.array_equal(states[0][k], states[1][k]), (v, k)
