@@ -737,12 +737,28 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     const double ri = (double)meta_r(a.w);
     const uint32_t pi = meta_pid(a.w);
     const uint32_t nw = candidate_ranges<PER, true>(G, a, ri, cells, s_win + t, DTILE, nullptr, i);
+    // In a periodic box a particle whose cell is at least one cell away from
+    // every periodic boundary (on axes of 5 cells or more) has all its
+    // candidates within 2 cells, less than 0.4 box lengths: the image shift
+    // is zero for all of them.  A wave whose particles are all such takes
+    // the plain filter and the plain exact test, with the same results.
+    bool plain = true;
+    if (PER) {
+        const int c[3] = {cell_coord(G, a.x, 0), cell_coord(G, a.y, 1), cell_coord(G, a.z, 2)};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax)
+            if (G.periodic & (1u << ax))
+                plain = plain && G.nc[ax] >= 5 && c[ax] >= 1 && c[ax] <= G.nc[ax] - 2;
+        plain = __all(plain) != 0;
+    }
     const PreFilter<PER> pre(G, a, J.margin);
+    const PreFilter<false> pre0(G, a, J.margin);
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     uint32_t sc = 0;
-    if (nw > 0) {
+    auto walk = [&](const auto& filt) {
         // the plain kernel's walk: branch-free over the ranges with a
         // sentinel range at the end, four records in flight
+        if (nw == 0) return;
         s_win[nw * DTILE + t] = make_uint2(NONE, NONE);
         uint32_t w = 0;
         uint2 rg = s_win[t];
@@ -764,7 +780,7 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
 #define DEM_HALF_STEP(Q, JQ)                                       \
     {                                                              \
         if (JQ == NONE) break;                                     \
-        const bool hit = pre(Q);                                   \
+        const bool hit = filt(Q);                                  \
         s_j[min(sc, (uint32_t)SB) * DTILE + t] = JQ;               \
         sc += hit ? 1u : 0u;                                       \
         JQ = next();                                               \
@@ -777,7 +793,11 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
             DEM_HALF_STEP(q3, j3)
         }
 #undef DEM_HALF_STEP
-    }
+    };
+    if (!PER || plain)
+        walk(pre0);
+    else
+        walk(pre);
     if (sc > SB) {
         // more survivors than the buffer holds: walk the candidates again
         // with the exact FP64 test and enter each contact at once (a list
@@ -788,7 +808,7 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
                 if (jx >= nsz) continue;
                 const double4 b = xr[jx];
                 double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                if (PER) {
+                if (PER && !plain) {
                     double Sx, Sy, Sz;
                     int ky;
                     image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
@@ -816,7 +836,7 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
                 if (jj[m] >= nsz) continue;
                 const double4 b = bb[m];
                 double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
-                if (PER) {
+                if (PER && !plain) {
                     double Sx, Sy, Sz;
                     int ky;
                     image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
