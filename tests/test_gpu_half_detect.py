@@ -152,3 +152,35 @@ def test_full_detect_flag_with_variants_changes_nothing():
             g.close()
         for k in ("x", "v", "w", "F", "T"):
             assert np.array_equal(states[0][k], states[1][k]), (v, k)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5, 6])
+def test_half_and_full_detect_agree_on_small_periodic_grids(k):
+    # sheared periodic boxes of k cells per axis: at 5 cells and more the
+    # waves away from every periodic boundary take the plain filter and
+    # exact test of the half search, below that every wave shifts images
+    say("case half vs full periodic grid", k)
+    sc = gen.scene_random(seed=431, n=1000, phi=0.22, p_touch=0.8, walls=0, periodic=7,
+                          gravity=(0, 0, 0), shear_rate=5000.0)
+    sc.v *= 10.0
+    L = float(sc.hi[0] - sc.lo[0])
+    cell = L / (k + 0.5)
+    assert cell >= 2.0 * float(np.max(sc.r))
+    dt = oracle.Sim(sc, mode=1).dt
+    gs = [Sim.from_scene(sc, precision=PREC_FP64, dt=dt, cell_size=cell, flags=f)
+          for f in (0, FLAG_FULL_DETECT)]
+    try:
+        assert tuple(gs[0].info()["cells"]) == (k, k, k)
+        for step in range(20):
+            for g in gs:
+                g.step(1)
+            a, b = gs[0].get_contacts(), gs[1].get_contacts()
+            for q in range(3):
+                assert np.array_equal(a[q], b[q]), "step %d" % step
+        sa, sb = gs[0].get_state(), gs[1].get_state()
+        for key in ("x", "v", "w", "F", "T"):
+            assert np.array_equal(sa[key], sb[key]), key
+        assert a[0].size > 0
+    finally:
+        for g in gs:
+            g.close()
