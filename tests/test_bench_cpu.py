@@ -1,0 +1,54 @@
+"""Host-side checks of the benchmark's accounting (no GPU): which profiled
+kernel instantiation stands for a phase, the algorithmic bytes of the two
+contact searches, and the counter summaries' guard by kernel source."""
+import hashlib
+import json
+import os
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_kernel_is_picks_the_half_search_force_instantiation():
+    assert bench.kernel_is("k_force<float, 8>", "k_force", "float")
+    assert bench.kernel_is("k_force<double, 16>", "k_force", "double")
+    # the full search's force kernel (no list slots) is not the headline's
+    assert not bench.kernel_is("k_force<float, 0>", "k_force", "float")
+    assert not bench.kernel_is("k_force<double, 8>", "k_force", "float")
+    assert not bench.kernel_is("k_force_thread<float>", "k_force", "float")
+    assert bench.kernel_is("k_detect_half<8, false>", "k_detect_half", "float")
+    assert not bench.kernel_is("k_detect<8, false>", "k_detect_half", "float")
+
+
+def test_kernel_bytes_of_the_two_searches():
+    n, m, mo = 1000, 300, 250
+    # half search: records 48, cell bounds 8, per contact list entry 8 and
+    # counter 4; its force kernel adds the counter read and reset and, per
+    # contact, the entry read and the partner index written
+    assert bench.kernel_bytes("detect", n, m, mo, False, 20) == 56 * n + 12 * m
+    assert bench.kernel_bytes("detect", n, m, mo, False, 20, half=False) == 48 * n + 4 * m
+    full = bench.kernel_bytes("force", n, m, mo, False, 20, half=False)
+    half = bench.kernel_bytes("force", n, m, mo, False, 20)
+    assert full == 196 * n + 36 * m + 28 * mo
+    assert half - full == 8 * n + 12 * m
+    assert bench.kernel_bytes("force", n, m, mo, True, 20, force_out=True, half=False) == full + 48 * n
+
+
+def test_counter_summaries_match_the_kernel_source_or_are_ignored():
+    src = os.path.join(ROOT, "paper_1503_03553_amd", "csrc", "dem_kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for name in ("hbm_traffic_dilute_1m.json", "valu_dilute_1m.json"):
+        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+        if rec["kernels_source_sha256"] == sha:
+            continue
+        # a stale summary is never used
+        if name.startswith("hbm"):
+            assert bench.measured_traffic("k_force", "float") is None
+        else:
+            assert bench.valu_insts("force", "float") is None
+    traffic = bench.measured_traffic("k_force", "float")
+    if traffic is not None:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_dilute_1m.json")))
+        key = [k for k in rec["per_launch_bytes"] if bench.kernel_is(k, "k_force", "float")]
+        assert len(key) == 1 and traffic == rec["per_launch_bytes"][key[0]]
