@@ -617,3 +617,306 @@ def test_tilted_rectangle_is_a_rotated_floor():
     np.testing.assert_allclose(sb.v[0], R @ sa.v[0], rtol=0, atol=1e-9 * np.abs(v0).max())
     np.testing.assert_allclose(sb.w[0], R @ sa.w[0], rtol=0, atol=1e-9 * np.abs(sa.w).max())
     assert sa.v[0, 2] > 0 and np.abs(sa.w).max() > 0
+
+
+# ------------------------------------- Eq. 3 projection, tangential damping,
+# -------------------------------------- Eq. 4 displacement, shear wrap
+def _printed_kn(mat, ri, rj=0.0):
+    """k_n with the paper's (2 - sigma^2)/E factor: the textbook Hertz
+    stiffness (Johnson) scaled by (1 - s^2)/(2 - s^2) (pinned by the contact
+    time tests above)."""
+    s2 = mat.poisson ** 2
+    return textbook_hertz_kn(mat.E, mat.poisson, mat.E, mat.poisson, ri, rj) * (1 - s2) / (2 - s2)
+
+
+def _mindlin_kt(mat, ri, rj, dn):
+    """Mindlin's tangential stiffness 8 G* sqrt(r* dn), 1/G* = (2 - nu)/G twice
+    (one material); rj = 0 is a wall (r* = ri)."""
+    Gs = 1.0 / (2.0 * (2.0 - mat.poisson) / mat.G)
+    rs = ri * rj / (ri + rj) if rj else ri
+    return 8.0 * Gs * math.sqrt(rs * dn)
+
+
+def test_eq3_projection_fixture_oblique_wall():
+    # Hand-worked fixture: the old displacement has a component along an
+    # oblique normal; Eq. (3) removes exactly that component.
+    with open(os.path.join(GOLD, "projection_oblique_wall.json")) as fh:
+        g = json.load(fh)
+    m = g["material"]
+    mat = gen.Material.make(E=m["E"], poisson=m["poisson"], density=m["density"],
+                            restitution=m["restitution"], mu=m["mu"])
+    wl = g["wall"]
+    r, dn = g["radius"], g["overlap"]
+    q = np.array(g["wall_centre"])
+    c = q + (r - dn) * np.array(g["outward_direction"])
+    sc = gen.Scene(lo=np.array(g["box_lo"]), hi=np.array(g["box_hi"]), x=c[None, :],
+                   v=np.zeros((1, 3)), w=np.zeros((1, 3)), r=gen.f32([r]),
+                   mat=np.zeros(1, np.uint16), materials=[mat], walls=0, gravity=(0, 0, 0),
+                   extra_walls=[gen.Wall(gen.RECT, tuple(wl["p"]), tuple(wl["u"]), tuple(wl["v"]))])
+    assert float(sc.r[0]) == r  # 2^-17 is a float32 number
+    P = oracle.params(sc, dt=1e-9)
+    F, T, dtn, dn_o, capped = oracle.pair(P, c, np.zeros(3), np.zeros(3), r, 0, face=6,
+                                          dt_old=g["dt_old"])
+    e = g["expected"]
+    kn = _printed_kn(mat, r)
+    kt = _mindlin_kt(mat, r, 0.0, dn)
+    assert abs(dn_o - dn) <= 1e-9 * dn
+    assert capped == e["capped"]
+    np.testing.assert_allclose(dtn, e["dt_new"], rtol=0, atol=1e-9 * 2e-9)
+    want_F = kn * dn ** 1.5 * np.array(e["F_over_kn_dn15"]) + kt * np.array(e["F_over_kt"])
+    np.testing.assert_allclose(F, want_F, rtol=0, atol=1e-9 * np.abs(want_F).max())
+    want_T = r * kt * np.array(e["T_over_r_kt"])
+    np.testing.assert_allclose(T, want_T, rtol=0, atol=1e-9 * np.abs(want_T).max())
+
+
+def test_eq3_history_stays_in_the_rotating_tangent_plane():
+    # Every stored displacement is perpendicular to the normal of the step
+    # that produced it (Eq. 3 projects the old one and v_t is tangential; a
+    # capped one is -F_t / k_t, also tangential), while the normals turn from
+    # step to step.  Without the projection, or with its sign reversed, the
+    # old displacement's component along the turned normal survives.
+    sc = gen.scene_cluster(seed=13, n_side=4, vel_sigma=1.0, polydisperse=True, walls=0,
+                           gravity=(0, 0, 0))
+    sc.w = np.random.default_rng(4).normal(0, 3e5, size=sc.w.shape)
+    s = oracle.Sim(sc, mode=0)
+    turned = 0.0
+    n_prev = {}
+    for _ in range(30):
+        x0, v0, w0 = s.x.copy(), s.v.copy(), s.w.copy()
+        hist0 = s.hist.as_dict()
+        s.step()
+        h = s.hist
+        part, d = _pair_normals(x0, h)
+        assert part.all()
+        n = d / np.linalg.norm(d, axis=1)[:, None]
+        along = np.abs(np.sum(h.dt * n, axis=1))
+        ii, jj = h.i.astype(np.int64), h.j.astype(np.int64)
+        # rounding scale of the three terms of Eq. (3)
+        vel = (np.linalg.norm(v0[ii], axis=1) + np.linalg.norm(v0[jj], axis=1) +
+               sc.r[ii] * np.linalg.norm(w0[ii], axis=1) + sc.r[jj] * np.linalg.norm(w0[jj], axis=1))
+        old = np.array([np.linalg.norm(hist0.get((a, b), np.zeros(3))) for a, b in zip(ii, jj)])
+        bound = 1e-12 * (old + np.linalg.norm(h.dt, axis=1) + vel * s.dt)
+        assert np.all(along <= bound), float((along / np.maximum(bound, 1e-300)).max())
+        for k, key in enumerate(zip(ii.tolist(), jj.tolist())):
+            if key in n_prev and key in hist0:
+                turned = max(turned, float(np.linalg.norm(hist0[key]) *
+                                           abs(np.dot(n_prev[key], n[k]) - 1.0) ** 0.5))
+        n_prev = {key: n[k] for k, key in enumerate(zip(ii.tolist(), jj.tolist()))}
+    # the normals did turn under old displacements: the check had something to see
+    assert turned > 1e-6 * 1e-9
+
+
+def _damped_slip(u0, gamma, wd, t):
+    """Slip velocity of the damped contact spring u'' + 2 gamma u' + w0^2 u = 0
+    with u(0) = 0, u'(0) = u0."""
+    return u0 * np.exp(-gamma * t) * (np.cos(wd * t) - gamma / wd * np.sin(wd * t))
+
+
+def test_tangential_damping_of_the_stick_oscillation():
+    # A sphere pressed on a face, sticking (mu large), damped (eps < 1).  The
+    # contact point's tangential displacement u obeys
+    #   m u'' = (1 + m r^2 / I) (-k_t u - eta u') = 3.5 (-k_t u - eta u'),
+    # so the slip decays at gamma = 1.75 eta / m and turns at
+    # wd = sqrt(3.5 k_t / m - gamma^2), with eta = alpha(eps) sqrt(m k_n sqrt(dn))
+    # (Eq. 1: the tangential damping uses the same eta as the normal one).
+    mat = gen.Material.make(restitution=0.9, mu=100.0)
+    L, g = 100e-6, 1e4
+    r = float(gen.f32([5e-6])[0])
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    kn = _printed_kn(mat, r)
+    d0 = (m * g / kn) ** (2 / 3)
+    kt = _mindlin_kt(mat, r, 0.0, d0)
+    eta = oracle.alpha(0.9) * math.sqrt(m * kn * math.sqrt(d0))
+    gamma = 1.75 * eta / m
+    wd = math.sqrt(3.5 * kt / m - gamma ** 2)
+    T = 2 * math.pi / wd
+    u0 = 1e-5
+    sc = gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([[L / 2, L / 2, r - d0]]),
+                   v=np.array([[u0, 0, 0]]), w=np.zeros((1, 3)), r=gen.f32([r]),
+                   mat=np.zeros(1, np.uint16), materials=[mat], walls=gen.WALL_ALL,
+                   gravity=(0, 0, -g))
+    dt = T / 8000
+    s = oracle.Sim(sc, dt=dt, mode=0)
+    k = int(3 * T / dt)
+    slip = np.empty(k)
+    for q in range(k):
+        s.step()
+        slip[q] = s.v[0, 0] - r * s.w[0, 1]
+    # semi-implicit Euler samples the velocity at the end of each step
+    t = dt * np.arange(1, k + 1)
+    want = _damped_slip(u0, gamma, wd, t)
+    assert np.abs(slip - want).max() < 5e-3 * u0
+    # the oscillation really decays over the three periods
+    assert np.abs(slip[-int(T / dt):]).max() < 0.6 * u0
+
+
+def _capped_invariant(F, dt_new, n, kt):
+    """|F_t + k_t dt_new| relative to |F_t| for contact forces F, normals n."""
+    Ft = F - np.sum(F * n, axis=1)[:, None] * n
+    return np.linalg.norm(Ft + kt[:, None] * dt_new, axis=1) / np.linalg.norm(Ft, axis=1)
+
+
+def test_eq4_displacement_recomputed_from_the_capped_force_on_a_face():
+    # Gross sliding on a face with damping (eps = 0.5): every step is capped,
+    # and Eq. (4) resets the displacement so that F_t = -k_t dt holds for the
+    # capped force itself (the damping term folded in, as the paper states
+    # it).  Reading -(F_t + eta v_t) / k_t instead, or keeping the uncapped
+    # displacement, breaks the identity by eta |v_t| / |F_t| (order one here).
+    mat = gen.Material.make(restitution=0.5, mu=0.3)
+    L, g = 100e-6, 1e4
+    r = float(gen.f32([5e-6])[0])
+    m = 1200 * 4 / 3 * math.pi * r ** 3
+    kn = _printed_kn(mat, r)
+    d0 = (m * g / kn) ** (2 / 3)
+    sc = gen.Scene(lo=np.zeros(3), hi=np.full(3, L), x=np.array([[L / 2, L / 2, r - d0]]),
+                   v=np.array([[0.05, 0.01, 0]]), w=np.zeros((1, 3)), r=gen.f32([r]),
+                   mat=np.zeros(1, np.uint16), materials=[mat], walls=gen.WALL_ALL,
+                   gravity=(0, 0, -g))
+    s = oracle.Sim(sc, dt=1e-9, mode=0)
+    n = np.array([[0.0, 0.0, -1.0]])
+    worst, eta_share = 0.0, 0.0
+    for _ in range(100):
+        x0, v0, w0 = s.x.copy(), s.v.copy(), s.w.copy()
+        s.step(keep_contact_forces=True)
+        assert len(s.hist) == 1
+        dn = r - x0[0, 2]
+        kt = _mindlin_kt(mat, r, 0.0, dn)
+        F = s.cF
+        Ft = F - np.sum(F * n, axis=1)[:, None] * n
+        fn = abs(float(np.sum(F * n)))
+        assert abs(np.linalg.norm(Ft) - 0.3 * fn) <= 1e-12 * fn  # capped
+        worst = max(worst, float(_capped_invariant(F, s.hist.dt, n, np.array([kt]))[0]))
+        vt = np.array([v0[0, 0] - r * w0[0, 1], v0[0, 1] + r * w0[0, 0], 0.0])
+        eta = oracle.alpha(0.5) * math.sqrt(m * kn * math.sqrt(dn))
+        eta_share = max(eta_share, eta * np.linalg.norm(vt) / np.linalg.norm(Ft))
+    assert worst < 1e-10
+    assert eta_share > 0.1  # the damping term is large: the two readings differ
+
+
+def test_eq4_displacement_recomputed_on_capped_particle_contacts():
+    # The same identity on every capped particle-particle contact of a
+    # shaken polydisperse cluster, with k_t = 8 G* sqrt(r* dn) from the
+    # geometry at the start of each step.
+    mat = gen.Material.make(restitution=0.5, mu=0.3)
+    sc = gen.scene_cluster(seed=11, n_side=4, vel_sigma=1.0, polydisperse=True, walls=0,
+                           gravity=(0, 0, 0))
+    sc.materials = [mat]
+    s = oracle.Sim(sc, mode=0)
+    seen = 0
+    for _ in range(10):
+        x0 = s.x.copy()
+        s.step(keep_contact_forces=True)
+        h = s.hist
+        part, d = _pair_normals(x0, h)
+        dist = np.linalg.norm(d, axis=1)
+        n = d / dist[:, None]
+        ri, rj = sc.r[h.i], sc.r[h.j]
+        dn = ri + rj - dist
+        kt = np.array([_mindlin_kt(mat, a, b, c) for a, b, c in zip(ri, rj, dn)])
+        F = s.cF
+        fn = np.abs(np.sum(F * n, axis=1))
+        Ft = np.linalg.norm(F - np.sum(F * n, axis=1)[:, None] * n, axis=1)
+        cap = Ft >= 0.3 * fn * (1 - 1e-12)
+        seen += int(cap.sum())
+        if cap.any():
+            assert _capped_invariant(F[cap], h.dt[cap], n[cap], kt[cap]).max() < 1e-9
+    assert seen > 20
+
+
+def _peculiar_momentum(s, m, shear, lo_y):
+    return (m * (s.v[:, 0] - shear * (s.x[:, 1] - lo_y))).sum()
+
+
+def test_lees_edwards_wrap_keeps_peculiar_momentum():
+    # Simple shear u = shear (y - lo_y) along x: a particle crossing the high y
+    # boundary re-enters at the low one with x shifted back by the image
+    # offset and v_x lowered by shear L_y, so its velocity relative to the
+    # flow is unchanged.  Pair forces cancel (images included), so with zero
+    # total momentum along y the total momentum relative to the flow,
+    # sum m (v_x - shear (y - lo_y)), stays constant through the wraps.
+    shear = 2000.0
+    sc = gen.scene_random(seed=31, n=1000, phi=0.25, p_touch=0.7, walls=0, periodic=7,
+                          gravity=(0, 0, 0), shear_rate=shear, vel_sigma=10.0)
+    m = 1200 * 4 / 3 * np.pi * sc.r ** 3
+    sc.v[:, 1] -= (m * sc.v[:, 1]).sum() / m.sum()  # no net motion across y
+    s = oracle.Sim(sc, mode=1)
+    q0 = _peculiar_momentum(s, m, shear, sc.lo[1])
+    scale = (m * (np.abs(s.v[:, 0]) + shear * (sc.hi[1] - sc.lo[1]))).sum()
+    Ly = sc.hi[1] - sc.lo[1]
+    wraps = 0
+    for _ in range(100):
+        y0 = s.x[:, 1].copy()
+        s.step()
+        wraps += int(np.sum(np.abs(s.x[:, 1] - y0) > 0.5 * Ly))
+        assert abs(_peculiar_momentum(s, m, shear, sc.lo[1]) - q0) <= 1e-12 * scale
+    assert wraps >= 5 and len(s.hist) > 100
+
+
+def test_lees_edwards_shifted_copy_follows_the_same_motion():
+    # A sheared periodic box is unchanged by moving everything by b along y
+    # while adding shear * b to v_x (a boost with the flow).  A compressed
+    # cluster in the middle of the box (no boundary involved) and the same
+    # cluster moved across the y boundary (pairs in contact through the
+    # sheared image, particles wrapping during the run) must follow the same
+    # motion once the second is brought back.
+    shear, t0 = 5000.0, 3.7e-4
+    a = gen.scene_cluster(seed=5, n_side=4, vel_sigma=0.05, polydisperse=True, walls=0,
+                          gravity=(0, 0, 0))
+    Lb = 3.0 * (a.hi[0] - a.lo[0])
+    a.x += (Lb - (a.hi[0] - a.lo[0])) / 2
+    a.hi = np.full(3, Lb)
+    a.periodic = 7
+    a.shear_rate = shear
+    a.materials = [gen.Material.make(restitution=0.5, mu=0.3)]
+    sa = oracle.Sim(a, mode=0)
+    dt = sa.dt
+    k = 150
+    D = lambda t: math.fmod(shear * Lb * t, Lb)
+    # move the cluster so that the particle with the largest upward speed
+    # among those in its middle layer sits just below the boundary (the
+    # particles above it start across): it crosses about a third of the way
+    # through the run
+    mid = np.argsort(np.abs(a.x[:, 1] - np.median(a.x[:, 1])))[:16]
+    p = mid[np.argmax(a.v[mid, 1])]
+    assert a.v[p, 1] > 0
+    b = (Lb - a.x[p, 1]) - 0.3 * k * dt * a.v[p, 1]
+    bsc = a.copy()
+    y = a.x[:, 1] + b
+    wrap0 = y >= Lb
+    bsc.x[:, 1] = np.where(wrap0, y - Lb, y)
+    bsc.x[:, 0] = np.where(wrap0, np.mod(a.x[:, 0] - D(t0), Lb), a.x[:, 0])
+    bsc.v[:, 0] = a.v[:, 0] + shear * b - np.where(wrap0, shear * Lb, 0.0)
+    assert 0 < wrap0.sum() < a.n
+    sa.time = t0
+    sb = oracle.Sim(bsc, dt=dt, mode=0)
+    sb.time = t0
+    crossed, across, total = 0, 0, 0
+    for _ in range(k):
+        yb = sb.x[:, 1].copy()
+        sa.step()
+        sb.step()
+        crossed += int(np.sum(np.abs(sb.x[:, 1] - yb) > 0.5 * Lb))
+        assert len(sa.hist) == len(sb.hist)
+        total += len(sb.hist)
+        hi_, hj_ = sb.hist.i.astype(np.int64), sb.hist.j.astype(np.int64)
+        across += int(np.sum(np.abs(yb[hi_] - yb[hj_]) > 0.5 * Lb))
+    # particles wrapped during the run, and many contacts acted through the
+    # sheared image
+    assert crossed >= 1 and across > 0.05 * total and total > 20 * k
+    assert np.all(np.abs(sa.x[:, 1] - a.x[:, 1]) < 0.25 * Lb)  # the reference never wraps
+    # bring the shifted copy back: w = number of wraps relative to the shift
+    w = np.rint((sa.x[:, 1] + b - sb.x[:, 1]) / Lb)
+    t1 = sa.time
+    # the boosted copy also drifts along x with the flow speed at b
+    xb = np.mod(sb.x[:, 0] + w * D(t1) - shear * b * (t1 - t0), Lb)
+    dx = xb - sa.x[:, 0]
+    dx -= Lb * np.rint(dx / Lb)
+    move = np.linalg.norm(sa.x - a.x, axis=1).max()
+    assert np.abs(dx).max() <= 1e-6 * move
+    assert np.abs(sb.x[:, 1] + w * Lb - b - sa.x[:, 1]).max() <= 1e-6 * move
+    assert np.abs(sb.x[:, 2] - sa.x[:, 2]).max() <= 1e-6 * move
+    dv = sa.v - a.v
+    vscale = np.abs(dv).max()
+    assert np.abs(sb.v[:, 0] + w * shear * Lb - shear * b - sa.v[:, 0]).max() <= 1e-6 * vscale
+    assert np.abs(sb.v[:, 1:] - sa.v[:, 1:]).max() <= 1e-6 * vscale
+    assert np.abs(sb.w - sa.w).max() <= 1e-6 * np.abs(sa.w).max()
