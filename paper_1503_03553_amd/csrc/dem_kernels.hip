@@ -1,24 +1,29 @@
 // HIP kernels of one DEM step for CDNA4 (gfx950, wave64).
 //
-// Step = detect -> force -> radix sort -> reorder, all on one stream:
+// Step = contact search -> force -> sort -> reorder, all on one stream:
 //
-//  detect   one lane per particle scans the 27 cells around it (section 3.3,
-//           "cell-based method"), keeps the partners it touches in an LDS row
-//           ordered by partner id, and the workgroup reserves one contiguous
-//           range of the contact list for its 128 particles.  This is the
-//           paper's first loop (section 3.4: collect the ids of touching
-//           partners first); the reservation compacts the rows device-wide,
-//           so the next kernel sees only real contacts.
-//  force    one lane per compacted contact: history match against the
-//           previous step's table, the contact law (Eq. 1-4, torque), then a
-//           per-particle sum in ascending partner id through LDS, gravity
+//  search   the paper's first loop (section 3.4: collect the ids of touching
+//           partners first).  Default (k_detect_half): one lane per particle
+//           scans the upper half of the 27-cell stencil around it (section
+//           3.3, "cell-based method"), so each pair is tested once, and
+//           enters every contact in both particles' adjacency lists.  With
+//           DEM_FLAG_FULL_DETECT (k_detect): the lane scans all 27 cells and
+//           keeps its partners in an LDS row ordered by partner id; the
+//           workgroup compacts its 128 rows into its own region of the
+//           contact list.
+//  force    the second loop: the workgroup first turns its particles' lists
+//           into rows ordered by partner id (default path), then runs one
+//           lane per compacted contact: history match against the previous
+//           step's table, the contact law (Eq. 1-4, torque), a per-particle
+//           sum in ascending partner id through LDS, gravity
 //           ("ForceGravity"), semi-implicit Euler ("Integrate"), and the new
-//           cell key ("CalcHash").  This is the paper's second loop, with
-//           every lane of a wavefront busy on a real contact.
-//  sort     LSD radix sort of the cell keys ("BitonicSort" in the paper),
-//           8-bit digits, reduce-then-scan, wave64 ballot ranking.
-//  reorder  gathers the state into the new cell order and writes the cell
-//           bounds ("FindCellBoundsAndReorder").
+//           cell key ("CalcHash").  Every lane of a wavefront is busy on a
+//           real contact.
+//  sort     the particles that changed cell are merged into the unchanged
+//           ones ("BitonicSort" in the paper); an LSD radix sort (8-bit
+//           digits, wave64 ballot ranking) is the fallback.
+//  reorder  the permutation into the new cell order, the gathered position
+//           records and the cell bounds ("FindCellBoundsAndReorder").
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -119,13 +124,21 @@ __device__ inline float4 far_record(const Geo& G, const double4& p) {
                 : make_float4(q, q, q, meta_r(p.w));
 }
 
+// Squared centre distance ((dx^2 + dy^2) + dz^2) with no fused multiply-add:
+// the contact predicate and the contact geometry both use it, so a pair the
+// predicate accepts has d2 < s^2 in the force computation as well.
+__device__ inline double dist2(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    double d2 = dx * dx + dy * dy;
+    d2 = d2 + dz * dz;
+    return d2;
+}
+
 // The contact predicate on FP64 positions, written out with no fused
 // multiply-add so that the contact set is bit-exact: ((dx^2+dy^2)+dz^2) < s^2.
 __device__ inline bool touching(double dx, double dy, double dz, double s) {
 #pragma clang fp contract(off)
-    double d2 = dx * dx + dy * dy;
-    d2 = d2 + dz * dz;
-    return d2 < s * s;
+    return dist2(dx, dy, dz) < s * s;
 }
 
 // Extra wall W and a centre c: w = q - c for the wall's point q closest to c
@@ -955,23 +968,25 @@ __device__ __forceinline__ PairTerms<R> pair_terms(
             dy = dy + Sy;
             dz = dz + Sz;
         }
-        const double d2 = dx * dx + dy * dy + dz * dz;
+        // the predicate's own d2 (same operations, no fused multiply-add):
+        // d2 < s^2 holds here exactly as it did in the contact search, so
+        // with a correctly rounded square root d <= s and the overlap is
+        // never negative; the clamp keeps sqrt(dn) finite even so.  The
+        // overlap is taken in FP64 in both precisions (s - d cancels), the
+        // normal in the force precision.
+        const double d2 = dist2(dx, dy, dz);
         const double s = rid + rjd;
+        const double d = sqrt(d2);
+        p.dn = (R)fmax(s - d, 0.0);
         if (sizeof(R) == 8) {
-            const double d = sqrt(d2);
             p.nx = (R)(dx / d);
             p.ny = (R)(dy / d);
             p.nz = (R)(dz / d);
-            p.dn = (R)(s - d);
         } else {
-            // overlap from (s^2 - d^2) / (s + d): the subtraction in FP64
-            // avoids the cancellation of s - d in FP32
-            const float d32 = sqrtf((float)d2);
-            const float inv = 1.0f / d32;
+            const float inv = 1.0f / (float)d;
             p.nx = (R)((float)dx * inv);
             p.ny = (R)((float)dy * inv);
             p.nz = (R)((float)dz * inv);
-            p.dn = (R)((float)(s * s - d2) / ((float)s + d32));
         }
         p.vx = (R)((a0.x - b0.x) - (double)ky * G.le_dv);
         p.vy = (R)(a0.y - b0.y);
@@ -1013,7 +1028,7 @@ __device__ __forceinline__ PairTerms<R> pair_terms(
                 p.ny = (R)(wy / d);
                 p.nz = (R)(wz / d);
             }
-            p.dn = (R)(rid - d);
+            p.dn = (R)fmax(rid - d, 0.0);
         }
         p.vx = (R)a0.x;
         p.vy = (R)a0.y;
