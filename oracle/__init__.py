@@ -81,7 +81,7 @@ def lib():
         L.orc_step.restype = ctypes.c_int
         L.orc_step.argtypes = [_P, ctypes.c_long, _vp, _vp, _vp, _vp, _vp, ctypes.c_long, _vp,
                                _vp, _vp, ctypes.c_long, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                               ctypes.c_int, ctypes.c_int]
+                               _vp, ctypes.c_int, ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -222,6 +222,7 @@ class Sim:
         self.T = np.zeros_like(self.x)
         self.cF = None
         self.cT = None
+        self.cQ = None  # per contact: |F_t| before the cap, mu |F_n|, rounding scale
 
     def step(self, k=1, keep_contact_forces=False):
         n = self.r.shape[0]
@@ -233,6 +234,7 @@ class Sim:
             odt = np.zeros((cap, 3))
             cF = np.zeros((cap, 3)) if keep_contact_forces else None
             cT = np.zeros((cap, 3)) if keep_contact_forces else None
+            cQ = np.zeros((cap, 3)) if keep_contact_forces else None
             m = ctypes.c_long()
             h = self.hist
             rc = lib().orc_step(ctypes.byref(self.P), n, self.x.ctypes.data, self.v.ctypes.data,
@@ -241,12 +243,13 @@ class Sim:
                                 ctypes.addressof(m), oi.ctypes.data, oj.ctypes.data,
                                 odt.ctypes.data, self.F.ctypes.data, self.T.ctypes.data,
                                 None if cF is None else cF.ctypes.data,
-                                None if cT is None else cT.ctypes.data, self.mode, self.threads)
+                                None if cT is None else cT.ctypes.data,
+                                None if cQ is None else cQ.ctypes.data, self.mode, self.threads)
             if rc != 0:
                 raise RuntimeError("orc_step failed (%d)" % rc)
             mm = m.value
             self.hist = History(oi[:mm].copy(), oj[:mm].copy(), odt[:mm].copy())
             if keep_contact_forces:
-                self.cF, self.cT = cF[:mm].copy(), cT[:mm].copy()
+                self.cF, self.cT, self.cQ = cF[:mm].copy(), cT[:mm].copy(), cQ[:mm].copy()
             self.time = self.time + self.dt
         return self

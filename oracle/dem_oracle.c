@@ -145,6 +145,11 @@ typedef struct {
     double F[3], T[3], dt[3];
     double dn;
     int capped;
+    /* diagnostics of the sliding test (not used by the step): |F_t| before
+     * the cap, mu |F_n|, and the sum of the magnitudes of the terms that
+     * enter both (k_t |dt|, eta (|v| + |r1 w1 + r2 w2|), mu (k_n dn^1.5 +
+     * eta |v|)), the scale of the rounding of a lower-precision evaluation */
+    double ft_pre, mufn, scale;
 } orc_pair_out;
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -243,6 +248,10 @@ void orc_contact_law(const orc_params *P, int mi, int mj, double ri, double rs, 
         Ft[a] = -kt * dtv[a] - eta * vt[a];
     }
     double fn = sqrt(dot3(Fn, Fn)), ft = sqrt(dot3(Ft, Ft));
+    o->ft_pre = ft;
+    o->mufn = mu * fn;
+    o->scale = kt * sqrt(dot3(dtv, dtv)) + eta * (sqrt(dot3(v, v)) + sqrt(dot3(rw, rw))) +
+               mu * (el + eta * sqrt(dot3(v, v)));
     o->capped = 0;
     /* Eq. (4): sliding friction, then the displacement that reproduces it */
     if (ft > mu * fn) {
@@ -544,6 +553,8 @@ static long hist_find(long m, const uint32_t *hi, const uint32_t *hj, uint32_t i
  *   history out: up to cap_out contacts; *m_out receives the count
  *   F_out, T_out (n,3) optional: per-particle totals used in this step
  *   cF, cT (cap_out,3) optional: per-contact force and torque on i
+ *   cQ (cap_out,3) optional: per contact |F_t| before the cap, mu |F_n| and
+ *     the rounding scale of the sliding test (orc_pair_out)
  *   mode 0 brute force, 1 cell list; nthreads 0 = OpenMP default
  * Returns 0, -1 (history capacity), -2 (a per-particle contact list over
  * 64) or -3 (a pair touching through two images).
@@ -551,8 +562,8 @@ static long hist_find(long m, const uint32_t *hi, const uint32_t *hj, uint32_t i
 int orc_step(const orc_params *P, long n, double *x, double *v, double *w, const double *r,
              const uint16_t *mat, long m_in, const uint32_t *hi_, const uint32_t *hj_,
              const double *hdt, long cap_out, long *m_out, uint32_t *ho_i, uint32_t *ho_j,
-             double *ho_dt, double *F_out, double *T_out, double *cF, double *cT, int mode,
-             int nthreads) {
+             double *ho_dt, double *F_out, double *T_out, double *cF, double *cT, double *cQ,
+             int mode, int nthreads) {
     orc_image im[75];
     int nim = orc_images(P, P->time, im);
     orc_grid g;
@@ -655,6 +666,11 @@ int orc_step(const orc_params *P, long n, double *x, double *v, double *w, const
                 Ts[a] += o.T[a];
                 if (cF) cF[3 * q + a] = o.F[a];
                 if (cT) cT[3 * q + a] = o.T[a];
+            }
+            if (cQ) {
+                cQ[3 * q] = o.ft_pre;
+                cQ[3 * q + 1] = o.mufn;
+                cQ[3 * q + 2] = o.scale;
             }
         }
         for (int a = 0; a < 3; ++a) {

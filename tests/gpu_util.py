@@ -3,8 +3,11 @@ on the same seeded scene and compare them to the tolerances of the contract.
 
 Tolerances (relative, per step): forces and torques 1e-5 of the natural
 scale (sum of |F_ij| over a particle's contacts plus |m g|), tangential
-displacement 1e-5 of its magnitude, contact sets bit-exact; trajectories
-1e-4 of the largest displacement after 100 steps.
+displacement 1e-5 of the larger of its magnitude and the contact's overlap,
+contact sets bit-exact; trajectories 1e-4 of the largest displacement after
+100 steps.  In mixed precision the contacts that sit on the sliding cap
+within an FP32 rounding bound (cap ties) and their owners are counted
+instead of held to the tolerance.
 """
 import sys
 
@@ -105,12 +108,39 @@ def contact_overlaps(scene, x, i, j, time):
     return out
 
 
-def check_step(o, scene, st, ci, cj, cdt, tol, allow_cap_flips=0.0, x0=None, time=0.0):
+# A contact whose sliding test the oracle decides by less than this many
+# units of the magnitudes of the terms that enter it (k_t |dt|, eta |v|,
+# mu |F_n|, ...) can go either way when those terms are rounded to FP32
+# (2^-18 = 64 FP32 rounding units): such a "cap tie" may switch between
+# the capped and the uncapped branch of Eq. (4).  The force stays
+# continuous there, but the displacement jumps by eta v_t / k_t (the
+# paper's reset folds the damping in), so in mixed precision those contacts'
+# displacements and their owners' totals are reported, not held to the
+# tolerance.  Every other contact and particle is.
+CAP_BAND = 2.0 ** -18
+
+
+def cap_ties(o):
+    """Mask of the oracle's contacts (o.hist order) that are cap ties."""
+    q = o.cQ
+    return np.abs(q[:, 0] - q[:, 1]) <= CAP_BAND * q[:, 2]
+
+
+def _stats(rel):
+    rel = np.asarray(rel, float)
+    if rel.size == 0:
+        return (0.0, 0.0)
+    return (float(rel.max()), float(np.median(rel)))
+
+
+def check_step(o, scene, st, ci, cj, cdt, tol, ties=False, x0=None, time=0.0):
     """Compare one GPU step (new state `st` with F, T; contacts ci, cj, cdt)
     with the oracle `o` that took the same step with keep_contact_forces.
     Tangential displacements are compared against the larger of their own
     magnitude and the contact's overlap at the start of the step (positions
-    x0, default the scene's)."""
+    x0, default the scene's).  With `ties` (mixed precision) the cap ties and
+    the particles that own them are exempt from the tolerance and counted.
+    Returns the counts and the (max, median) relative errors."""
     compare_contacts(ci, cj, o.hist.i, o.hist.j)
     # tangential displacement per contact
     ref = o.hist.dt
@@ -118,30 +148,36 @@ def check_step(o, scene, st, ci, cj, cdt, tol, allow_cap_flips=0.0, x0=None, tim
     scale = np.linalg.norm(ref, axis=1)
     dn = contact_overlaps(scene, scene.x if x0 is None else x0, o.hist.i, o.hist.j, time)
     floor = np.maximum(dn, 1e-9 * (scale.max() if scale.size else 0.0)) + 1e-300
-    bad = err > tol * np.maximum(scale, floor)
-    nbad = int(bad.sum())
-    if nbad:
-        assert nbad <= allow_cap_flips * len(ref), \
-            "%d of %d tangential displacements off (max rel %.3g)" % (
-                nbad, len(ref), float((err / np.maximum(scale, floor)).max()))
+    rel_dt = err / np.maximum(scale, floor)
+    tie = cap_ties(o) if ties else np.zeros(len(ref), bool)
+    bad = (rel_dt > tol) & ~tie
+    assert not bad.any(), "%d of %d tangential displacements off (max rel %.3g)" % (
+        int(bad.sum()), len(ref), float(rel_dt[~tie].max()))
     # per-particle force and torque
     sF, sT = natural_force_scale(o, scene)
-    eF = np.linalg.norm(st["F"] - o.F, axis=1)
-    eT = np.linalg.norm(st["T"] - o.T, axis=1)
-    okF = eF <= tol * sF + 1e-300
-    okT = eT <= tol * np.maximum(sT, 1e-300) + 1e-300
-    if allow_cap_flips == 0.0:
-        assert okF.all(), "force off: max rel %.3g" % float((eF / np.maximum(sF, 1e-300)).max())
-        assert okT.all(), "torque off: max rel %.3g" % float((eT / np.maximum(sT, 1e-300)).max())
-    else:
-        assert (~okF).sum() <= allow_cap_flips * scene.n + 1
-        assert (~okT).sum() <= allow_cap_flips * scene.n + 1
-    return dict(contacts=len(ref), bad_dt=nbad)
+    relF = np.linalg.norm(st["F"] - o.F, axis=1) / np.maximum(sF, 1e-300)
+    relT = np.linalg.norm(st["T"] - o.T, axis=1) / np.maximum(sT, 1e-300)
+    relT[sT == 0] = np.where(np.linalg.norm(st["T"][sT == 0], axis=1) == 0, 0.0, np.inf)
+    owner = np.zeros(scene.n, bool)
+    owner[o.hist.i[tie].astype(np.int64)] = True
+    badF = (relF > tol) & ~owner
+    badT = (relT > tol) & ~owner
+    assert not badF.any(), "force off: max rel %.3g" % float(relF[~owner].max())
+    assert not badT.any(), "torque off: max rel %.3g" % float(relT[~owner].max())
+    return dict(contacts=len(ref), cap_ties=int(tie.sum()),
+                tie_dt_off=int(((rel_dt > tol) & tie).sum()),
+                tie_owners=int(owner.sum()),
+                tie_owners_off=int((((relF > tol) | (relT > tol)) & owner).sum()),
+                err_dt=_stats(rel_dt[~tie]), err_F=_stats(relF[~owner]),
+                err_T=_stats(relT[~owner]))
 
 
-def step_parity(scene, precision, history=None, tol=1e-5, dt=None, allow_cap_flips=0.0, **kw):
+def step_parity(scene, precision, history=None, tol=1e-5, dt=None, ties=None, **kw):
     """One step from identical state and history; compares contact set,
-    tangential displacements, per-particle F and T and the new state."""
+    tangential displacements, per-particle F and T and the new state.  Cap
+    ties are exempt in mixed precision only (ties=None)."""
+    if ties is None:
+        ties = precision == PREC_MIXED
     g, o = make_pair(scene, precision, dt=dt, **kw)
     try:
         if history is not None:
@@ -154,8 +190,7 @@ def step_parity(scene, precision, history=None, tol=1e-5, dt=None, allow_cap_fli
         st = g.get_state()
         ci, cj, cdt = g.get_contacts()
         o.step(keep_contact_forces=True)
-        rep = check_step(o, scene, st, ci, cj, cdt, tol, allow_cap_flips, x0=scene.x,
-                         time=0.0)
+        rep = check_step(o, scene, st, ci, cj, cdt, tol, ties, x0=scene.x, time=0.0)
         return g, o, st, rep
     finally:
         g.close()
@@ -188,8 +223,11 @@ def trajectory_parity(scene, precision, steps=100, tol=1e-4, dt=None, chunk=None
             else:
                 diff = gv - ov
             scale = np.linalg.norm(d_ref, axis=1).max()
-            err = np.linalg.norm(diff, axis=1).max()
+            e = np.linalg.norm(diff, axis=1)
+            err = e.max()
             out[name] = (err, scale)
+            # per particle, relative to the largest change: (max, median)
+            out[name + "_rel"] = _stats(e / max(scale, 1e-300))
             assert err <= tol * scale + 1e-300, "%s: max err %.3g vs scale %.3g" % (name, err, scale)
         return out
     finally:

@@ -21,7 +21,7 @@ from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, PREC_MIXED, Sim
 pytestmark = pytest.mark.gpu
 
 
-def last_step_parity(sc, steps, tol, allow_cap_flips, threads=16):
+def last_step_parity(sc, steps, tol, threads=16):
     g = Sim.from_scene(sc, precision=PREC_MIXED, flags=FLAG_NO_FORCE_OUTPUT)
     dt = g.info()["dt"]
     g.step(steps - 1)
@@ -50,7 +50,7 @@ def last_step_parity(sc, steps, tol, allow_cap_flips, threads=16):
     st1["T"] = (st1["w"] - st0["w"]) * (inertia / dt)[:, None]
     # the velocity change is a difference of nearby FP64 numbers: its own
     # rounding is far below the tolerance (checked against the oracle's too)
-    rep = check_step(o, sc, st1, ci, cj, cdt, tol, allow_cap_flips, x0=st0["x"], time=t0)
+    rep = check_step(o, sc, st1, ci, cj, cdt, tol, True, x0=st0["x"], time=t0)
     # positions: each moved by dt times the new velocity
     dx = st1["x"] - o.x
     if sc.periodic:
@@ -68,7 +68,7 @@ def test_dense_sheared_pack_full_size():
     say("case dense shear", n)
     sc = gen.config_dense_shear(n=n)
     say("  generated, box %.4g m" % (sc.hi[0] - sc.lo[0]))
-    rep = last_step_parity(sc, steps=100, tol=1e-5, allow_cap_flips=0.01)
+    rep = last_step_parity(sc, steps=100, tol=1e-5)
     say("  ", rep)
     # touch-seeded pack: a quarter of a directed contact per particle or more
     assert rep["contacts"] > n // 4
@@ -77,5 +77,5 @@ def test_dense_sheared_pack_full_size():
 def test_dilute_headline_workload_full_size():
     say("case dilute 1M")
     sc = gen.config_dilute()
-    rep = last_step_parity(sc, steps=200, tol=1e-5, allow_cap_flips=0.01)
+    rep = last_step_parity(sc, steps=200, tol=1e-5)
     say("  ", rep)

@@ -31,10 +31,8 @@ PRECS = [("fp64", PREC_FP64), ("mixed", PREC_MIXED)]
 def test_full_detect_one_step_parity(name, prec_name, prec):
     say("case full one_step", name, prec_name)
     sc = SCENES[name]()
-    allow = 0.0 if prec == PREC_FP64 else 0.01
     tol = 1e-9 if prec == PREC_FP64 else 1e-5
-    _, _, _, rep = step_parity(sc, prec, history=random_history(sc, seed=5), tol=tol,
-                               allow_cap_flips=allow, flags=FLAG_FULL_DETECT)
+    _, _, _, rep = step_parity(sc, prec, history=random_history(sc, seed=5), tol=tol, flags=FLAG_FULL_DETECT)
     assert rep["contacts"] > 0
 
 

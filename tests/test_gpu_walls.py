@@ -87,9 +87,8 @@ def test_walls_one_step_parity(prec_name, prec):
     sc = wall_scene(31)
     assert wall_contacts(sc) >= 60
     hist = random_history(sc, seed=6)
-    allow = 0.0 if prec == PREC_FP64 else 0.01
     tol = 1e-9 if prec == PREC_FP64 else 1e-5
-    _, _, _, rep = step_parity(sc, prec, history=hist, tol=tol, allow_cap_flips=allow)
+    _, _, _, rep = step_parity(sc, prec, history=hist, tol=tol)
     say("  contacts", rep["contacts"])
 
 
