@@ -19,7 +19,10 @@
  *    cell order internally.
  *  - Ownership: the caller owns every host buffer; the library copies what it
  *    needs and never keeps a caller pointer after a call returns.  A
- *    dem_sim owns its device memory and frees it in dem_destroy.
+ *    dem_sim or dem_pool owns its device memory and frees it on destruction,
+ *    unless the caller lent it a device arena at creation: then every device
+ *    buffer is carved from that arena, which the caller keeps owning (it
+ *    must outlive the handle and is never freed by the library).
  *  - Errors: every call returns a dem_status; nothing is thrown across the
  *    ABI.  dem_step only enqueues work; a condition found on the device
  *    (contact capacity, non-finite state) is reported by the next blocking
@@ -74,8 +77,9 @@ typedef struct {
     double E, poisson, G, density, restitution, mu;
 } dem_material;
 
-/* A static wall inside the box besides its faces (section 3.2, kernel list:
- * "CollideRectangle", "CollideLine"): kind DEM_WALL_RECT is the closed
+/* A static wall inside the box besides its faces (section 3.3, item 5 of the
+ * changes to the sample code: rectangles and straight lines; section 4.2,
+ * kernel list: "CollideRectangle", "CollideLine"): kind DEM_WALL_RECT is the closed
  * rectangle p + s u + t v (u and v orthogonal and non-zero), kind
  * DEM_WALL_SEGMENT the closed segment p + s u; s, t in [0, 1], lengths in
  * metres.  Like a box face it is a body of infinite radius and mass with the
@@ -162,45 +166,71 @@ typedef struct {
 } dem_info;
 
 /*
- * Create a simulation and upload its initial state (section 4.2: the CPU
- * creates the initial configuration and sends it to the GPU).
+ * Create a simulation and upload its initial state (section 4.2: the only
+ * work of the CPU is to create the initial configuration and send it to the
+ * GPU; section 2 names the state: positions, velocities, angular
+ * velocities, radii and materials).
  *   params, mats[n_mats]   box, walls, gravity, time step, precision, materials
  *   n                      particles (0 allowed)
- *   x, v, w                (n,3) positions, velocities, angular velocities
+ *   x, v, w                (n,3) positions, velocities, angular velocities;
+ *                          along a periodic axis positions must lie in [lo, hi]
  *   radius                 (n) radii; FP32 so that sums of two radii are exact in FP64
  *   mat_id                 (n) material index < n_mats, or NULL for all 0
+ *   device_arena           NULL: the library allocates its device memory.
+ *                          Otherwise device memory of arena_bytes bytes, aligned
+ *                          to 256 bytes, lent by the caller (e.g. a torch uint8
+ *                          tensor): every device buffer of the simulation is
+ *                          carved from it.  arena_bytes must be at least
+ *                          dem_footprint(params, n); room beyond that lets the
+ *                          contact table grow (without room, growth fails with
+ *                          DEM_ECAPACITY).  The arena must outlive the handle.
  *   stream                 hipStream_t to enqueue on, or NULL for the null stream
  * On success *out receives the handle.  Returns DEM_EINVAL for a bad box,
- * materials, radius, a particle id space over 2^32 - 16, fewer than 3 cells
- * along a periodic axis, or a wall on a periodic axis.
+ * materials, radius, a position outside the box along a periodic axis, a
+ * particle id space over 2^32 - 16, fewer than 3 cells along a periodic axis,
+ * a wall on a periodic axis, or an arena that is misaligned or too small.
  */
 dem_status dem_create(const dem_params *params, const dem_material *mats, uint32_t n_mats,
                       uint64_t n, const double *x, const double *v, const double *w,
-                      const float *radius, const uint16_t *mat_id, void *stream, dem_sim **out);
+                      const float *radius, const uint16_t *mat_id, void *device_arena,
+                      uint64_t arena_bytes, void *stream, dem_sim **out);
 
 /*
- * Enqueue nsteps time steps on the simulation's stream and return.  One step
- * is: contact detection over the 27 cells around each particle, contact
- * history match, contact law (Eq. 1-4, torque), per-particle sums with
- * gravity, semi-implicit Euler integration of velocity, position and angular
- * velocity, cell hashing, radix sort by cell key and reorder into cell order.
+ * Enqueue nsteps time steps on the simulation's stream and return (section
+ * 4.2: the CPU only calls the GPU kernels again and again; section 3.4: the
+ * force loop split into a contact search and a force loop).  One step is:
+ * contact search (by default over the upper half of the 27 cells around
+ * each particle, each pair tested once and entered in both particles'
+ * lists; the full 27-cell scan of section 3.3 with DEM_FLAG_FULL_DETECT),
+ * contact history match, contact law (Eq. 1-4, torque), per-particle sums
+ * with gravity, semi-implicit Euler integration of velocity, position and
+ * angular velocity, cell hashing, the sort by cell key (merge of the
+ * particles that changed cell, radix sort as fallback) and the reorder into
+ * cell order.
  */
 dem_status dem_step(dem_sim *sim, uint32_t nsteps);
 
-/* Wait for enqueued steps; handles capacity regrowth; reports device errors. */
+/* Wait for the enqueued steps (section 4.2: the host's loop over the GPU
+ * kernels); handles capacity regrowth and redoes an abandoned step; reports
+ * device errors. */
 dem_status dem_sync(dem_sim *sim);
 
 /*
- * Copy the current state to host buffers in pid order (blocking).  Any
- * pointer may be NULL to skip it.  F, T are the per-particle force (with
- * gravity) and torque used by the last completed step (zero before the
- * first step or with DEM_FLAG_NO_FORCE_OUTPUT).
+ * Copy the current state to host buffers in pid order (blocking): the
+ * position, velocity and angular velocity the "Integrate" kernel updates
+ * (section 4.2) and the force and torque of Eq. (1) and the torque line of
+ * section 2 summed over each particle's contacts, with m g ("ForceGravity").
+ * Any pointer may be NULL to skip it.  F, T are those used by the last
+ * completed step (zero before the first step or with
+ * DEM_FLAG_NO_FORCE_OUTPUT).
  */
 dem_status dem_get_state(dem_sim *sim, double *x, double *v, double *w, double *F, double *T);
 
 /*
- * Copy the contact history to host buffers (blocking): for every directed
- * contact (i, j) of the last completed step, sorted by (i, j), its tangential
+ * Copy the contact history to host buffers (blocking): the pair-wise
+ * tangential displacement of Eq. (3), which section 4.2 stores like a sparse
+ * matrix ("InitializeContactIDs" keeps only the pairs in contact).  For every
+ * directed contact (i, j) of the last completed step, sorted by (i, j), its
  * displacement dt_xyz (3 doubles).  j is a pid or DEM_FACE_ID + f.  At most
  * cap entries are written; *m receives the total count (call with cap = 0 to
  * size the buffers).
@@ -209,35 +239,45 @@ dem_status dem_get_contacts(dem_sim *sim, uint64_t cap, uint32_t *i, uint32_t *j
                             uint64_t *m);
 
 /*
- * Replace the contact history used by the next step (tests and resume).
- * Entries need not be sorted; duplicate (i, j) pairs are rejected.
+ * Replace the contact history used by the next step (the sparse matrix of
+ * tangential displacements of section 4.2; for tests and resume).  Entries
+ * need not be sorted; duplicate (i, j) pairs are rejected.
  */
 dem_status dem_set_contacts(dem_sim *sim, uint64_t m, const uint32_t *i, const uint32_t *j,
                             const double *dt_xyz);
 
-/* Replace positions, velocities, angular velocities (pid order); the contact
- * history is kept. */
+/* Replace positions, velocities, angular velocities (pid order; the state of
+ * section 2 that section 4.2's initial configuration sets); the contact
+ * history is kept.  Positions must lie in [lo, hi] along periodic axes. */
 dem_status dem_set_state(dem_sim *sim, const double *x, const double *v, const double *w);
 
-/* Diagnostics (blocking). */
+/* Diagnostics (blocking): step count, time, and the contact counts per step
+ * (section 3.4: the number of contacts per particle sets the work of the
+ * force loop). */
 dem_status dem_get_info(dem_sim *sim, dem_info *info);
 
-/* Free the simulation and its device memory.  NULL is ignored. */
+/* Free the simulation and the device memory it allocated (a lent arena is
+ * left to its owner).  NULL is ignored.  Housekeeping of the handle; the
+ * paper has no counterpart. */
 void dem_destroy(dem_sim *sim);
 
-/* A static string for a status code. */
+/* A static string for a status code (housekeeping; no counterpart in the
+ * paper). */
 const char *dem_status_str(dem_status s);
 
 /* Device bytes a simulation of n particles with these parameters needs at
- * creation (contact table at its automatic initial capacity). */
+ * creation (contact table at its automatic initial capacity): the size of
+ * the arena dem_create needs (section 4.2: every array of the method lives
+ * on the GPU). */
 uint64_t dem_footprint(const dem_params *params, uint64_t n);
 
 /*
- * Kernel timing.  dem_profile(sim, 1) makes every following dem_step record
- * HIP events around each phase on the simulation's stream; dem_profile_read
- * waits and returns, per phase, the summed milliseconds and the launch count
- * since the last read (then resets).  Phases: 0 detect, 1 force (history
- * match, contact law, sums, integration, hashing), 2 sort, 3 reorder.
+ * Kernel timing (section 5.2 times each kernel of the step).  dem_profile(sim,
+ * 1) makes every following dem_step record HIP events around each phase on
+ * the simulation's stream; dem_profile_read waits and returns, per phase,
+ * the summed milliseconds and the launch count since the last read (then
+ * resets).  Phases: 0 detect, 1 force (history match, contact law, sums,
+ * integration, hashing), 2 sort, 3 reorder.
  */
 #define DEM_NPHASE 4
 dem_status dem_profile(dem_sim *sim, int enable);
@@ -247,25 +287,35 @@ dem_status dem_profile_read(dem_sim *sim, double *ms, uint64_t *launches);
  *
  * A pool advances many independent simulations ("jobs") of uneven sizes with
  * one set of kernel launches per step: the data-parallel decomposition of
- * section 4.2 (one thread per particle, one workgroup per tile of particles)
- * applied across jobs instead of within one.  Each job occupies whole
- * 128-particle tiles, has its own box, walls, gravity, shear, time step,
- * materials and contact history, and is bitwise independent of its
- * neighbours: a job gives the same results alone (dem_create) as in any mix.
- * All jobs of a pool share one precision.  Jobs run for a fixed number of
- * steps; a finished or failed job stays frozen in the pool until removed.
- * Admission (dem_pool_add) and removal happen between steps, so new jobs can
- * join while others run (continuous batching).
+ * section 3.3 and 4.2 (one thread per particle, the step as a fixed sequence
+ * of kernels over all particles) applied across jobs instead of within one.
+ * Each job occupies whole 128-particle tiles, has its own box, walls,
+ * gravity, shear, time step, materials and contact history, and is bitwise
+ * independent of its neighbours: a job gives the same results alone
+ * (dem_create) as in any mix.  All jobs of a pool share one precision.  Jobs
+ * run for a fixed number of steps; a finished or failed job stays frozen in
+ * the pool until removed.  Admission (dem_pool_add) and removal happen
+ * between steps, so new jobs can join while others run (continuous
+ * batching).  The paper runs one simulation at a time; the pool applies its
+ * step unchanged to each job.
  */
 typedef struct dem_pool dem_pool; /* opaque, owned by the library */
 
 typedef struct {
-    uint64_t max_particles;  /* particle positions (rounded up to 128-particle tiles) */
-    uint64_t max_cells;      /* cell-table entries shared by all jobs' grids */
-    uint32_t max_jobs;       /* job slots */
+    uint64_t max_particles;  /* particle positions (rounded up to 128-particle tiles);
+                                0: the most that fit hbm_budget (see below) */
+    uint64_t max_cells;      /* cell-table entries shared by all jobs' grids; with
+                                max_particles = 0, 0 means 4 per position plus 4096
+                                per job slot */
+    uint32_t max_jobs;       /* job slots (with max_particles = 0, 0 means 256) */
     int32_t precision;       /* dem_precision of every job */
     uint32_t contact_slots;  /* initial contact slots per particle position; 0 = 8 */
     uint32_t flags;          /* DEM_FLAG_* */
+    uint64_t hbm_budget;     /* device bytes the pool may take: with max_particles = 0
+                                the capacities are the largest whose footprint fits
+                                (the arena's size when 0 and an arena is lent);
+                                otherwise a footprint above a non-zero budget is
+                                DEM_EINVAL */
 } dem_pool_params;
 
 typedef enum { DEM_JOB_RUNNING = 0, DEM_JOB_DONE = 1, DEM_JOB_FAILED = 2 } dem_job_status;
@@ -279,20 +329,27 @@ typedef struct {
     double time, dt;      /* simulation time and time step */
 } dem_job_info;
 
-/* Device bytes dem_pool_create allocates for these parameters. */
+/* Device bytes dem_pool_create allocates (or needs in a lent arena) for these
+ * parameters (section 4.2: every array of the method lives on the GPU); 0 for
+ * invalid parameters. */
 uint64_t dem_pool_footprint(const dem_pool_params *pp);
 
 /* Create an empty pool with all its device memory (no allocation happens in
- * later calls unless the contact table must grow).  stream as in dem_create. */
-dem_status dem_pool_create(const dem_pool_params *pp, void *stream, dem_pool **out);
+ * later calls unless the contact table must grow).  device_arena and
+ * arena_bytes as in dem_create (at least dem_pool_footprint(pp) bytes);
+ * stream as in dem_create.  Section 4.2: the device holds everything; the
+ * host only admits jobs and calls the kernels. */
+dem_status dem_pool_create(const dem_pool_params *pp, void *device_arena, uint64_t arena_bytes,
+                           void *stream, dem_pool **out);
 
 /*
- * Admit one job that will run `steps` steps (1 .. 2^32 - 2).  Arguments are
- * those of dem_create; params->precision must equal the pool's,
- * params->max_contacts and params->flags are ignored (the pool's apply).  The
- * upload is enqueued on the pool's stream.  On success *job receives an id
- * unique within the pool.  DEM_EBUSY: not enough contiguous free tiles,
- * cells or slots, or the pool's sort key would exceed 32 bits.
+ * Admit one job that will run `steps` steps (1 .. 2^32 - 2): its initial
+ * configuration is sent to the device as in dem_create (section 4.2).
+ * Arguments are those of dem_create; params->precision must equal the
+ * pool's, params->max_contacts and params->flags are ignored (the pool's
+ * apply).  The upload is enqueued on the pool's stream.  On success *job
+ * receives an id unique within the pool.  DEM_EBUSY: not enough contiguous
+ * free tiles, cells or slots, or the pool's sort key would exceed 32 bits.
  */
 dem_status dem_pool_add(dem_pool *pool, const dem_params *params, const dem_material *mats,
                         uint32_t n_mats, uint64_t n, const double *x, const double *v,
@@ -300,9 +357,10 @@ dem_status dem_pool_add(dem_pool *pool, const dem_params *params, const dem_mate
                         uint32_t steps, uint64_t *job);
 
 /*
- * The host half of dem_pool_add, separately: dem_job_prepare validates a job
- * and places its particles in cell order (arguments as dem_pool_add; no GPU
- * call, safe to run on other threads while a pool steps);
+ * The host half of dem_pool_add, separately (section 4.2: creating the
+ * initial configuration is the host's only work): dem_job_prepare validates
+ * a job and places its particles in cell order (arguments as dem_pool_add;
+ * no GPU call, safe to run on other threads while a pool steps);
  * dem_pool_add_prepared then admits it between steps (DEM_EBUSY leaves the
  * prepared job usable for a later try; any other outcome consumes it).
  * dem_job_prep_cells gives the cells it takes (0 once consumed), and
@@ -318,7 +376,9 @@ dem_status dem_pool_add_prepared(dem_pool *pool, dem_job_prep *prep, uint32_t st
                                  uint64_t *job);
 void dem_job_prep_free(dem_job_prep *prep);
 
-/* Enqueue nsteps steps of every running job (finished jobs are skipped). */
+/* Enqueue nsteps steps of every running job (finished jobs are skipped): the
+ * step of dem_step (section 4.2 kernel list, section 3.4 split) over all
+ * jobs at once. */
 dem_status dem_pool_step(dem_pool *pool, uint32_t nsteps);
 
 /* Wait for enqueued steps; capacity regrowth as in dem_sync.  A job's
@@ -326,7 +386,8 @@ dem_status dem_pool_step(dem_pool *pool, uint32_t nsteps);
 dem_status dem_pool_sync(dem_pool *pool);
 
 /* Wait, then write up to cap ids of jobs that finished or failed since the
- * last poll; *n_done receives the count written. */
+ * last poll; *n_done receives the count written (host side of the serving
+ * loop; no counterpart in the paper). */
 dem_status dem_pool_poll(dem_pool *pool, uint64_t *done, uint32_t cap, uint32_t *n_done);
 
 /* Status, step counts and time of a job (blocking). */
@@ -339,21 +400,24 @@ dem_status dem_pool_get_state(dem_pool *pool, uint64_t job, double *x, double *v
 dem_status dem_pool_remove(dem_pool *pool, uint64_t job);
 
 /* Room for the next job: the largest contiguous run of free particle
- * positions and of free cells, and the free job slots.  NULL skips. */
+ * positions and of free cells, and the free job slots.  NULL skips.
+ * Admission by device footprint (host side of the serving loop). */
 dem_status dem_pool_capacity(dem_pool *pool, uint64_t *free_particles, uint64_t *free_cells,
                              uint32_t *free_jobs);
 
 /* Cells of the grid a job of n particles with these parameters and largest
  * radius rmax gets (what it takes of the pool's max_cells); 0 if the
- * parameters are invalid.  With dem_pool_capacity this tells whether a job
- * fits before its data is prepared. */
+ * parameters are invalid.  Section 3.3: the cell-based search needs cells at
+ * least as wide as the largest contact distance.  With dem_pool_capacity
+ * this tells whether a job fits before its data is prepared. */
 uint64_t dem_job_cells(const dem_params *params, uint64_t n, double rmax);
 
 /* Kernel timing of the pool's steps, as dem_profile / dem_profile_read. */
 dem_status dem_pool_profile(dem_pool *pool, int enable);
 dem_status dem_pool_profile_read(dem_pool *pool, double *ms, uint64_t *launches);
 
-/* Free the pool and its device memory.  NULL is ignored. */
+/* Free the pool and the device memory it allocated (a lent arena is left to
+ * its owner).  NULL is ignored. */
 void dem_pool_destroy(dem_pool *pool);
 
 #ifdef __cplusplus

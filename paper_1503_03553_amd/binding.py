@@ -83,7 +83,8 @@ class Info(ctypes.Structure):
 class PoolParams(ctypes.Structure):
     _fields_ = [("max_particles", ctypes.c_uint64), ("max_cells", ctypes.c_uint64),
                 ("max_jobs", ctypes.c_uint32), ("precision", ctypes.c_int32),
-                ("contact_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+                ("contact_slots", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("hbm_budget", ctypes.c_uint64)]
 
 
 class JobInfo(ctypes.Structure):
@@ -111,7 +112,7 @@ def lib():
         P = ctypes.POINTER(Params)
         L.dem_create.restype = ctypes.c_int
         L.dem_create.argtypes = [P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp,
-                                 _vp, ctypes.POINTER(_vp)]
+                                 _vp, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)]
         L.dem_step.restype = ctypes.c_int
         L.dem_step.argtypes = [_vp, ctypes.c_uint32]
         L.dem_sync.restype = ctypes.c_int
@@ -143,7 +144,7 @@ def lib():
         L.dem_pool_footprint.restype = ctypes.c_uint64
         L.dem_pool_footprint.argtypes = [PP]
         L.dem_pool_create.restype = ctypes.c_int
-        L.dem_pool_create.argtypes = [PP, _vp, ctypes.POINTER(_vp)]
+        L.dem_pool_create.argtypes = [PP, _vp, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)]
         L.dem_pool_add.restype = ctypes.c_int
         L.dem_pool_add.argtypes = [_vp, P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp,
                                    _vp, _vp, ctypes.c_uint32, u64p]
@@ -198,6 +199,18 @@ def _c(a, dtype, shape=None):
     return a
 
 
+def _arena_handle(arena):
+    """(device pointer, bytes) of a lent device arena: a torch tensor on the
+    GPU (any dtype, contiguous) or a (pointer, bytes) pair; None for none."""
+    if arena is None:
+        return None, 0
+    if isinstance(arena, tuple):
+        return int(arena[0]), int(arena[1])
+    if not arena.is_cuda or not arena.is_contiguous():
+        raise ValueError("the arena must be a contiguous tensor on the GPU")
+    return int(arena.data_ptr()), int(arena.numel() * arena.element_size())
+
+
 def _stream_handle(stream):
     if stream is None:
         return None
@@ -250,7 +263,10 @@ class Sim:
     def __init__(self, lo, hi, x, v, w, r, materials, mat=None, walls=0x3F, periodic=0,
                  gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
                  precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0, flags=0,
-                 stream=None, extra_walls=()):
+                 stream=None, extra_walls=(), arena=None):
+        """arena: device memory lent for every device buffer of the simulation
+        (a torch tensor on the GPU, or (pointer, bytes)); it must hold at least
+        footprint(params, n) bytes and is kept referenced by the handle."""
         L = lib()
         self.params = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time,
                                   precision, kn_form, cell_size, max_contacts, flags, extra_walls)
@@ -265,10 +281,12 @@ class Sim:
         mat16 = None if mat is None else _c(mat, np.uint16, (n,))
         self.n = n
         self._h = _vp()
+        self._arena = arena  # a lent arena must outlive the handle
+        aptr, abytes = _arena_handle(arena)
         self._keep = (x, v, w, r32, mats, mat16)
         code = L.dem_create(ctypes.byref(self.params), ctypes.cast(mats, _vp), len(materials), n,
                             x.ctypes.data, v.ctypes.data, w.ctypes.data, r32.ctypes.data,
-                            None if mat16 is None else mat16.ctypes.data,
+                            None if mat16 is None else mat16.ctypes.data, aptr, abytes,
                             _stream_handle(stream), ctypes.byref(self._h))
         self._keep = None
         _check(code, "dem_create")
@@ -356,6 +374,7 @@ class Sim:
         if self._h:
             lib().dem_destroy(self._h)
             self._h = _vp()
+        self._arena = None
 
     def __del__(self):
         try:
@@ -371,8 +390,9 @@ class Sim:
 
 
 def make_pool_params(max_particles, max_cells, max_jobs, precision=PREC_MIXED, contact_slots=0,
-                     flags=0) -> PoolParams:
+                     flags=0, hbm_budget=0) -> PoolParams:
     pp = PoolParams()
+    pp.hbm_budget = int(hbm_budget)
     pp.max_particles = int(max_particles)
     pp.max_cells = int(max_cells)
     pp.max_jobs = int(max_jobs)
@@ -456,15 +476,20 @@ class PreparedJob:
 class Pool:
     """Many simulations advanced by shared launches (dem_pool_*)."""
 
-    def __init__(self, max_particles, max_cells, max_jobs, precision=PREC_MIXED, contact_slots=0,
-                 flags=0, stream=None):
+    def __init__(self, max_particles=0, max_cells=0, max_jobs=0, precision=PREC_MIXED,
+                 contact_slots=0, flags=0, stream=None, hbm_budget=0, arena=None):
+        """Capacities as given, or with max_particles = 0 the largest that fit
+        hbm_budget bytes (or the lent arena)."""
         self.params = make_pool_params(max_particles, max_cells, max_jobs, precision,
-                                       contact_slots, flags)
+                                       contact_slots, flags, hbm_budget)
         self.precision = int(precision)
         self._h = _vp()
         self._n = {}
-        _check(lib().dem_pool_create(ctypes.byref(self.params), _stream_handle(stream),
-                                     ctypes.byref(self._h)), "dem_pool_create")
+        self._arena = arena
+        aptr, abytes = _arena_handle(arena)
+        _check(lib().dem_pool_create(ctypes.byref(self.params), aptr, abytes,
+                                     _stream_handle(stream), ctypes.byref(self._h)),
+               "dem_pool_create")
 
     def _handle(self):
         if not self._h:
@@ -574,6 +599,7 @@ class Pool:
         if self._h:
             lib().dem_pool_destroy(self._h)
             self._h = _vp()
+        self._arena = None
 
     def __del__(self):
         try:

@@ -55,6 +55,7 @@ uint32_t spread2_host(uint32_t v) {
 struct Buf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool in_arena = false;  // carved from a borrowed arena: never passed to hipFree
 };
 
 // Phase boundaries of one step: phase p runs between events p and p + 1.
@@ -97,6 +98,10 @@ uint64_t tiles_of(uint64_t n) { return (n + TILE - 1) / TILE; }
 
 struct dem_pool {
     hipStream_t stream = nullptr;
+    // a borrowed device arena (caller memory): every device buffer is carved
+    // from it in order; the library never frees it
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
     bool fp64 = false;
     uint32_t flags = 0;
     int kmax = 8;                     // row buffer of the detect kernel (8, 16 or 32)
@@ -175,29 +180,49 @@ dem_status hip_status(hipError_t e) {
         if (e_ != hipSuccess) return hip_status(e_); \
     } while (0)
 
+// Alignment of every buffer carved from an arena (and of the arena itself).
+constexpr size_t ARENA_ALIGN = 256;
+
 dem_status dalloc(dem_pool* s, size_t bytes, void** out) {
     void* p = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return DEM_ENOMEM;
+    if (s->arena) {
+        const size_t off = (s->arena_used + ARENA_ALIGN - 1) & ~(ARENA_ALIGN - 1);
+        if (off > s->arena_bytes || bytes > s->arena_bytes - off) return DEM_ENOMEM;
+        p = s->arena + off;
+        s->arena_used = off + bytes;
+        s->bufs.push_back({p, bytes, true});
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return DEM_ENOMEM;
+        }
+        s->bufs.push_back({p, bytes, false});
     }
-    s->bufs.push_back({p, bytes});
     s->device_bytes += bytes;
     *out = p;
     return DEM_OK;
 }
 
+// Free a device buffer.  A buffer carved from an arena returns its space
+// only when it is the last one carved (growth beyond the arena's spare room
+// then fails with DEM_ECAPACITY instead of allocating).
 void dfree(dem_pool* s, void* p) {
     if (!p) return;
     for (size_t k = 0; k < s->bufs.size(); ++k)
         if (s->bufs[k].p == p) {
-            s->device_bytes -= s->bufs[k].bytes;
+            const Buf b = s->bufs[k];
+            s->device_bytes -= b.bytes;
             s->bufs.erase(s->bufs.begin() + k);
-            break;
+            if (b.in_arena) {
+                if ((char*)b.p + b.bytes == s->arena + s->arena_used)
+                    s->arena_used = (size_t)((char*)b.p - s->arena);
+            } else {
+                (void)hipFree(p);
+            }
+            return;
         }
-    (void)hipFree(p);
 }
 
 template <typename T>
@@ -286,6 +311,16 @@ dem_status plan_grid(const dem_params& P, double rmax, uint64_t n, Layout& out) 
 
 bool finite3(const double* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
+// Whether a position lies in [lo, hi] along every periodic axis.  The cell
+// of a position outside would be clamped into a border cell, whose stencil
+// need not hold the partners that touch the position's periodic image, so
+// such input is rejected rather than wrapped silently.
+bool in_periodic_box(const dem_params& P, const double* x) {
+    for (int a = 0; a < 3; ++a)
+        if (((P.periodic >> a) & 1u) && !(x[a] >= P.lo[a] && x[a] <= P.hi[a])) return false;
+    return true;
+}
+
 dem_status validate(const dem_params* P, const dem_material* mats, uint32_t n_mats) {
     if (!P || !mats || n_mats < 1 || n_mats > DEM_MAX_MATERIALS) return DEM_EINVAL;
     for (int a = 0; a < 3; ++a) {
@@ -373,13 +408,15 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
     b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4 + DEM_MAX_WALLS * sizeof(dem_wall));
     b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
+    b += 48 * ARENA_ALIGN;  // alignment of each buffer in an arena
     return b;
 }
 
 void destroy_pool(dem_pool* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    for (auto& b : s->bufs) (void)hipFree(b.p);
+    for (auto& b : s->bufs)
+        if (!b.in_arena) (void)hipFree(b.p);
     s->bufs.clear();
     for (auto& pe : s->prof_ev)
         for (int q = 0; q <= DEM_NPHASE; ++q) (void)hipEventDestroy(pe.e[q]);
@@ -387,9 +424,11 @@ void destroy_pool(dem_pool* s) {
 }
 
 dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_jobs, bool fp64,
-                       uint32_t slots, uint32_t flags, void* stream, dem_pool** out) {
+                       uint32_t slots, uint32_t flags, void* arena, uint64_t arena_bytes,
+                       void* stream, dem_pool** out) {
     *out = nullptr;
     if (max_jobs < 1 || slots < 1) return DEM_EINVAL;
+    if (arena && ((uintptr_t)arena % ARENA_ALIGN != 0 || arena_bytes == 0)) return DEM_EINVAL;
     if (flags & ~(DEM_FLAG_NO_FORCE_OUTPUT | DEM_FLAG_RADIX_SORT | DEM_FLAG_FUSED |
                   DEM_FLAG_ACTION_REACTION | DEM_FLAG_THREAD_SPLIT | DEM_FLAG_FULL_DETECT))
         return DEM_EINVAL;
@@ -403,6 +442,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     dem_pool* s = new (std::nothrow) dem_pool();
     if (!s) return DEM_ENOMEM;
     s->stream = (hipStream_t)stream;
+    s->arena = (char*)arena;
+    s->arena_bytes = arena ? arena_bytes : 0;
     s->fp64 = fp64;
     s->flags = flags;
     s->slots = slots;
@@ -738,6 +779,7 @@ dem_status prepare_job(const dem_params* params, const dem_material* mats, uint3
     for (uint64_t i = 0; i < n; ++i) {
         if (!(radius[i] > 0.0f) || !std::isfinite(radius[i])) return DEM_EINVAL;
         if (!finite3(x + 3 * i) || !finite3(v + 3 * i) || !finite3(w + 3 * i)) return DEM_EINVAL;
+        if (!in_periodic_box(*params, x + 3 * i)) return DEM_EINVAL;
         if (mat_id && mat_id[i] >= n_mats) return DEM_EINVAL;
         rmax = std::max(rmax, (double)radius[i]);
     }
@@ -1049,8 +1091,9 @@ dem_status sync_impl(dem_pool* s) {
                 uint2* a2 = nullptr;
                 r = dalloc_t(s, (size_t)s->max_tiles * TILE * s->kmax, &a2);
                 if (r != DEM_OK) {
-                    s->failed = r;
-                    return r;
+                    // a lent arena without room left is a capacity limit
+                    s->failed = s->arena ? DEM_ECAPACITY : r;
+                    return s->failed;
                 }
                 dfree(s, s->adj);
                 s->adj = a2;
@@ -1282,7 +1325,9 @@ dem_status write_contacts(dem_pool* s, int slot, std::vector<Contact>& c) {
 dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* v, const double* w) {
     HostJob& J = s->jobs[slot];
     for (uint64_t k = 0; k < J.n; ++k)
-        if (!finite3(x + 3 * k) || !finite3(v + 3 * k) || !finite3(w + 3 * k)) return DEM_EINVAL;
+        if (!finite3(x + 3 * k) || !finite3(v + 3 * k) || !finite3(w + 3 * k) ||
+            !in_periodic_box(J.P, x + 3 * k))
+            return DEM_EINVAL;
     std::vector<Contact> c;
     dem_status r = read_contacts(s, slot, c);
     if (r != DEM_OK) return r;
@@ -1331,7 +1376,8 @@ uint64_t dem_footprint(const dem_params* P, uint64_t n) {
 
 dem_status dem_create(const dem_params* params, const dem_material* mats, uint32_t n_mats,
                       uint64_t n, const double* x, const double* v, const double* w,
-                      const float* radius, const uint16_t* mat_id, void* stream, dem_sim** out) {
+                      const float* radius, const uint16_t* mat_id, void* device_arena,
+                      uint64_t arena_bytes, void* stream, dem_sim** out) {
     if (!out) return DEM_EINVAL;
     *out = nullptr;
     dem_status r = validate(params, mats, n_mats);
@@ -1355,8 +1401,10 @@ dem_status dem_create(const dem_params* params, const dem_material* mats, uint32
     if (params->max_contacts)
         slots = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((params->max_contacts + np - 1) / np, 1024));
     dem_pool* p = nullptr;
+    if (device_arena && arena_bytes < dem_footprint(params, n)) return DEM_EINVAL;
     r = create_pool(n, (uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2], 1,
-                    params->precision == DEM_PREC_FP64, slots, params->flags, stream, &p);
+                    params->precision == DEM_PREC_FP64, slots, params->flags, device_arena,
+                    arena_bytes, stream, &p);
     if (r != DEM_OK) return r;
     int slot = 0;
     Prepared pj;
@@ -1520,22 +1568,60 @@ dem_status dem_profile_read(dem_sim* s, double* ms, uint64_t* launches) {
 }
 
 // ------------------------------------------------------------------- pool
-uint64_t dem_pool_footprint(const dem_pool_params* pp) {
-    if (!pp) return 0;
-    return pool_bytes(std::max<uint64_t>(1, tiles_of(pp->max_particles)), pp->max_cells, pp->max_jobs,
-                      pp->precision == DEM_PREC_FP64, pp->contact_slots ? pp->contact_slots : 8,
-                      pp->flags);
+// The capacities a pool gets: as given, or, with max_particles = 0, the
+// most particle positions whose footprint fits the budget (hbm_budget, else
+// the arena's size) with 4 cells per position plus 4096 per job slot (the
+// largest grid a job can take) and max_jobs slots (256 when 0).
+static bool resolve_pool(const dem_pool_params* pp, uint64_t arena_bytes, uint64_t& P,
+                         uint64_t& C, uint32_t& J, uint32_t& slots) {
+    if (pp->precision != DEM_PREC_FP64 && pp->precision != DEM_PREC_MIXED) return false;
+    if (pp->contact_slots > 1024) return false;
+    slots = pp->contact_slots ? (uint32_t)pp->contact_slots : 8u;
+    const bool fp64 = pp->precision == DEM_PREC_FP64;
+    P = pp->max_particles;
+    C = pp->max_cells;
+    J = pp->max_jobs;
+    if (P) return J >= 1 && C >= 1;
+    const uint64_t B = pp->hbm_budget ? pp->hbm_budget : arena_bytes;
+    if (!B) return false;
+    if (!J) J = 256;
+    auto cells = [&](uint64_t t) { return C ? C : 4 * t * TILE + 4096ull * J; };
+    auto fits = [&](uint64_t t) { return pool_bytes(t, cells(t), J, fp64, slots, pp->flags) <= B; };
+    if (!fits(1)) return false;
+    uint64_t lo = 1, hi = 1;
+    while (fits(hi) && hi * TILE * slots < MAX_ENTRIES) hi *= 2;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (fits(mid)) lo = mid;
+        else hi = mid;
+    }
+    P = lo * TILE;
+    C = cells(lo);
+    return true;
 }
 
-dem_status dem_pool_create(const dem_pool_params* pp, void* stream, dem_pool** out) {
+uint64_t dem_pool_footprint(const dem_pool_params* pp) {
+    if (!pp) return 0;
+    uint64_t P, C;
+    uint32_t J, slots;
+    if (!resolve_pool(pp, 0, P, C, J, slots)) return 0;
+    return pool_bytes(std::max<uint64_t>(1, tiles_of(P)), C, J, pp->precision == DEM_PREC_FP64,
+                      slots, pp->flags);
+}
+
+dem_status dem_pool_create(const dem_pool_params* pp, void* device_arena, uint64_t arena_bytes,
+                           void* stream, dem_pool** out) {
     if (!pp || !out) return DEM_EINVAL;
     *out = nullptr;
-    if (pp->precision != DEM_PREC_FP64 && pp->precision != DEM_PREC_MIXED) return DEM_EINVAL;
-    if (pp->max_jobs < 1 || pp->max_particles < 1 || pp->max_cells < 1) return DEM_EINVAL;
-    if (pp->contact_slots > 1024) return DEM_EINVAL;
-    const uint32_t slots = pp->contact_slots ? (uint32_t)pp->contact_slots : 8u;
-    return create_pool(pp->max_particles, pp->max_cells, pp->max_jobs,
-                       pp->precision == DEM_PREC_FP64, slots, pp->flags, stream, out);
+    uint64_t P, C;
+    uint32_t J, slots;
+    if (!resolve_pool(pp, device_arena ? arena_bytes : 0, P, C, J, slots)) return DEM_EINVAL;
+    const uint64_t need = pool_bytes(std::max<uint64_t>(1, tiles_of(P)), C, J,
+                                     pp->precision == DEM_PREC_FP64, slots, pp->flags);
+    if (pp->hbm_budget && need > pp->hbm_budget) return DEM_EINVAL;
+    if (device_arena && need > arena_bytes) return DEM_EINVAL;
+    return create_pool(P, C, J, pp->precision == DEM_PREC_FP64, slots, pp->flags, device_arena,
+                       arena_bytes, stream, out);
 }
 
 dem_status dem_pool_add(dem_pool* s, const dem_params* params, const dem_material* mats,
