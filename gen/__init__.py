@@ -241,25 +241,47 @@ def rsa_tiled(r, lo, hi, splits=(4, 4, 4), p_touch=0.0, touch_max=2e-3, seed=0, 
     return x
 
 
-def config_dense_shear(seed=None, n=8_000_000, phi=0.4, shear_rate=100.0, p_touch=0.9,
+def config_dense_start(seed=None, n=8_000_000, phi=0.55, phi0=0.30, shear_rate=100.0,
                        splits=(4, 4, 4)):
-    """Dense periodic pack under Lees-Edwards simple shear: N polydisperse
-    spheres (the radius law of the dilute workload), shear rate 100/s along x
-    with velocity gradient along y, no gravity, 100 steps.  RSA jams before
-    the dense limit, so the volume fraction is 0.4 (largest spheres first,
-    most spheres placed touching an earlier one)."""
+    """Start of the dense sheared pack: N polydisperse spheres (the radius law
+    of the dilute workload) in the periodic cube that holds them at volume
+    fraction phi, placed by RSA with their radii shrunk by (phi0/phi)^(1/3)
+    (volume fraction phi0, which RSA reaches).  The returned scene carries
+    the shrunk radii, zero velocities and the material of the growth
+    (restitution 0.1, no friction, no gravity); meta holds the full radii
+    (r_full), phi, phi0, and the material and shear rate of the sheared run
+    that follows the growth."""
     seed = SEED_BASE + 3 if seed is None else seed
     rng = np.random.Generator(np.random.PCG64(seed))
     r = lognormal_radii(rng, n)
     L = box_side(r, phi)
     lo, hi = np.zeros(3), np.full(3, L)
-    x = rsa_tiled(r, lo, hi, splits=splits, p_touch=p_touch, seed=seed)
-    mats = [Material.make(restitution=0.5, mu=0.3)]
-    sc = _finish(rng, x, r, lo, hi, mats, vel_sigma=0.01, walls=0, periodic=7,
-                 gravity=(0.0, 0.0, 0.0), shear_rate=shear_rate, steps=100,
-                 name="dense-shear-%d" % n, meta=dict(phi=phi))
-    sc.v[:, 0] += shear_rate * (x[:, 1] - lo[1])
-    return sc
+    r0 = f32(r * (phi0 / phi) ** (1.0 / 3.0))
+    x = rsa_tiled(r0, lo, hi, splits=splits, seed=seed) if n > 200_000 else \
+        rsa(r0, lo, hi, periodic=7, seed=seed, big_first=True)
+    grow_mat = Material.make(restitution=0.1, mu=0.0)
+    run_mat = Material.make(restitution=0.5, mu=0.3)
+    z = np.zeros((n, 3))
+    return Scene(lo=lo, hi=hi, x=x, v=z.copy(), w=z.copy(), r=r0, mat=np.zeros(n, np.uint16),
+                 materials=[grow_mat], walls=0, periodic=7, gravity=(0.0, 0.0, 0.0),
+                 steps=100, name="dense-shear-%d" % n,
+                 meta=dict(phi=phi, phi0=phi0, r_full=r, run_material=run_mat,
+                           shear_rate=shear_rate, seed=seed))
+
+
+def dense_run_scene(start, x, v, w):
+    """The sheared run of the dense pack: the grown positions, velocities and
+    angular velocities (pid order) with the full radii, the run's material,
+    and the Lees-Edwards shear (the affine profile shear_rate * (y - lo_y)
+    added to v_x)."""
+    m = start.meta
+    v = np.array(v, np.float64, copy=True)
+    v[:, 0] += m["shear_rate"] * (np.asarray(x)[:, 1] - start.lo[1])
+    return Scene(lo=start.lo.copy(), hi=start.hi.copy(), x=np.array(x, np.float64, copy=True),
+                 v=v, w=np.array(w, np.float64, copy=True), r=m["r_full"].copy(),
+                 mat=np.zeros(start.n, np.uint16), materials=[m["run_material"]], walls=0,
+                 periodic=7, gravity=(0.0, 0.0, 0.0), shear_rate=m["shear_rate"], steps=100,
+                 name=start.name, meta=dict(phi=m["phi"]))
 
 
 def config_ablation(n, regime, seed=None, r=5e-6):

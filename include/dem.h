@@ -251,6 +251,15 @@ dem_status dem_set_contacts(dem_sim *sim, uint64_t m, const uint32_t *i, const u
  * history is kept.  Positions must lie in [lo, hi] along periodic axes. */
 dem_status dem_set_state(dem_sim *sim, const double *x, const double *v, const double *w);
 
+/* Replace the radii (pid order; the particle sizes of section 2's contact
+ * law), keeping positions, velocities, angular velocities and the contact
+ * history; masses and moments of inertia follow the new radii, the time step
+ * stays.  Used to grow a packing by inflating its particles.  DEM_EINVAL for
+ * a radius that is not finite and positive, or when twice the largest radius
+ * exceeds a cell width of the simulation's grid (create it with a cell_size
+ * for the largest radius it will reach). */
+dem_status dem_set_radii(dem_sim *sim, const float *radius);
+
 /* Diagnostics (blocking): step count, time, and the contact counts per step
  * (section 3.4: the number of contacts per particle sets the work of the
  * force loop). */

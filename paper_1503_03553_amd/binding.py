@@ -31,7 +31,8 @@ STATUS = {0: "DEM_OK", -1: "DEM_EINVAL", -2: "DEM_ENOMEM", -3: "DEM_ECAPACITY",
 
 # every symbol include/dem.h declares
 EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state", "dem_get_contacts",
-           "dem_set_contacts", "dem_set_state", "dem_get_info", "dem_destroy", "dem_status_str",
+           "dem_set_contacts", "dem_set_state", "dem_set_radii", "dem_get_info", "dem_destroy",
+           "dem_status_str",
            "dem_footprint", "dem_profile", "dem_profile_read", "dem_pool_footprint",
            "dem_pool_create", "dem_pool_add", "dem_pool_step", "dem_pool_sync", "dem_pool_poll",
            "dem_pool_job_info", "dem_pool_get_state", "dem_pool_remove", "dem_pool_capacity",
@@ -126,6 +127,8 @@ def lib():
         L.dem_set_contacts.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, _vp]
         L.dem_set_state.restype = ctypes.c_int
         L.dem_set_state.argtypes = [_vp, _vp, _vp, _vp]
+        L.dem_set_radii.restype = ctypes.c_int
+        L.dem_set_radii.argtypes = [_vp, _vp]
         L.dem_get_info.restype = ctypes.c_int
         L.dem_get_info.argtypes = [_vp, ctypes.POINTER(Info)]
         L.dem_destroy.restype = None
@@ -284,10 +287,10 @@ class Sim:
         self._arena = arena  # a lent arena must outlive the handle
         aptr, abytes = _arena_handle(arena)
         self._keep = (x, v, w, r32, mats, mat16)
-        code = L.dem_create(ctypes.byref(self.params), ctypes.cast(mats, _vp), len(materials), n,
-                            x.ctypes.data, v.ctypes.data, w.ctypes.data, r32.ctypes.data,
-                            None if mat16 is None else mat16.ctypes.data, aptr, abytes,
-                            _stream_handle(stream), ctypes.byref(self._h))
+        m16 = None if mat16 is None else mat16.ctypes.data
+        code = L.dem_create(ctypes.byref(self.params), ctypes.cast(mats, _vp), len(materials),
+                            n, x.ctypes.data, v.ctypes.data, w.ctypes.data, r32.ctypes.data,
+                            m16, aptr, abytes, _stream_handle(stream), ctypes.byref(self._h))
         self._keep = None
         _check(code, "dem_create")
 
@@ -352,6 +355,11 @@ class Sim:
         w = _c(w, np.float64, (self.n, 3))
         _check(lib().dem_set_state(self._handle(), x.ctypes.data, v.ctypes.data, w.ctypes.data),
                "dem_set_state")
+
+    def set_radii(self, r):
+        """New radii (pid order), rounded to FP32; state and history kept."""
+        r32 = _c(r, np.float32, (self.n,))
+        _check(lib().dem_set_radii(self._handle(), r32.ctypes.data), "dem_set_radii")
 
     def info(self) -> dict:
         inf = Info()

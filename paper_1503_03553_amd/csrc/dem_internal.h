@@ -215,6 +215,11 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
 void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
                     const uint32_t* vals_s, const State& Y, const Sorted& S, uint32_t* perm,
                     uint2* cells, hipStream_t s);
+// Replaces the radii of the positions [p0, p0 + n) of one job (rnew in
+// particle-id order) in the state X the next step reads and its sorted
+// records S.
+void launch_set_radii(uint32_t p0, uint32_t n, const float* rnew, const State& X, const Sorted& S,
+                      hipStream_t s);
 // Rewrites the cell bounds of the current order from the sorted positions.
 void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipStream_t s);
 size_t sort_hist_words(uint32_t n);

@@ -2343,6 +2343,34 @@ __global__ __launch_bounds__(TILE) void k_rebuild_cells(PoolView P, const Job* _
     if (i == end - 1 || key_at(i + 1) != key) cells[lin].y = i + 1;
 }
 
+// New radii for the positions [p0, p0 + n) of one job (rnew indexed by the
+// particle id in the meta word): the radius half of the meta word of the
+// state buffer the next step reads, of its sorted records, and the radius of
+// the FP32 records of the contact search.
+__global__ __launch_bounds__(TILE) void k_set_radii(uint32_t p0, uint32_t n,
+                                                    const float* __restrict__ rnew,
+                                                    double4* __restrict__ xr,
+                                                    double4* __restrict__ xs,
+                                                    float4* __restrict__ xf) {
+    const uint32_t q = blockIdx.x * TILE + threadIdx.x;
+    if (q >= n) return;
+    const uint32_t i = p0 + q;
+    auto with_r = [&](double w) {
+        const uint32_t pid = meta_pid(w);
+        const float r = pid < n ? rnew[pid] : meta_r(w);
+        return __longlong_as_double((long long)pack_meta(r, pid));
+    };
+    double4 a = xr[i];
+    a.w = with_r(a.w);
+    xr[i] = a;
+    double4 b = xs[i];
+    b.w = with_r(b.w);
+    xs[i] = b;
+    float4 f = xf[i];
+    f.w = meta_r(b.w);
+    xf[i] = f;
+}
+
 // End of a step: every running job advances (one thread per job).
 __global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
     if (__atomic_load_n(&P.st->err, __ATOMIC_RELAXED)) return;
@@ -2551,6 +2579,13 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
     }
     *keys_out = ki;
     *vals_out = vi;
+}
+
+void launch_set_radii(uint32_t p0, uint32_t n, const float* rnew, const State& X, const Sorted& S,
+                      hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_set_radii, dim3((n + TILE - 1) / TILE), dim3(TILE), 0, s, p0, n, rnew,
+                           X.xr, S.xr, S.xf);
 }
 
 void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipStream_t s) {

@@ -1347,6 +1347,42 @@ dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* 
     return write_contacts(s, slot, c);
 }
 
+// New radii of a job's particles (pid order), keeping positions, velocities
+// and contact history.  The grid stays: every cell must remain at least as
+// wide as the largest contact distance.  Masses and inertias follow the
+// radii (they are computed from them in the kernels); the time step stays.
+dem_status set_radii_impl(dem_pool* s, int slot, const float* radius) {
+    HostJob& J = s->jobs[slot];
+    const uint64_t n = J.n;
+    double rmax = 0.0;
+    for (uint64_t k = 0; k < n; ++k) {
+        if (!(radius[k] > 0.0f) || !std::isfinite(radius[k])) return DEM_EINVAL;
+        rmax = std::max(rmax, (double)radius[k]);
+    }
+    if (n == 0) return DEM_OK;
+    for (int a = 0; a < 3; ++a)
+        if (!(2.0 * rmax * 1.000001 <= J.lay.cell[a])) return DEM_EINVAL;
+    Job jd;
+    dem_status r = read_job(s, slot, jd);
+    if (r != DEM_OK) return r;
+    double span = 0.0;
+    for (int a = 0; a < 3; ++a) span = std::max(span, std::fabs(J.geo.lo[a]) + std::fabs(J.geo.hi[a]));
+    J.geo.reach = rmax + 1e-9 * span;
+    jd.g.reach = J.geo.reach;
+    // the radii travel through the sort's scratch keys (unused between steps)
+    r = upload(s, s->keys_t, radius, n * sizeof(float));
+    if (r == DEM_OK) r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
+    if (r != DEM_OK) return r;
+    const uint32_t p0 = J.tile0 * TILE;
+    launch_set_radii(p0, (uint32_t)n, (const float*)s->keys_t, s->S[s->cur], s->srt, s->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->staging.clear();
+    s->held.clear();
+    J.r.assign(radius, radius + n);
+    return DEM_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -1493,6 +1529,13 @@ dem_status dem_set_state(dem_sim* s, const double* x, const double* v, const dou
     dem_status r = sim_sync(s);
     if (r != DEM_OK) return r;
     return set_state_impl(s->pool, s->slot, x, v, w);
+}
+
+dem_status dem_set_radii(dem_sim* s, const float* radius) {
+    if (!s || (s->pool->jobs[s->slot].n && !radius)) return DEM_EINVAL;
+    dem_status r = sim_sync(s);
+    if (r != DEM_OK) return r;
+    return set_radii_impl(s->pool, s->slot, radius);
 }
 
 dem_status dem_get_info(dem_sim* s, dem_info* info) {

@@ -64,14 +64,18 @@ def last_step_parity(sc, steps, tol, threads=16):
 
 
 def test_dense_sheared_pack_full_size():
+    from paper_1503_03553_amd import pack
     n = int(os.environ.get("DEM_FULL_N", "8000000"))
     say("case dense shear", n)
-    sc = gen.config_dense_shear(n=n)
-    say("  generated, box %.4g m" % (sc.hi[0] - sc.lo[0]))
+    start = gen.config_dense_start(n=n)
+    say("  generated, box %.4g m" % (start.hi[0] - start.lo[0]))
+    g = pack.grown(start, log=say)
+    say("  grown:", g["stats"])
+    sc = gen.dense_run_scene(start, g["x"], g["v"], g["w"])
     rep = last_step_parity(sc, steps=100, tol=1e-5)
     say("  ", rep)
-    # touch-seeded pack: a quarter of a directed contact per particle or more
-    assert rep["contacts"] > n // 4
+    # the grown pack at phi 0.55: more than one directed contact per particle
+    assert rep["contacts"] > n
 
 
 def test_dilute_headline_workload_full_size():
