@@ -35,10 +35,12 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "particle-steps/s at 1M (FP32 batched vs FP64 plain); p50/p99 job latency"
 
 
-def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True):
-    """Algorithmic HBM bytes of one launch (each record counted once); `half`:
-    the default half search, whose lists the force kernel turns into rows
-    (else the full search writes the rows)."""
+def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True, merge=True):
+    """Bytes one launch of the phase's kernels reads and writes as
+    implemented (each record counted once); `half`: the default half search,
+    whose lists the force kernel turns into rows (else the full search
+    writes the rows); `merge`: the default sort (merge of the particles that
+    changed cell) rather than the radix sort."""
     if phase == "detect":
         if half:
             # own FP32 record 16 + FP64 position 32, cell bounds 8 (as
@@ -60,6 +62,10 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True)
         extra = 8 * n + 12 * m if half else 0
         return (104 + 92 + fo) * n + 36 * m + 28 * m_old + extra
     if phase == "sort":
+        if merge:
+            # keys before and after the step read, sorted index written, plus
+            # the few movers (negligible)
+            return 12 * n
         passes = max(1, (key_bits + 7) // 8)
         return 20 * n * passes
     if phase == "reorder":
@@ -69,14 +75,45 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True)
     return 0
 
 
-def phase_rows(prof, n, m, m_old, fp64, key_bits, half=True):
+def method_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, merge=True):
+    """Algorithmic bytes of one launch: what the method's step needs of HBM
+    for the work the phase's kernels do, each particle's record and each
+    contact's entry counted once, independent of how the kernels organise
+    it.  Per particle with c directed contacts (c' of the step before):
+      detect  (contact search)          40 + 4c: position and radius 28, cell
+              ranges 8, row start/count 4; partner index 4 per contact
+      force   (history match, contact law, per-particle sums, integration
+              and hashing in one pass)  176 + 32c + 28c': own and partner
+              records once 80 (position, velocity, angular velocity,
+              radius, id), permutation and old row 8, row 8, integrated
+              state written 72, key and index 8; per contact partner index 4
+              and new id and displacement 28; per old contact id and
+              displacement 28; F and T 24 (48 in FP64) only when stored
+      sort    (stable sort of (key, index))  the implementation's bytes
+      reorder (gather into cell order, cell bounds)  at most 168 (index 4,
+              record gathered 80 and written 80, bounds 4); the kernel gathers
+              only positions, so its own smaller count applies
+    """
+    impl = kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=force_out, merge=merge)
+    if phase == "detect":
+        return min(40 * n + 4 * m, impl)
+    if phase == "force":
+        fo = (48 if fp64 else 24) if force_out else 0
+        return (176 + fo) * n + 32 * m + 28 * m_old
+    if phase == "reorder":
+        return min(168 * n, impl)
+    return impl
+
+
+def phase_rows(prof, n, m, m_old, fp64, key_bits, half=True, merge=True):
     rows = {}
     for ph, (ms, cnt) in prof.items():
         if cnt == 0:
             continue
         avg_s = ms / cnt * 1e-3
-        b = kernel_bytes(ph, n, m, m_old, fp64, key_bits, half=half)
-        rows[ph] = dict(avg_us=avg_s * 1e6, bytes=b, gbs=b / avg_s / 1e9)
+        b = method_bytes(ph, n, m, m_old, fp64, key_bits, merge=merge)
+        bi = kernel_bytes(ph, n, m, m_old, fp64, key_bits, half=half, merge=merge)
+        rows[ph] = dict(avg_us=avg_s * 1e6, bytes=b, impl_bytes=bi, gbs=b / avg_s / 1e9)
     return rows
 
 
@@ -151,6 +188,10 @@ def valu_of(phase, avg_us, precision_tag):
 
 
 def roofline_of(rows, precision_tag="float"):
+    """The dominant kernel against the HBM peak: `achieved` is its
+    algorithmic bytes (method_bytes) per launch over its average launch
+    duration; `implementation_bytes_per_launch` is what the kernel moves as
+    written, `overhead_bytes_per_launch` the difference."""
     dom = max(rows, key=lambda p: rows[p]["avg_us"])
     r = rows[dom]
     kern = PHASE_KERNELS[dom][0] if dom in PHASE_KERNELS else "k_" + dom
@@ -158,7 +199,23 @@ def roofline_of(rows, precision_tag="float"):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(r["gbs"] / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(kern, precision_tag),
             "bytes_per_launch": int(r["bytes"]), "avg_launch_us": round(r["avg_us"], 2),
+            "implementation_bytes_per_launch": int(r["impl_bytes"]),
+            "overhead_bytes_per_launch": int(r["impl_bytes"] - r["bytes"]),
             "valu_issue": valu_of(dom, r["avg_us"], precision_tag)}
+
+
+def contact_kernels_of(rows):
+    """The contact search and the force kernel together (the force/contact
+    kernels) against the HBM peak: their algorithmic bytes over the sum of
+    their average launch durations, beside the 0.5 target."""
+    if "detect" not in rows or "force" not in rows:
+        return None
+    b = rows["detect"]["bytes"] + rows["force"]["bytes"]
+    us = rows["detect"]["avg_us"] + rows["force"]["avg_us"]
+    gbs = b / (us * 1e-6) / 1e9
+    return {"bytes_per_step": int(b), "us_per_step": round(us, 2), "achieved": round(gbs, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "target_frac": 0.5}
 
 
 def kernels_of(rows, precision_tag="float", headline=True):
@@ -168,6 +225,7 @@ def kernels_of(rows, precision_tag="float", headline=True):
     for k, v in rows.items():
         va = valu_of(k, v["avg_us"], precision_tag) if headline else None
         out[k] = {"avg_us": round(v["avg_us"], 2), "GBps": round(v["gbs"], 1),
+                  "bytes": int(v["bytes"]), "implementation_bytes": int(v["impl_bytes"]),
                   "valu_frac": None if va is None else va["frac"]}
     return out
 
@@ -345,22 +403,66 @@ def run_serving(templates, arr, tmpl, steps, stream, budget_particles, superstep
 
 
 # ----------------------------------------------------------- cpu oracle
-def cpu_baseline(sc, budget_s):
+def cpu_model():
+    """The host CPU's model name (/proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads():
+    """Threads for the all-core oracle run: the CPUs this process may use,
+    at most 16 (a one-GPU share of the host)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if env:
+        n = min(n, env)
+    return max(1, min(n, 16))
+
+
+def oracle_rate(sc, threads, budget_s, max_steps=50, steps=None):
+    """particle-steps/s of the oracle (cell-list mode) on `sc` with `threads`
+    OpenMP threads: one untimed step, then `steps` (or as many as fit
+    budget_s, at most max_steps) timed."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    threads = min(threads, 16)
     s = oracle.Sim(sc, mode=1, threads=threads)
     t0 = time.perf_counter()
     s.step(1)
     t1 = time.perf_counter() - t0
-    k = max(1, min(50, int(budget_s / max(t1, 1e-6))))
+    k = steps if steps else max(1, min(max_steps, int(budget_s / max(t1, 1e-6))))
     t0 = time.perf_counter()
     s.step(k)
     el = time.perf_counter() - t0
-    return {"value": round(sc.n * k / el, 1), "unit": "particle-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "%d steps (after 1 untimed) of the same %d-particle workload, cell-list mode, "
-                      "OpenMP over particles" % (k, sc.n)}
+    return sc.n * k / el, k
+
+
+def cpu_baseline(sc, budget_s, plain=None):
+    """The oracle on the host's cores: the headline workload (a bounded
+    number of steps) on all cores of the process's share and on one core,
+    and the 2,000-sphere plain workload over its 1000 steps on both."""
+    th = host_threads()
+    rate, k = oracle_rate(sc, th, budget_s)
+    rate1, k1 = oracle_rate(sc, 1, budget_s, max_steps=20)
+    out = {"value": round(rate, 1), "unit": "particle-steps/s", "cores": th, "kind": "oracle",
+           "sample": "%d steps (after 1 untimed) of the same %d-particle workload, cell-list mode, "
+                     "OpenMP over particles" % (k, sc.n),
+           "single_core": {"value": round(rate1, 1), "cores": 1,
+                           "sample": "%d steps (after 1 untimed), one thread" % k1},
+           "cpu_model": cpu_model(), "cpus_visible": os.cpu_count()}
+    if plain is not None:
+        pa, ka = oracle_rate(plain, th, 0, steps=1000)
+        p1, k1 = oracle_rate(plain, 1, 0, steps=1000)
+        out["plain_2000_fp64"] = {"all_cores": round(pa, 1), "single_core": round(p1, 1),
+                                  "cores": th, "steps": ka, "unit": "particle-steps/s"}
+    return out
 
 
 def main():
@@ -384,7 +486,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget", type=int, default=8_000_000)
     ap.add_argument("--superstep", type=int, default=20)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="first run a plain device-to-device copy of this many MiB 5 times "
                          "(reference reads/writes for HBM traffic counters)")
@@ -392,6 +494,10 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--dense-n", type=int, default=8_000_000)
     ap.add_argument("--dense-steps", type=int, default=100)
+    ap.add_argument("--grow-increments", type=int, default=200,
+                    help="radius increments of the dense pack's growth")
+    ap.add_argument("--grow-steps", type=int, default=20,
+                    help="DEM steps after each radius increment")
     ap.add_argument("--ablation-sizes", default="131072,524288,2097152")
     ap.add_argument("--ablation-steps", type=int, default=20)
     ap.add_argument("--only", choices=("all", "single", "batch", "serve", "ablation", "dense"),
@@ -433,8 +539,8 @@ def main():
     dense = None
     if not a.no_dense:
         t = time.perf_counter()
-        dense = gen.config_dense_shear(n=a.dense_n)
-        log("dense input: %d spheres in %.1fs" % (dense.n, time.perf_counter() - t))
+        dense = gen.config_dense_start(n=a.dense_n)
+        log("dense start: %d spheres in %.1fs" % (dense.n, time.perf_counter() - t))
     serve_in = None
     if not a.no_serve:
         t = time.perf_counter()
@@ -497,6 +603,7 @@ def headline(a, sc, stream, log):
                    "history_matched_per_step": round(mixed["matched"], 1),
                    "cells": list(mixed["info"]["cells"]), "key_bits": mixed["info"]["key_bits"]},
         "roofline": roofline_of(rows),
+        "contact_kernels_roofline": contact_kernels_of(rows),
         "kernels": kernels_of(rows),
     }
     step_bytes = sum(r["bytes"] for r in rows.values())
@@ -534,28 +641,52 @@ def headline(a, sc, stream, log):
                                  round(f64["seconds_profiled"] / a.steps * 1e3, 4),
                              "roofline": roofline_of(rows64, "double"),
                              "kernels": kernels_of(rows64, "double")}
+        # the 2,000-sphere plain workload in FP64 over its 1000 steps (launch
+        # latency bound at this size)
+        import gen
+        pl = gen.config_plain()
+        r = run_single(pl, PREC_FP64, 1000, a.warmup, stream)
+        out["plain_2000_fp64"] = {"value": round(pl.n * 1000 / r["seconds"], 1),
+                                  "unit": "particle-steps/s", "steps": 1000,
+                                  "ms_per_step": round(r["seconds"] / 1000 * 1e3, 4),
+                                  "contacts_per_particle": round(r["contacts"] / pl.n, 4)}
 
     return out
 
 
+def gen_dense_run(start, g):
+    import gen
+    return gen.dense_run_scene(start, g["x"], g["v"], g["w"])
+
+
 def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
     if dense is not None:
-        # the 8M dense sheared pack: throughput and contact-table churn
-        from paper_1503_03553_amd import PREC_MIXED
-        r = run_single(dense, PREC_MIXED, a.dense_steps, a.warmup, stream)
-        rows = phase_rows(r["prof"], dense.n, r["contacts"], r["contacts_old"], False,
+        # the 8M dense sheared pack: grown to phi 0.55 on the GPU (not timed),
+        # then the sheared run: throughput and contact-table churn
+        from paper_1503_03553_amd import PREC_MIXED, pack
+        t = time.perf_counter()
+        g = pack.grown(dense, increments=a.grow_increments, steps_per_increment=a.grow_steps,
+                       stream=stream, log=log)
+        grow_s = time.perf_counter() - t
+        run = gen_dense_run(dense, g)
+        log("dense pack grown in %.1fs: %s" % (grow_s, json.dumps(g["stats"])))
+        r = run_single(run, PREC_MIXED, a.dense_steps, a.warmup, stream)
+        rows = phase_rows(r["prof"], run.n, r["contacts"], r["contacts_old"], False,
                           r["info"]["key_bits"])
         m = r["contacts"]
         out["dense_shear_8m"] = {
-            "value": round(dense.n * a.dense_steps / r["seconds"], 1), "unit": "particle-steps/s",
-            "particles": dense.n, "steps": a.dense_steps,
+            "value": round(run.n * a.dense_steps / r["seconds"], 1), "unit": "particle-steps/s",
+            "particles": run.n, "steps": a.dense_steps, "warmup": a.warmup,
             "ms_per_step": round(r["seconds"] / a.dense_steps * 1e3, 4),
-            "workload": "%d spheres, phi %.2f, Lees-Edwards shear %g/s, mixed precision" % (
-                dense.n, dense.meta.get("phi", 0.0), dense.shear_rate),
-            "contacts_per_particle": round(m / dense.n, 4),
+            "workload": "%d spheres, phi %.2f grown on the GPU from RSA at phi %.2f, Lees-Edwards "
+                        "shear %g/s, mixed precision" % (run.n, dense.meta["phi"],
+                                                         dense.meta["phi0"], run.shear_rate),
+            "growth": dict(g["stats"], seconds=round(grow_s, 2)),
+            "contacts_per_particle": round(m / run.n, 4),
             "churn_per_step": {"created": round(m - r["matched"], 1),
                                "broken": round(r["contacts_old"] - r["matched"], 1),
                                "created_frac": round((m - r["matched"]) / max(m, 1), 5)},
+            "contact_kernels_roofline": contact_kernels_of(rows),
             "kernels": kernels_of(rows, headline=False)}
     if batch:
         from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
@@ -615,7 +746,8 @@ def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
             "rows": run_ablation(sizes, a.ablation_steps, 5, stream, log)}
 
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(sc, a.cpu_budget)
+        import gen
+        out["cpu_baseline"] = cpu_baseline(sc, a.cpu_budget, gen.config_plain())
 
 
 if __name__ == "__main__":

@@ -52,3 +52,27 @@ def test_counter_summaries_match_the_kernel_source_or_are_ignored():
         rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_dilute_1m.json")))
         key = [k for k in rec["per_launch_bytes"] if bench.kernel_is(k, "k_force", "float")]
         assert len(key) == 1 and traffic == rec["per_launch_bytes"][key[0]]
+
+
+def test_method_bytes_count_the_method_not_the_implementation():
+    n, m, mo = 1000, 300, 250
+    # contact search: record 28, cell ranges 8, row 4, partner index 4 per contact
+    assert bench.method_bytes("detect", n, m, mo, False, 20) == 40 * n + 4 * m
+    # history match + contact law + sums + integration + hashing in one pass:
+    # 176 per particle, 4 + 28 per contact, 28 per old contact; F/T only when stored
+    assert bench.method_bytes("force", n, m, mo, False, 20) == 176 * n + 32 * m + 28 * mo
+    assert bench.method_bytes("force", n, m, mo, True, 20, force_out=True) == \
+        (176 + 48) * n + 32 * m + 28 * mo
+    # the implementation moves more than the method needs in both kernels
+    for ph in ("detect", "force"):
+        assert bench.kernel_bytes(ph, n, m, mo, False, 20) > bench.method_bytes(ph, n, m, mo,
+                                                                                False, 20)
+    # the reorder gathers positions only: its own count is below the method's 168
+    assert bench.method_bytes("reorder", n, m, mo, False, 20) == 100 * n
+    rows = bench.phase_rows({"detect": (0.05, 1), "force": (0.07, 1)}, n, m, mo, False, 20)
+    c = bench.contact_kernels_of(rows)
+    assert c["bytes_per_step"] == 40 * n + 4 * m + 176 * n + 32 * m + 28 * mo
+    assert abs(c["us_per_step"] - 120.0) < 1e-9
+    r = bench.roofline_of(rows)
+    assert r["kernel"] == "k_force" and r["overhead_bytes_per_launch"] == \
+        bench.kernel_bytes("force", n, m, mo, False, 20) - r["bytes_per_launch"]
