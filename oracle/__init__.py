@@ -223,7 +223,7 @@ class Sim:
         self.cF = None
         self.cT = None
         # per contact: |F_t| before the cap, mu |F_n|, rounding scale of the
-        # sliding test, sum of the magnitudes of the terms of Eq. (1)
+        # sliding test, sum of the magnitudes of the terms of Eq. (1), k_t
         self.cQ = None
 
     def step(self, k=1, keep_contact_forces=False):
@@ -236,7 +236,7 @@ class Sim:
             odt = np.zeros((cap, 3))
             cF = np.zeros((cap, 3)) if keep_contact_forces else None
             cT = np.zeros((cap, 3)) if keep_contact_forces else None
-            cQ = np.zeros((cap, 4)) if keep_contact_forces else None
+            cQ = np.zeros((cap, 5)) if keep_contact_forces else None
             m = ctypes.c_long()
             h = self.hist
             rc = lib().orc_step(ctypes.byref(self.P), n, self.x.ctypes.data, self.v.ctypes.data,

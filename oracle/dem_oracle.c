@@ -151,8 +151,8 @@ typedef struct {
      * eta |v|)), the scale of the rounding of a lower-precision evaluation;
      * of Eq. (1), the sum of the magnitudes of its four terms before the cap
      * (k_n dn^1.5 + eta |v_n| + k_t |dt| + eta |v_t|), the scale of the
-     * rounding of a lower-precision evaluation of the force */
-    double ft_pre, mufn, scale, fterm;
+     * rounding of a lower-precision evaluation of the force; and k_t */
+    double ft_pre, mufn, scale, fterm, kt;
 } orc_pair_out;
 
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
@@ -256,6 +256,7 @@ void orc_contact_law(const orc_params *P, int mi, int mj, double ri, double rs, 
     o->scale = kt * sqrt(dot3(dtv, dtv)) + eta * (sqrt(dot3(v, v)) + sqrt(dot3(rw, rw))) +
                mu * (el + eta * sqrt(dot3(v, v)));
     o->fterm = el + eta * sqrt(dot3(vn, vn)) + kt * sqrt(dot3(dtv, dtv)) + eta * sqrt(dot3(vt, vt));
+    o->kt = kt;
     o->capped = 0;
     /* Eq. (4): sliding friction, then the displacement that reproduces it */
     if (ft > mu * fn) {
@@ -557,8 +558,9 @@ static long hist_find(long m, const uint32_t *hi, const uint32_t *hj, uint32_t i
  *   history out: up to cap_out contacts; *m_out receives the count
  *   F_out, T_out (n,3) optional: per-particle totals used in this step
  *   cF, cT (cap_out,3) optional: per-contact force and torque on i
- *   cQ (cap_out,4) optional: per contact |F_t| before the cap, mu |F_n|,
- *     the rounding scale of the sliding test and that of Eq. (1) (orc_pair_out)
+ *   cQ (cap_out,5) optional: per contact |F_t| before the cap, mu |F_n|,
+ *     the rounding scale of the sliding test and that of Eq. (1), and k_t
+ *     (orc_pair_out)
  *   mode 0 brute force, 1 cell list; nthreads 0 = OpenMP default
  * Returns 0, -1 (history capacity), -2 (a per-particle contact list over
  * 64) or -3 (a pair touching through two images).
@@ -672,10 +674,11 @@ int orc_step(const orc_params *P, long n, double *x, double *v, double *w, const
                 if (cT) cT[3 * q + a] = o.T[a];
             }
             if (cQ) {
-                cQ[4 * q] = o.ft_pre;
-                cQ[4 * q + 1] = o.mufn;
-                cQ[4 * q + 2] = o.scale;
-                cQ[4 * q + 3] = o.fterm;
+                cQ[5 * q] = o.ft_pre;
+                cQ[5 * q + 1] = o.mufn;
+                cQ[5 * q + 2] = o.scale;
+                cQ[5 * q + 3] = o.fterm;
+                cQ[5 * q + 4] = o.kt;
             }
         }
         for (int a = 0; a < 3; ++a) {

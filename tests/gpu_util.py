@@ -6,7 +6,9 @@ scale (sum of |F_ij| over a particle's contacts plus |m g|; in mixed
 precision the sum over its contacts of the magnitudes of the four terms of
 Eq. (1), elastic and damping normal, spring and damping tangential, plus
 |m g|), tangential displacement 1e-5 of the larger of its magnitude and the
-contact's overlap, contact sets bit-exact; trajectories 1e-4 of the largest
+contact's overlap (in mixed precision, for a contact on the sliding cap, also
+of that rounding scale over k_t: Eq. (4) resets the displacement from the
+capped FP32 force), contact sets bit-exact; trajectories 1e-4 of the largest
 displacement after 100 steps.  In mixed precision the contacts that sit on
 the sliding cap within an FP32 rounding bound (cap ties) and their owners
 are counted instead of held to the tolerance.
@@ -154,6 +156,12 @@ def check_step(o, scene, st, ci, cj, cdt, tol, ties=False, x0=None, time=0.0):
     scale = np.linalg.norm(ref, axis=1)
     dn = contact_overlaps(scene, scene.x if x0 is None else x0, o.hist.i, o.hist.j, time)
     floor = np.maximum(dn, 1e-9 * (scale.max() if scale.size else 0.0)) + 1e-300
+    if ties:
+        # a capped contact's displacement is reset from the FP32 capped force:
+        # its rounding is that of the force terms, over k_t
+        capped = o.cQ[:, 0] > o.cQ[:, 1]
+        floor = np.where(capped, np.maximum(floor, o.cQ[:, 3] / np.maximum(o.cQ[:, 4], 1e-300)),
+                         floor)
     rel_dt = err / np.maximum(scale, floor)
     tie = cap_ties(o) if ties else np.zeros(len(ref), bool)
     bad = (rel_dt > tol) & ~tie
