@@ -106,6 +106,15 @@ def lib():
     """Load libdem.so (raises if it has not been built)."""
     global _LIB
     if _LIB is None:
+        # PyTorch ships its own HIP and HSA runtimes under the sonames of
+        # ROCm's.  Loaded first, they are the ones libdem.so binds to, so the
+        # process has one runtime and torch's device memory and streams are
+        # valid handles for the library; loaded after libdem.so, torch would
+        # bring a second HSA runtime that cannot open the GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(_SO):
             raise RuntimeError("libdem.so not found at %s; run __graft_entry__.build() or "
                                "python paper_1503_03553_amd/build.py" % _SO)
