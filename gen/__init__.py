@@ -393,10 +393,15 @@ def scene_cluster(seed, n_side=4, r=5e-6, overlap_max=2e-3, vel_sigma=0.05, jitt
 
 def scene_random(seed, n, phi=0.3, p_touch=0.7, touch_max=2e-3, walls=WALL_ALL,
                  periodic=0, gravity=(0.0, 0.0, -9.81), polydisperse=True, vel_sigma=0.1,
-                 shear_rate=0.0, n_materials=1):
-    """Seeded random RSA fill with touch seeding; optionally periodic or several materials."""
+                 shear_rate=0.0, n_materials=1, big_frac=0.0, big_r=8e-6):
+    """Seeded random RSA fill with touch seeding; optionally periodic or several
+    materials; with big_frac, that fraction of the spheres (chosen at random)
+    gets radius big_r."""
     rng = np.random.Generator(np.random.PCG64(seed))
     r = lognormal_radii(rng, n) if polydisperse else f32(np.full(n, 4e-6))
+    if big_frac > 0.0:
+        r = r.copy()
+        r[rng.random(n) < big_frac] = f32(np.array([big_r]))[0]
     L = box_side(r, phi)
     lo, hi = np.zeros(3), np.full(3, L)
     x = rsa(r, lo, hi, periodic=periodic, p_touch=p_touch, touch_max=touch_max, seed=seed)

@@ -109,8 +109,11 @@ typedef struct {
     int32_t precision;   /* dem_precision */
     int32_t kn_form;     /* 0: k_n with (2 - sigma^2)/E as printed in section 2;
                             1: textbook Hertz (1 - sigma^2)/E */
-    double cell_size;    /* [m]; 0 = the largest contact distance 2 r_max.  Must be
-                            >= 2 r_max. */
+    double cell_size;    /* [m]; 0 = automatic: twice the radius cut of the two-level
+                            search (the radius exceeded by about 2 % of the
+                            particles, at least r_max / 2) with the default search,
+                            the largest contact distance 2 r_max with the full one.
+                            A given size must be >= 2 r_max (one-level search). */
     uint64_t max_contacts; /* initial contact-table capacity; 0 = automatic */
     uint32_t flags;        /* DEM_FLAG_* */
     uint32_t n_extra_walls;          /* entries of extra_walls, at most DEM_MAX_WALLS */
@@ -163,6 +166,10 @@ typedef struct {
     uint32_t cells[3];      /* cell grid */
     uint32_t key_bits;      /* bits of the cell key sorted each step */
     uint64_t device_bytes;  /* device memory held */
+    double radius_cut;      /* two-level contact search: particles of a larger radius
+                               scan a two-cell stencil themselves; the largest
+                               radius when none do */
+    uint64_t big;           /* particles above the radius cut */
 } dem_info;
 
 /*
@@ -201,7 +208,8 @@ dem_status dem_create(const dem_params *params, const dem_material *mats, uint32
  * force loop split into a contact search and a force loop).  One step is:
  * contact search (by default over the upper half of the 27 cells around
  * each particle, each pair tested once and entered in both particles'
- * lists; the full 27-cell scan of section 3.3 with DEM_FLAG_FULL_DETECT),
+ * lists, the few particles above the radius cut scanning a two-cell stencil
+ * themselves; the full 27-cell scan of section 3.3 with DEM_FLAG_FULL_DETECT),
  * contact history match, contact law (Eq. 1-4, torque), per-particle sums
  * with gravity, semi-implicit Euler integration of velocity, position and
  * angular velocity, cell hashing, the sort by cell key (merge of the
@@ -405,6 +413,9 @@ dem_status dem_pool_job_info(dem_pool *pool, uint64_t job, dem_job_info *info);
 /* A job's state in pid order, as dem_get_state (blocking); NULL skips. */
 dem_status dem_pool_get_state(dem_pool *pool, uint64_t job, double *x, double *v, double *w);
 
+/* New radii of a job (pid order), as dem_set_radii (between steps). */
+dem_status dem_pool_set_radii(dem_pool *pool, uint64_t job, const float *radius);
+
 /* Free a job's tiles, cells and slot (between steps; enqueued in order). */
 dem_status dem_pool_remove(dem_pool *pool, uint64_t job);
 
@@ -414,11 +425,13 @@ dem_status dem_pool_remove(dem_pool *pool, uint64_t job);
 dem_status dem_pool_capacity(dem_pool *pool, uint64_t *free_particles, uint64_t *free_cells,
                              uint32_t *free_jobs);
 
-/* Cells of the grid a job of n particles with these parameters and largest
- * radius rmax gets (what it takes of the pool's max_cells); 0 if the
- * parameters are invalid.  Section 3.3: the cell-based search needs cells at
- * least as wide as the largest contact distance.  With dem_pool_capacity
- * this tells whether a job fits before its data is prepared. */
+/* The most cells the grid of a job of n particles with these parameters and
+ * largest radius rmax can get (what it may take of the pool's max_cells); 0
+ * if the parameters are invalid.  Section 3.3: the cell-based search needs
+ * cells at least as wide as the largest contact distance; with the two-level
+ * search of the default (half) search, cells of twice a radius cut of at
+ * least rmax / 2.  With dem_pool_capacity this tells whether a job fits
+ * before its data is prepared. */
 uint64_t dem_job_cells(const dem_params *params, uint64_t n, double rmax);
 
 /* Kernel timing of the pool's steps, as dem_profile / dem_profile_read. */

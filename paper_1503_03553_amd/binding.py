@@ -30,13 +30,15 @@ STATUS = {0: "DEM_OK", -1: "DEM_EINVAL", -2: "DEM_ENOMEM", -3: "DEM_ECAPACITY",
           -4: "DEM_ENONFINITE", -5: "DEM_EDEVICE", -6: "DEM_EBUSY"}
 
 # every symbol include/dem.h declares
-EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state", "dem_get_contacts",
+EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state",
+           "dem_get_contacts",
            "dem_set_contacts", "dem_set_state", "dem_set_radii", "dem_get_info", "dem_destroy",
            "dem_status_str",
            "dem_footprint", "dem_profile", "dem_profile_read", "dem_pool_footprint",
            "dem_pool_create", "dem_pool_add", "dem_pool_step", "dem_pool_sync", "dem_pool_poll",
            "dem_pool_job_info", "dem_pool_get_state", "dem_pool_remove", "dem_pool_capacity",
            "dem_job_cells", "dem_job_prepare", "dem_job_prep_cells", "dem_pool_add_prepared",
+           "dem_pool_set_radii",
            "dem_job_prep_free",
            "dem_pool_profile", "dem_pool_profile_read", "dem_pool_destroy")
 
@@ -78,7 +80,8 @@ class Info(ctypes.Structure):
                 ("capacity", ctypes.c_uint64), ("regrows", ctypes.c_uint64),
                 ("sum_contacts", ctypes.c_uint64), ("sum_matched", ctypes.c_uint64),
                 ("sum_old", ctypes.c_uint64), ("cells", ctypes.c_uint32 * 3),
-                ("key_bits", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64)]
+                ("key_bits", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
+                ("radius_cut", ctypes.c_double), ("big", ctypes.c_uint64)]
 
 
 class PoolParams(ctypes.Structure):
@@ -170,6 +173,8 @@ def lib():
         L.dem_pool_job_info.argtypes = [_vp, ctypes.c_uint64, ctypes.POINTER(JobInfo)]
         L.dem_pool_get_state.restype = ctypes.c_int
         L.dem_pool_get_state.argtypes = [_vp, ctypes.c_uint64, _vp, _vp, _vp]
+        L.dem_pool_set_radii.restype = ctypes.c_int
+        L.dem_pool_set_radii.argtypes = [_vp, ctypes.c_uint64, _vp]
         L.dem_pool_remove.restype = ctypes.c_int
         L.dem_pool_remove.argtypes = [_vp, ctypes.c_uint64]
         L.dem_pool_capacity.restype = ctypes.c_int
@@ -585,6 +590,12 @@ class Pool:
         _check(lib().dem_pool_get_state(self._handle(), int(job), x.ctypes.data, v.ctypes.data,
                                         w.ctypes.data), "dem_pool_get_state")
         return dict(x=x, v=v, w=w)
+
+    def set_radii(self, job, r):
+        """New radii of a job (pid order), rounded to FP32; state and history kept."""
+        r32 = _c(r, np.float32, (self._n[int(job)],))
+        _check(lib().dem_pool_set_radii(self._handle(), int(job), r32.ctypes.data),
+               "dem_pool_set_radii")
 
     def remove(self, job):
         _check(lib().dem_pool_remove(self._handle(), int(job)), "dem_pool_remove")

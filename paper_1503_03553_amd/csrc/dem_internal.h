@@ -41,12 +41,18 @@ struct Geo {
     double lo[3], hi[3], L[3];
     double inv_cell[3];
     double cw[3];           // cell widths L / nc
-    double reach;           // largest radius of the job plus a rounding margin: a
+    double reach;           // largest radius of the particles the cell stencil pairs
+                            // (all, or those up to rcut) plus a rounding margin: a
                             // partner of particle i is within r_i + reach of it
+    double reach_big;       // largest radius of the job plus the margin (wide scan)
     double inv_L[3];        // 1 / L, for the minimum-image choice
     int nc[3];
     uint32_t walls, periodic;
     int le;                 // Lees-Edwards shear active
+    float rcut;             // two-level contact search: particles of a larger radius
+                            // ("big") pair through the wide scan; >= every radius
+                            // when the job has none
+    int nbig;               // whether the job has big particles
     int key_bits;           // bits of the cell key
     int xbits;              // bits of its x part (the fastest-varying index)
     double g[3];

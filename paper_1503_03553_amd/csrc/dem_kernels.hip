@@ -386,6 +386,7 @@ template <bool PER>
 struct PreFilter {
     float4 me;
     float Lx, Ly, Lz, Df, iLx, iLy, iLz, rm;
+    float rc;  // candidates with a larger radius are the wide scan's (two-level search)
     uint32_t per;
     __device__ PreFilter(const Geo& G, const double4& a, float margin) {
         me = far_record(G, a);
@@ -398,6 +399,7 @@ struct PreFilter {
         iLz = (float)G.inv_L[2];
         rm = me.w + margin;
         per = G.periodic;
+        rc = G.rcut;
     }
     __device__ bool operator()(const float4& b) const {
         float dx = b.x - me.x, dy = b.y - me.y, dz = b.z - me.z;
@@ -414,7 +416,7 @@ struct PreFilter {
             if (per & 4u) dz += (float)(-(int)rintf(dz * iLz)) * Lz;
         }
         const float sm = rm + b.w;
-        return !(dx * dx + dy * dy + dz * dz >= sm * sm);
+        return !(dx * dx + dy * dy + dz * dz >= sm * sm) && b.w <= rc;
     }
 };
 
@@ -697,6 +699,149 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
 }
 
 // ------------------------------------------------------------ half detect
+// Wide scan of one large particle ("big": radius above the job's cut) by the
+// whole wavefront (two-level contact search).  The one-cell stencil of the
+// half search only holds partners of particles no larger than the cut; a big
+// particle instead scans every cell within two cells of its own (cells are
+// at least as wide as its largest contact distance halved) and enters each
+// contact it finds in both lists.  A pair of two big particles is entered by
+// the one at the lower position.  Lane l < 25 forms row l of the 5 x 5 rows
+// of the stencil (its cells within reach, at most two contiguous ranges when
+// the row wraps around a periodic x axis); the wavefront then tests the
+// concatenated ranges 64 candidates at a time with the exact FP64 predicate.
+// s_w: this wavefront's 64 words x 4 of scratch in LDS (column lane,
+// stride DTILE).
+template <bool PER, typename Append>
+__device__ __forceinline__ void wide_scan(const Geo& G, const uint2* __restrict__ cells,
+                                          const double4* __restrict__ xr, uint32_t nsz,
+                                          const double4& b, uint32_t bi, int lane,
+                                          uint32_t* s_w, Append append) {
+    const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
+    const bool px = PER && (G.periodic & 1u), py = PER && (G.periodic & 2u),
+               pz = PER && (G.periodic & 4u), le = PER && G.le;
+    const double rb = (double)meta_r(b.w);
+    const uint32_t bpid = meta_pid(b.w);
+    const double reach = rb + G.reach_big;
+    const int cy = cell_coord(G, b.y, 1), cz = cell_coord(G, b.z, 2);
+    uint32_t lo1 = 0, n1 = 0, lo2 = 0, n2 = 0;
+    if (lane < 25) {
+        const int oy = lane % 5 - 2, oz = lane / 5 - 2;
+        int y = cy + oy, z = cz + oz, ky = 0;
+        bool ok = true;
+        if (y < 0 || y >= ny) {
+            if (!py) ok = false;
+            ky = y < 0 ? -1 : 1;
+            y -= ky * ny;
+        }
+        if (z < 0 || z >= nz) {
+            if (!pz) ok = false;
+            z = z < 0 ? z + nz : z - nz;
+        }
+        // squared gaps to the row's (y, z) slab, in the unwrapped frame
+        double gy = 0.0, gz = 0.0;
+        if (oy > 0) gy = G.lo[1] + (double)(cy + oy) * G.cw[1] - b.y;
+        if (oy < 0) gy = b.y - (G.lo[1] + (double)(cy + oy + 1) * G.cw[1]);
+        if (oz > 0) gz = G.lo[2] + (double)(cz + oz) * G.cw[2] - b.z;
+        if (oz < 0) gz = b.z - (G.lo[2] + (double)(cz + oz + 1) * G.cw[2]);
+        gy = fmax(gy, 0.0);
+        gz = fmax(gz, 0.0);
+        const double rx2 = reach * reach - gy * gy - gz * gz;
+        if (ok && rx2 > 0.0) {
+            const double rx = sqrt(rx2);
+            // across a sheared y boundary the partner row is offset along x
+            const double bx = le && ky != 0 ? b.x - (double)ky * G.le_shift : b.x;
+            const double lim = 4.0 * (double)nx;
+            double fl = floor((bx - rx - G.lo[0]) * G.inv_cell[0]);
+            double fh = floor((bx + rx - G.lo[0]) * G.inv_cell[0]);
+            double fc = floor((bx - G.lo[0]) * G.inv_cell[0]);
+            fl = fmin(fmax(fl, -lim), lim);  // also NaN -> -lim
+            fh = fmin(fmax(fh, -lim), lim);
+            fc = fmin(fmax(fc, -lim), lim);
+            int xl = (int)fl, xh = (int)fh;
+            int xc = (int)fc;
+            if (px) {
+                // the window relative to the cell of the x-aligned image in [0, nx)
+                int m = xc % nx;
+                m = m < 0 ? m + nx : m;
+                xl -= xc - m;
+                xh -= xc - m;
+                xc = m;
+            }
+            if (!px) {
+                // cells clamp coordinates outside the box into the border cells
+                xc = cell_coord(G, b.x, 0);
+                xl = xl < 0 ? 0 : (xl > nx - 1 ? nx - 1 : xl);
+                xh = xh < 0 ? 0 : (xh > nx - 1 ? nx - 1 : xh);
+            }
+            xl = xl < xc - 2 ? xc - 2 : xl;
+            xh = xh > xc + 2 ? xc + 2 : xh;
+            const uint32_t row = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx;
+            uint32_t a1 = 0xFFFFFFFFu, e1 = 0u, a2 = 0xFFFFFFFFu, e2 = 0u;
+            for (int x = xl; x <= xh; ++x) {
+                // a window of at most 5 cells on a periodic axis of at least
+                // 5 wraps at most once; its wrapped cells form the second range
+                const bool wrapped = x < 0 || x >= nx;
+                const int xw = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+                const uint2 c = cells[row + (uint32_t)xw];
+                if (wrapped) merge_range(c, a2, e2); else merge_range(c, a1, e1);
+            }
+            if (e1 > a1) { lo1 = a1; n1 = e1 - a1; }
+            if (e2 > a2) { lo2 = a2; n2 = e2 - a2; }
+        }
+    }
+    // exclusive prefix of the rows' candidate counts over the wavefront
+    const uint32_t cnt = n1 + n2;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    const uint32_t total = __shfl(inc, 63, 64);
+    s_w[0] = inc - cnt;
+    s_w[DTILE] = lo1;
+    s_w[2 * DTILE] = n1;
+    s_w[3 * DTILE] = lo2;
+    __builtin_amdgcn_wave_barrier();
+    uint32_t* const s0 = s_w - lane;  // lane 0's column of this wavefront
+    for (uint32_t k0 = 0; k0 < total; k0 += 64) {
+        const uint32_t q = k0 + (uint32_t)lane;
+        if (q < total) {
+            // the row whose candidates hold q: the last of rows 0..24 with
+            // exclusive prefix <= q
+            int lo = 0, hi = 24;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s0[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            const uint32_t off = q - s0[lo];
+            const uint32_t m1 = s0[2 * DTILE + lo];
+            const uint32_t j = off < m1 ? s0[DTILE + lo] + off : s0[3 * DTILE + lo] + (off - m1);
+            if (j != bi && j < nsz) {
+                const double4 c = xr[j];
+                const float rj = meta_r(c.w);
+                // a pair of two big particles: entered from the lower position
+                if (!(rj > G.rcut && j < bi)) {
+                    double dx = c.x - b.x, dy = c.y - b.y, dz = c.z - b.z;
+                    if (PER) {
+                        double Sx, Sy, Sz;
+                        int ky;
+                        image_shift(G, dx, dy, dz, Sx, Sy, Sz, ky);
+                        dx = dx + Sx;
+                        dy = dy + Sy;
+                        dz = dz + Sz;
+                    }
+                    if (touching(dx, dy, dz, rb + (double)rj)) {
+                        append(bi, j, meta_pid(c.w));
+                        append(j, bi, bpid);
+                    }
+                }
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Contact search that tests each pair once: the lane of a particle walks the
 // upper half of its cell stencil (the half-shell of candidate_ranges, about
 // 13.5 of the 27 cells for every particle alike, so the lanes of a wave stay
@@ -709,6 +854,12 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
 // cache lines and are read coalesced.  Box faces and extra walls go into the
 // particle's own list.  The force kernel (k_force with HK) turns the lists
 // into rows ordered by partner id: the rows of the full search.
+//
+// Two-level search: when a job has particles larger than its radius cut
+// G.rcut (a few per cent of a polydisperse job), its cells are sized for the
+// cut instead of the largest radius, which shrinks every particle's stencil;
+// the lanes skip those "big" particles (as partners and as walkers), and each
+// wavefront then runs the wide scan of its own big particles.
 template <int KMAX, bool PER>
 __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __restrict__ jobs,
                                                        const double4* __restrict__ xr,
@@ -719,7 +870,7 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     // survivors of the FP32 pre-filter, SB per lane (slot SB takes the
     // writes of a lane whose buffer is full; such a lane re-walks with the
     // exact test and enters its contacts directly, so the buffer need not
-    // hold a whole row)
+    // hold a whole row); afterwards the wide scans' row table
     constexpr int SB = 8;
     __shared__ uint32_t s_j[(SB + 1) * DTILE];
     // the half stencil has 5 rows: at most 5 ranges (10 with the wrapped x
@@ -741,7 +892,9 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     const Job& J = *Jp;
     const Geo& G = J.g;
     cells += J.cell_base;
-    if (i >= J.p0 + J.n) return;
+    // lanes past the job's last particle stay (the wide scan needs every
+    // lane of the wavefront) but search nothing
+    const bool valid = i < J.p0 + J.n;
     const uint32_t nsz = P.ns;
     auto append = [&](uint32_t p, uint32_t q, uint32_t pid) {
         const uint32_t k = atomicAdd(&deg[p], 1u);
@@ -749,7 +902,9 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     };
     const double ri = (double)meta_r(a.w);
     const uint32_t pi = meta_pid(a.w);
-    const uint32_t nw = candidate_ranges<PER, true>(G, a, ri, cells, s_win + t, DTILE, nullptr, i);
+    const bool big = valid && meta_r(a.w) > G.rcut;
+    const uint32_t nw = (valid && !big) ?
+        candidate_ranges<PER, true>(G, a, ri, cells, s_win + t, DTILE, nullptr, i) : 0u;
     // In a periodic box a particle whose cell is at least one cell away from
     // every periodic boundary (on axes of 5 cells or more) has all its
     // candidates within 2 cells, less than 0.4 box lengths: the image shift
@@ -820,6 +975,7 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
             for (uint32_t jx = rg2.x; jx < rg2.y; ++jx) {
                 if (jx >= nsz) continue;
                 const double4 b = xr[jx];
+                if (meta_r(b.w) > G.rcut) continue;  // the wide scan's pair
                 double dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z;
                 if (PER && !plain) {
                     double Sx, Sy, Sz;
@@ -864,18 +1020,36 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
             }
         }
     }
-    // box faces, then extra walls: the particle's own list
-    if (G.walls) {
-        for (int f = 0; f < 6; ++f) {
-            if (!(G.walls & (1u << f))) continue;
-            const int ax = f >> 1;
-            const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
-            const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
-            if (dist < ri) append(i, FACE + (uint32_t)f, FACE + (uint32_t)f);
+    if (valid) {
+        // box faces, then extra walls: the particle's own list
+        if (G.walls) {
+            for (int f = 0; f < 6; ++f) {
+                if (!(G.walls & (1u << f))) continue;
+                const int ax = f >> 1;
+                const double pc = ax == 0 ? a.x : (ax == 1 ? a.y : a.z);
+                const double dist = (f & 1) ? G.hi[ax] - pc : pc - G.lo[ax];
+                if (dist < ri) append(i, FACE + (uint32_t)f, FACE + (uint32_t)f);
+            }
+        }
+        for (uint32_t k = 0; k < J.nxw; ++k)
+            if (wall_touch(J.xw[k], a.x, a.y, a.z, ri)) append(i, FACE + 6u + k, FACE + 6u + k);
+    }
+    if (G.nbig) {
+        // the wavefront's big particles, one at a time, by all its lanes
+        const int lane = t & 63;
+        unsigned long long bal = __ballot(big);
+        while (bal) {
+            const int src = __ffsll((long long)bal) - 1;
+            bal &= bal - 1ull;
+            double4 b;
+            b.x = __shfl(a.x, src, 64);
+            b.y = __shfl(a.y, src, 64);
+            b.z = __shfl(a.z, src, 64);
+            b.w = __shfl(a.w, src, 64);
+            const uint32_t bi = tile * DTILE + (uint32_t)(t - lane) + (uint32_t)src;
+            wide_scan<PER>(G, cells, xr, nsz, b, bi, lane, s_j + t, append);
         }
     }
-    for (uint32_t k = 0; k < J.nxw; ++k)
-        if (wall_touch(J.xw[k], a.x, a.y, a.z, ri)) append(i, FACE + 6u + k, FACE + 6u + k);
 }
 
 // ------------------------------------------------------------- contact law

@@ -90,6 +90,7 @@ struct HostJob {
     std::vector<float> r;
     std::vector<uint16_t> mat;
     std::vector<dem_wall> walls;  // extra walls (P.extra_walls is not kept)
+    bool two_level = false;       // grid sized for the radius cut (half search)
 };
 
 uint64_t tiles_of(uint64_t n) { return (n + TILE - 1) / TILE; }
@@ -319,6 +320,58 @@ bool in_periodic_box(const dem_params& P, const double* x) {
     for (int a = 0; a < 3; ++a)
         if (((P.periodic >> a) & 1u) && !(x[a] >= P.lo[a] && x[a] <= P.hi[a])) return false;
     return true;
+}
+
+// Radius cut of the two-level contact search: the radius exceeded by about
+// 2 % of the particles, but at least half the largest radius (so that the
+// largest contact distance spans at most two cells of twice the cut).  The
+// largest radius itself when that leaves no particle above the cut.
+double radius_cut(const float* radius, uint64_t n, double rmax) {
+    if (n < 64) return rmax;
+    std::vector<float> r(radius, radius + n);
+    const uint64_t k = (uint64_t)(0.98 * (double)(n - 1));
+    std::nth_element(r.begin(), r.begin() + (long)k, r.end());
+    const double rc = std::max((double)r[k], 0.5 * rmax);
+    return rc >= rmax ? rmax : rc;
+}
+
+// Grid of a job: cells at least twice the radius cut when the two-level
+// search applies (every periodic axis then needs 5 cells, so that the wide
+// scan's two-cell stencil meets no cell twice), else twice the largest
+// radius.  `used` receives the cut the grid supports (rmax for a one-level
+// grid): the grid may come out coarser than asked (a cell-count limit), and
+// the cut then grows with it.  Cells of twice the cut hold every pair of
+// particles up to the cut, and since the cut is at least rmax / 2 the
+// largest contact distance spans at most two cells.
+dem_status plan_job_grid(const dem_params& P, double rmax, double rcut, uint64_t n,
+                         Layout& lay, double& used) {
+    used = rmax;
+    if (rcut < rmax && P.cell_size == 0.0 && plan_grid(P, rcut, n, lay) == DEM_OK) {
+        bool ok = true;
+        double cmin = INFINITY;
+        for (int a = 0; a < 3; ++a) {
+            cmin = std::min(cmin, lay.cell[a]);
+            if (((P.periodic >> a) & 1u) && lay.nc[a] < 5) ok = false;
+        }
+        const double cut = std::min(rmax, 0.5 * cmin / 1.000001);
+        if (ok && cut < rmax) {
+            used = cut;
+            return DEM_OK;
+        }
+    }
+    return plan_grid(P, rmax, n, lay);
+}
+
+// The radius cut as the kernels compare it (a float no larger than `used`)
+// and the reaches of the two stencils.
+void set_cut(Geo& G, double used, double rmax, double span) {
+    float rc = (float)used;
+    if ((double)rc > used) rc = std::nextafter(rc, 0.0f);
+    if (used >= rmax) rc = (float)rmax;
+    G.rcut = rc;
+    G.nbig = used < rmax ? 1 : 0;
+    G.reach = (used < rmax ? (double)rc : rmax) + 1e-9 * span;
+    G.reach_big = rmax + 1e-9 * span;
 }
 
 dem_status validate(const dem_params* P, const dem_material* mats, uint32_t n_mats) {
@@ -770,7 +823,8 @@ struct Prepared {
 
 dem_status prepare_job(const dem_params* params, const dem_material* mats, uint32_t n_mats,
                        uint64_t n, const double* x, const double* v, const double* w,
-                       const float* radius, const uint16_t* mat_id, Prepared& pj) {
+                       const float* radius, const uint16_t* mat_id, bool two_level,
+                       Prepared& pj) {
     dem_status r = validate(params, mats, n_mats);
     if (r != DEM_OK) return r;
     if (n >= (uint64_t)FACE) return DEM_EINVAL;
@@ -789,10 +843,12 @@ dem_status prepare_job(const dem_params* params, const dem_material* mats, uint3
         rmax = lmin / 6.1;
     }
     Layout lay;
-    r = plan_grid(*params, rmax, n, lay);
+    double used = rmax;
+    r = plan_job_grid(*params, rmax, two_level ? radius_cut(radius, n, rmax) : rmax, n, lay, used);
     if (r != DEM_OK) return r;
     HostJob& J = pj.J;
     J = HostJob();
+    J.two_level = two_level;
     J.P = *params;
     J.walls.assign(params->extra_walls, params->extra_walls + params->n_extra_walls);
     J.P.extra_walls = nullptr;
@@ -821,7 +877,7 @@ dem_status prepare_job(const dem_params* params, const dem_material* mats, uint3
     // may sit a few rounding units outside its cell's slab
     double span = 0.0;
     for (int a = 0; a < 3; ++a) span = std::max(span, std::fabs(G.lo[a]) + std::fabs(G.hi[a]));
-    G.reach = rmax + 1e-9 * span;
+    set_cut(G, used, rmax, span);
     G.walls = params->walls;
     G.periodic = params->periodic;
     G.le = params->shear_rate != 0.0;
@@ -1348,8 +1404,9 @@ dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* 
 }
 
 // New radii of a job's particles (pid order), keeping positions, velocities
-// and contact history.  The grid stays: every cell must remain at least as
-// wide as the largest contact distance.  Masses and inertias follow the
+// and contact history.  The grid stays: its cells must remain at least as
+// wide as the largest contact distance, or, with the two-level search, as
+// twice the radius cut (which this sets anew) and as the largest radius.  Masses and inertias follow the
 // radii (they are computed from them in the kernels); the time step stays.
 dem_status set_radii_impl(dem_pool* s, int slot, const float* radius) {
     HostJob& J = s->jobs[slot];
@@ -1360,15 +1417,32 @@ dem_status set_radii_impl(dem_pool* s, int slot, const float* radius) {
         rmax = std::max(rmax, (double)radius[k]);
     }
     if (n == 0) return DEM_OK;
-    for (int a = 0; a < 3; ++a)
-        if (!(2.0 * rmax * 1.000001 <= J.lay.cell[a])) return DEM_EINVAL;
+    // the cut the grid allows (the largest, so the fewest big particles):
+    // pairs up to the cut within one cell, the largest radius within two
+    double cmin = INFINITY;
+    bool five = true;
+    for (int a = 0; a < 3; ++a) {
+        cmin = std::min(cmin, J.lay.cell[a]);
+        if (((J.P.periodic >> a) & 1u) && J.lay.nc[a] < 5) five = false;
+    }
+    double used = std::min(rmax, 0.5 * cmin / 1.000001);
+    if (!J.two_level || !five) used = rmax;
+    if (used >= rmax) {
+        if (!(2.0 * rmax * 1.000001 <= cmin)) return DEM_EINVAL;
+        used = rmax;
+    } else if (!(rmax * 1.000001 <= cmin)) {
+        return DEM_EINVAL;
+    }
     Job jd;
     dem_status r = read_job(s, slot, jd);
     if (r != DEM_OK) return r;
     double span = 0.0;
     for (int a = 0; a < 3; ++a) span = std::max(span, std::fabs(J.geo.lo[a]) + std::fabs(J.geo.hi[a]));
-    J.geo.reach = rmax + 1e-9 * span;
+    set_cut(J.geo, used, rmax, span);
     jd.g.reach = J.geo.reach;
+    jd.g.reach_big = J.geo.reach_big;
+    jd.g.rcut = J.geo.rcut;
+    jd.g.nbig = J.geo.nbig;
     // the radii travel through the sort's scratch keys (unused between steps)
     r = upload(s, s->keys_t, radius, n * sizeof(float));
     if (r == DEM_OK) r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
@@ -1430,7 +1504,10 @@ dem_status dem_create(const dem_params* params, const dem_material* mats, uint32
         rmax = lmin / 6.1;
     }
     Layout lay;
-    r = plan_grid(*params, rmax, n, lay);
+    double used = rmax;
+    r = plan_job_grid(*params, rmax,
+                      (n && half_search(params->flags)) ? radius_cut(radius, n, rmax) : rmax, n,
+                      lay, used);
     if (r != DEM_OK) return r;
     const uint64_t np = std::max<uint64_t>(1, tiles_of(n)) * TILE;
     uint32_t slots = 8;
@@ -1444,7 +1521,8 @@ dem_status dem_create(const dem_params* params, const dem_material* mats, uint32
     if (r != DEM_OK) return r;
     int slot = 0;
     Prepared pj;
-    r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, pj);
+    r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, half_search(params->flags),
+                    pj);
     if (r == DEM_OK) r = commit_job(p, pj, 0xFFFFFFFFu, &slot);
     if (r == DEM_OK) r = sync_impl(p);
     if (r != DEM_OK) {
@@ -1557,6 +1635,8 @@ dem_status dem_get_info(dem_sim* s, dem_info* info) {
     for (int a = 0; a < 3; ++a) info->cells[a] = (uint32_t)J.lay.nc[a];
     info->key_bits = (uint32_t)J.lay.key_bits;
     info->device_bytes = p->device_bytes;
+    info->radius_cut = (double)J.geo.rcut;
+    for (const float rr : J.r) info->big += rr > J.geo.rcut ? 1u : 0u;
     std::vector<TileStats> ts(J.ntiles);
     if (J.ntiles)
         HIPCHK(hipMemcpy(ts.data(), p->ts + J.tile0, J.ntiles * sizeof(TileStats), hipMemcpyDeviceToHost));
@@ -1678,7 +1758,8 @@ dem_status dem_pool_add(dem_pool* s, const dem_params* params, const dem_materia
     // host work first, while enqueued steps run; then the job is placed
     // between steps
     Prepared pj;
-    dem_status r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, pj);
+    dem_status r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id,
+                               half_search(s->flags), pj);
     if (r != DEM_OK) return r;
     r = sync_impl(s);
     if (r != DEM_OK) return r;
@@ -1703,7 +1784,8 @@ dem_status dem_job_prepare(const dem_params* params, const dem_material* mats, u
     if (!p) return DEM_ENOMEM;
     dem_status r = DEM_OK;
     try {
-        r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id, p->pj);
+        r = prepare_job(params, mats, n_mats, n, x, v, w, radius, mat_id,
+                        params && half_search(params->flags), p->pj);
     } catch (const std::bad_alloc&) {
         r = DEM_ENOMEM;
     }
@@ -1722,6 +1804,8 @@ dem_status dem_pool_add_prepared(dem_pool* s, dem_job_prep* p, uint32_t steps, u
     if (s->failed != DEM_OK) return s->failed;
     if (steps == 0 || steps == 0xFFFFFFFFu) return DEM_EINVAL;
     if ((p->pj.J.P.precision == DEM_PREC_FP64) != s->fp64) return DEM_EINVAL;
+    // a job prepared for the two-level search needs the pool's half search
+    if (p->pj.J.geo.nbig && !half_search(s->flags)) return DEM_EINVAL;
     dem_status r = sync_impl(s);
     if (r != DEM_OK) return r;
     int slot = 0;
@@ -1798,6 +1882,15 @@ dem_status dem_pool_get_state(dem_pool* s, uint64_t job, double* x, double* v, d
     return get_state_impl(s, slot, x, v, w, nullptr, nullptr);
 }
 
+dem_status dem_pool_set_radii(dem_pool* s, uint64_t job, const float* radius) {
+    if (!s) return DEM_EINVAL;
+    const int slot = slot_of(s, job);
+    if (slot < 0 || (s->jobs[slot].n && !radius)) return DEM_EINVAL;
+    dem_status r = sync_impl(s);
+    if (r != DEM_OK) return r;
+    return set_radii_impl(s, slot, radius);
+}
+
 dem_status dem_pool_remove(dem_pool* s, uint64_t job) {
     if (!s) return DEM_EINVAL;
     const int slot = slot_of(s, job);
@@ -1810,7 +1903,12 @@ dem_status dem_pool_remove(dem_pool* s, uint64_t job) {
 uint64_t dem_job_cells(const dem_params* params, uint64_t n, double rmax) {
     if (!params || !(rmax > 0.0) || !std::isfinite(rmax)) return 0;
     Layout lay;
-    if (plan_grid(*params, rmax, n, lay) != DEM_OK) return 0;
+    double used = rmax;
+    // the radius cut of the two-level search is at least rmax / 2: the grid
+    // of that cut has the most cells a job can get
+    if (plan_job_grid(*params, rmax, half_search(params->flags) ? 0.5 * rmax : rmax, n, lay,
+                      used) != DEM_OK)
+        return 0;
     return (uint64_t)lay.nc[0] * lay.nc[1] * lay.nc[2];
 }
 

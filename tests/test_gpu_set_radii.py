@@ -55,7 +55,8 @@ def test_radii_beyond_the_grid_or_not_finite_are_refused():
         width = float(np.min((sc.hi - sc.lo) / np.array(g.info()["cells"])))
         assert cell > 0
         big = sc.r.copy()
-        big[0] = gen.f32(np.array([0.51 * width]))[0]
+        # wider than a cell: beyond even the two-level search's wide scan
+        big[0] = gen.f32(np.array([1.01 * width]))[0]
         with pytest.raises(DemError) as e:
             g.set_radii(big)
         assert e.value.code == -1
