@@ -56,8 +56,10 @@ typedef enum {
     DEM_ECAPACITY = -3,   /* contact table could not be grown */
     DEM_ENONFINITE = -4,  /* a force or state component became NaN/Inf */
     DEM_EDEVICE = -5,     /* a HIP runtime error */
-    DEM_EBUSY = -6        /* a pool has no room (particles, cells, job slots or key
+    DEM_EBUSY = -6,       /* a pool has no room (particles, cells, job slots or key
                              bits) for this job now; nothing was changed */
+    DEM_ESCRATCH = -7     /* dem_create_static: the simulation needs more device
+                             memory than the static scratch holds */
 } dem_status;
 
 typedef enum {
@@ -201,6 +203,32 @@ dem_status dem_create(const dem_params *params, const dem_material *mats, uint32
                       uint64_t n, const double *x, const double *v, const double *w,
                       const float *radius, const uint16_t *mat_id, void *device_arena,
                       uint64_t arena_bytes, void *stream, dem_sim **out);
+
+/*
+ * dem_create without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops that must not
+ * call hipMalloc, harnesses that forbid it).  Arguments and results are those
+ * of dem_create; instead of allocating, or borrowing a caller's arena, the
+ * simulation lives in a static scratch array of DEM_STATIC_BYTES that the
+ * library reserves on each device it runs on (held until the process ends).
+ * Neither this call nor any later call on the handle allocates device memory:
+ * contact-table growth beyond the scratch's spare room fails with
+ * DEM_ECAPACITY, as with a lent arena.
+ *  - DEM_ESCRATCH: dem_footprint(params, n) exceeds DEM_STATIC_BYTES
+ *    (about 75,000 particles with the default contact table); nothing was
+ *    created.
+ *  - DEM_EBUSY: a simulation made by this call still lives on the current
+ *    device (one per device at a time: they would share the array); destroy
+ *    it first.  Simulations on different devices are independent.
+ * The scratch keeps the contents of the simulation that used it last; every
+ * buffer that must start at zero is cleared at creation.  Creation and use
+ * from several threads must not overlap on one device.
+ */
+#define DEM_STATIC_BYTES (64ull << 20)
+dem_status dem_create_static(const dem_params *params, const dem_material *mats, uint32_t n_mats,
+                             uint64_t n, const double *x, const double *v, const double *w,
+                             const float *radius, const uint16_t *mat_id, void *stream,
+                             dem_sim **out);
 
 /*
  * Enqueue nsteps time steps on the simulation's stream and return (section

@@ -27,10 +27,11 @@ NPHASE = 4
 PHASES = ("detect", "force", "sort", "reorder")
 
 STATUS = {0: "DEM_OK", -1: "DEM_EINVAL", -2: "DEM_ENOMEM", -3: "DEM_ECAPACITY",
-          -4: "DEM_ENONFINITE", -5: "DEM_EDEVICE", -6: "DEM_EBUSY"}
+          -4: "DEM_ENONFINITE", -5: "DEM_EDEVICE", -6: "DEM_EBUSY", -7: "DEM_ESCRATCH"}
+STATIC_BYTES = 64 << 20  # DEM_STATIC_BYTES
 
 # every symbol include/dem.h declares
-EXPORTS = ("dem_create", "dem_step", "dem_sync", "dem_get_state",
+EXPORTS = ("dem_create", "dem_create_static", "dem_step", "dem_sync", "dem_get_state",
            "dem_get_contacts",
            "dem_set_contacts", "dem_set_state", "dem_set_radii", "dem_get_info", "dem_destroy",
            "dem_status_str",
@@ -126,6 +127,9 @@ def lib():
         L.dem_create.restype = ctypes.c_int
         L.dem_create.argtypes = [P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp, _vp, _vp,
                                  _vp, ctypes.c_uint64, _vp, ctypes.POINTER(_vp)]
+        L.dem_create_static.restype = ctypes.c_int
+        L.dem_create_static.argtypes = [P, _vp, ctypes.c_uint32, ctypes.c_uint64, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, ctypes.POINTER(_vp)]
         L.dem_step.restype = ctypes.c_int
         L.dem_step.argtypes = [_vp, ctypes.c_uint32]
         L.dem_sync.restype = ctypes.c_int
@@ -280,10 +284,15 @@ class Sim:
     def __init__(self, lo, hi, x, v, w, r, materials, mat=None, walls=0x3F, periodic=0,
                  gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
                  precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0, flags=0,
-                 stream=None, extra_walls=(), arena=None):
+                 stream=None, extra_walls=(), arena=None, static=False):
         """arena: device memory lent for every device buffer of the simulation
         (a torch tensor on the GPU, or (pointer, bytes)); it must hold at least
-        footprint(params, n) bytes and is kept referenced by the handle."""
+        footprint(params, n) bytes and is kept referenced by the handle.
+        static: create with dem_create_static (no device allocation; the
+        library's static scratch of STATIC_BYTES, one such simulation per
+        device at a time); not with an arena."""
+        if static and arena is not None:
+            raise ValueError("a static simulation takes no arena")
         L = lib()
         self.params = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time,
                                   precision, kn_form, cell_size, max_contacts, flags, extra_walls)
@@ -302,11 +311,17 @@ class Sim:
         aptr, abytes = _arena_handle(arena)
         self._keep = (x, v, w, r32, mats, mat16)
         m16 = None if mat16 is None else mat16.ctypes.data
-        code = L.dem_create(ctypes.byref(self.params), ctypes.cast(mats, _vp), len(materials),
-                            n, x.ctypes.data, v.ctypes.data, w.ctypes.data, r32.ctypes.data,
-                            m16, aptr, abytes, _stream_handle(stream), ctypes.byref(self._h))
+        if static:
+            code = L.dem_create_static(ctypes.byref(self.params), ctypes.cast(mats, _vp),
+                                       len(materials), n, x.ctypes.data, v.ctypes.data,
+                                       w.ctypes.data, r32.ctypes.data, m16,
+                                       _stream_handle(stream), ctypes.byref(self._h))
+        else:
+            code = L.dem_create(ctypes.byref(self.params), ctypes.cast(mats, _vp), len(materials),
+                                n, x.ctypes.data, v.ctypes.data, w.ctypes.data, r32.ctypes.data,
+                                m16, aptr, abytes, _stream_handle(stream), ctypes.byref(self._h))
         self._keep = None
-        _check(code, "dem_create")
+        _check(code, "dem_create_static" if static else "dem_create")
 
     @classmethod
     def from_scene(cls, sc, precision=PREC_FP64, **kw):

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <deque>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -165,6 +166,7 @@ struct dem_pool {
 struct dem_sim {
     dem_pool* pool = nullptr;
     int slot = 0;
+    int static_dev = -1;  // device whose static scratch holds it (dem_create_static), else -1
 };
 
 namespace {
@@ -1471,6 +1473,7 @@ const char* dem_status_str(dem_status s) {
         case DEM_ENONFINITE: return "non-finite force or state";
         case DEM_EDEVICE: return "HIP runtime error";
         case DEM_EBUSY: return "pool full";
+        case DEM_ESCRATCH: return "input too large for the static scratch";
     }
     return "unknown status";
 }
@@ -1483,6 +1486,27 @@ uint64_t dem_footprint(const dem_params* P, uint64_t n) {
     if (P->max_contacts) slots = std::max<uint64_t>(1, (P->max_contacts + np - 1) / np);
     return pool_bytes(np / TILE, cells, 1, P->precision == DEM_PREC_FP64, slots, P->flags);
 }
+
+// ------------------------------------------------------- static scratch
+// Device memory of the simulation dem_create_static makes: one array of
+// DEM_STATIC_BYTES per device, reserved when the library's code object is
+// loaded and held until the process ends.  In host code `scratch` only
+// names the symbol; its device address on each device comes from
+// hipGetSymbolAddress with that device current, and only that address is
+// handed to kernels and copies (as the arena of the simulation).
+static __device__ __align__(256) unsigned char scratch[DEM_STATIC_BYTES];
+
+namespace {
+constexpr int MAX_STATIC_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[MAX_STATIC_DEVICES] = {};  // device address of scratch, per device
+bool g_static_live[MAX_STATIC_DEVICES] = {};  // a simulation occupies that device's scratch
+
+void release_static(int dev) {
+    std::lock_guard<std::mutex> g(g_static_mu);
+    g_static_live[dev] = false;
+}
+}  // namespace
 
 dem_status dem_create(const dem_params* params, const dem_material* mats, uint32_t n_mats,
                       uint64_t n, const double* x, const double* v, const double* w,
@@ -1537,6 +1561,44 @@ dem_status dem_create(const dem_params* params, const dem_material* mats, uint32
     s->pool = p;
     s->slot = slot;
     *out = s;
+    return DEM_OK;
+}
+
+dem_status dem_create_static(const dem_params* params, const dem_material* mats,
+                             uint32_t n_mats, uint64_t n, const double* x, const double* v,
+                             const double* w, const float* radius, const uint16_t* mat_id,
+                             void* stream, dem_sim** out) {
+    if (!out || !params) return DEM_EINVAL;
+    *out = nullptr;
+    if (dem_footprint(params, n) > DEM_STATIC_BYTES) return DEM_ESCRATCH;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_STATIC_DEVICES) return DEM_EDEVICE;
+    void* base = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_static_mu);
+        if (g_static_live[dev]) return DEM_EBUSY;
+        if (!g_static_ptr[dev]) {
+            void* p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                return DEM_EDEVICE;
+            }
+            g_static_ptr[dev] = p;
+        }
+        base = g_static_ptr[dev];
+        g_static_live[dev] = true;  // held while this call builds the simulation
+    }
+    // the scratch keeps the previous simulation's contents: create_pool
+    // clears every buffer that must start at zero, as it does for an arena
+    dem_status r = dem_create(params, mats, n_mats, n, x, v, w, radius, mat_id, base,
+                              DEM_STATIC_BYTES, stream, out);
+    if (r != DEM_OK) {
+        release_static(dev);
+        return r;
+    }
+    (*out)->static_dev = dev;
     return DEM_OK;
 }
 
@@ -1657,6 +1719,7 @@ dem_status dem_get_info(dem_sim* s, dem_info* info) {
 void dem_destroy(dem_sim* s) {
     if (!s) return;
     destroy_pool(s->pool);
+    if (s->static_dev >= 0) release_static(s->static_dev);
     delete s;
 }
 
