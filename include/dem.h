@@ -112,14 +112,20 @@ typedef struct {
     int32_t kn_form;     /* 0: k_n with (2 - sigma^2)/E as printed in section 2;
                             1: textbook Hertz (1 - sigma^2)/E */
     double cell_size;    /* [m]; 0 = automatic: twice the radius cut of the two-level
-                            search (the radius exceeded by about 2 % of the
-                            particles, at least r_max / 2) with the default search,
-                            the largest contact distance 2 r_max with the full one.
-                            A given size must be >= 2 r_max (one-level search). */
+                            search (radius_cut below) with the default search, the
+                            largest contact distance 2 r_max with the full one.  A
+                            given size must be >= 2 r_max (one-level search). */
     uint64_t max_contacts; /* initial contact-table capacity; 0 = automatic */
     uint32_t flags;        /* DEM_FLAG_* */
     uint32_t n_extra_walls;          /* entries of extra_walls, at most DEM_MAX_WALLS */
     const dem_wall *extra_walls;     /* copied at creation; may be null when none */
+    double radius_cut;   /* [m] two-level contact search (default search, automatic
+                            cells): particles above this radius scan a two-cell
+                            stencil themselves and the cells are sized for twice
+                            the cut; raised to r_max / 2 if lower, r_max or more
+                            means one level.  0 = automatic: one level below volume
+                            fraction 0.3, else the radius exceeded by about 0.1 %
+                            of the particles */
 } dem_params;
 
 #define DEM_FLAG_NO_FORCE_OUTPUT 1u /* do not store per-particle F, T each step */

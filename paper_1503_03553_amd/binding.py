@@ -72,7 +72,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("kn_form", ctypes.c_int32),
                 ("cell_size", ctypes.c_double), ("max_contacts", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32), ("n_extra_walls", ctypes.c_uint32),
-                ("extra_walls", ctypes.c_void_p)]
+                ("extra_walls", ctypes.c_void_p), ("radius_cut", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -242,7 +242,7 @@ def _stream_handle(stream):
 
 def make_params(lo, hi, walls=0x3F, periodic=0, gravity=(0.0, 0.0, -9.81), shear_rate=0.0,
                 dt=0.0, time=0.0, precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0,
-                flags=0, extra_walls=()) -> Params:
+                flags=0, extra_walls=(), radius_cut=0.0) -> Params:
     """dem_params; extra_walls holds objects with kind, p, u, v (e.g. gen.Wall),
     kept alive by the returned structure."""
     P = Params()
@@ -260,6 +260,7 @@ def make_params(lo, hi, walls=0x3F, periodic=0, gravity=(0.0, 0.0, -9.81), shear
     P.cell_size = float(cell_size)
     P.max_contacts = int(max_contacts)
     P.flags = int(flags)
+    P.radius_cut = float(radius_cut)
     ws = list(extra_walls or ())
     arr = (Wall * max(1, len(ws)))()
     for k, wl in enumerate(ws):
@@ -284,7 +285,7 @@ class Sim:
     def __init__(self, lo, hi, x, v, w, r, materials, mat=None, walls=0x3F, periodic=0,
                  gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
                  precision=PREC_FP64, kn_form=0, cell_size=0.0, max_contacts=0, flags=0,
-                 stream=None, extra_walls=(), arena=None, static=False):
+                 stream=None, extra_walls=(), arena=None, static=False, radius_cut=0.0):
         """arena: device memory lent for every device buffer of the simulation
         (a torch tensor on the GPU, or (pointer, bytes)); it must hold at least
         footprint(params, n) bytes and is kept referenced by the handle.
@@ -295,7 +296,8 @@ class Sim:
             raise ValueError("a static simulation takes no arena")
         L = lib()
         self.params = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time,
-                                  precision, kn_form, cell_size, max_contacts, flags, extra_walls)
+                                  precision, kn_form, cell_size, max_contacts, flags, extra_walls,
+                                  radius_cut)
         x = _c(x, np.float64, (-1, 3))
         n = x.shape[0]
         v = _c(v, np.float64, (n, 3))
@@ -467,9 +469,9 @@ class PreparedJob:
 
     def __init__(self, lo, hi, x, v, w, r, materials, precision, mat=None, walls=0x3F,
                  periodic=0, gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0,
-                 kn_form=0, cell_size=0.0, extra_walls=()):
+                 kn_form=0, cell_size=0.0, extra_walls=(), radius_cut=0.0):
         P = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time, precision,
-                        kn_form, cell_size, extra_walls=extra_walls)
+                        kn_form, cell_size, extra_walls=extra_walls, radius_cut=radius_cut)
         x = _c(x, np.float64, (-1, 3))
         n = x.shape[0]
         v = _c(v, np.float64, (n, 3))
@@ -535,9 +537,9 @@ class Pool:
 
     def add(self, lo, hi, x, v, w, r, materials, steps, mat=None, walls=0x3F, periodic=0,
             gravity=(0.0, 0.0, -9.81), shear_rate=0.0, dt=0.0, time=0.0, kn_form=0,
-            cell_size=0.0, extra_walls=()) -> int:
+            cell_size=0.0, extra_walls=(), radius_cut=0.0) -> int:
         P = make_params(lo, hi, walls, periodic, gravity, shear_rate, dt, time, self.precision,
-                        kn_form, cell_size, extra_walls=extra_walls)
+                        kn_form, cell_size, extra_walls=extra_walls, radius_cut=radius_cut)
         x = _c(x, np.float64, (-1, 3))
         n = x.shape[0]
         v = _c(v, np.float64, (n, 3))
