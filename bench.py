@@ -5,19 +5,26 @@ Headline workload (`value`): 1,000,000 polydisperse spheres (lognormal radii,
 median 4 um, sigma_log 0.15, clipped to [2, 8] um) in a walled box at volume
 fraction 0.1 under gravity, half of them seeded touching a neighbour; FP32
 contact force arithmetic with FP64 overlap, history and integration; 200
-steps, one simulation.  Beside it, on the same GPU and in the same run:
-  fp64_plain  the same input with every operation in FP64;
-  batched     256 independent jobs, N log-uniform in [1k, 200k], run in one
-              pool (one set of launches per step), cell factor and job layout
-              picked by the autotuner;
-  serving     a Poisson stream (20 jobs/s) of jobs of 1k-1M particles and
-              100-2000 steps served by continuous batching; p50/p99 latency
-              and aggregate throughput;
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline
-              workload, on the host's cores.
+steps (the default), one simulation.  Beside it, on the same GPU and in the
+same run:
+  fp64_plain      the same input with every operation in FP64;
+  plain_2000_fp64 2,000 monodisperse spheres at volume fraction 0.3, FP64,
+                  1000 steps;
+  dense_shear_8m  8M spheres grown to volume fraction 0.55 (not timed), then
+                  Lees-Edwards shear: throughput and contact-table churn;
+  batched         256 independent jobs, N log-uniform in [1k, 200k], volume
+                  fraction U[0.1, 0.5], run in one pool (one set of launches
+                  per step), cell factor and job layout picked by the
+                  autotuner;
+  serving         1,000 requests arriving as a Poisson stream (20 jobs/s),
+                  jobs of 1k-1M particles and 100-2000 steps, served by
+                  continuous batching; p50/p99 latency split into queueing
+                  and service, and aggregate throughput;
+  cpu_baseline    the FP64 CPU oracle on a bounded sample of the headline
+                  workload, on all cores of the process's share and on one.
 
 Prints one JSON line.  The roofline object is that of the dominant kernel of
-the headline run: algorithmic bytes per launch / its average duration from
+the headline run: the method's bytes per launch / its average duration from
 HIP events recorded on the stream the kernels run on.
 """
 from __future__ import annotations
@@ -27,6 +34,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -381,21 +390,22 @@ def run_one_at_a_time(scenes, precision, steps, warmup, stream):
 
 
 # --------------------------------------------------------------- serving
-def run_serving(templates, arr, tmpl, steps, stream, budget_particles, superstep, log):
-    """Serve the requests at their arrival times; the same requests all
-    arriving at once give the throughput of a pool that is never idle."""
+def run_serving(scenes, arr, steps, stream, budget_particles, superstep, log, at_once_too=False):
+    """Serve the requests (request q: scenes[q] for steps[q] steps, arriving
+    at arr[q]) at their arrival times; the same requests all arriving at once
+    give the throughput of a pool that is never idle."""
     from paper_1503_03553_amd import FLAG_NO_FORCE_OUTPUT, PREC_MIXED, Pool
     from paper_1503_03553_amd.serve import Request, Server
     max_jobs = 256
     out = []
-    for at_once in (False, True):
+    for at_once in ((False, True) if at_once_too else (False,)):
         pool = Pool(max_particles=budget_particles, max_cells=4 * budget_particles + 4096 * 64,
                     max_jobs=max_jobs, precision=PREC_MIXED, stream=stream,
                     flags=FLAG_NO_FORCE_OUTPUT)
-        reqs = [Request(q, templates[int(tmpl[q])], int(steps[q]), 0.0 if at_once else float(arr[q]))
+        reqs = [Request(q, scenes[q], int(steps[q]), 0.0 if at_once else float(arr[q]))
                 for q in range(len(arr))]
         srv = Server(pool, superstep=superstep, target_s=0.05)
-        st = srv.run(reqs, deadline=600.0)
+        st = srv.run(reqs, deadline=900.0)
         pool.close()
         log("serving%s: %s" % (" (all at once)" if at_once else "", json.dumps(st)))
         out.append(st)
@@ -482,7 +492,11 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=10)
     ap.add_argument("--alone-steps", type=int, default=100,
                     help="steps per job when the batched jobs run one at a time (0 = skip)")
-    ap.add_argument("--serve-horizon", type=float, default=10.0)
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-all-at-once", action="store_true",
+                    help="also serve the same requests all arriving at once")
+    ap.add_argument("--serve-gen-threads", type=int, default=12,
+                    help="host threads drawing the served scenes during the GPU legs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-budget", type=int, default=8_000_000)
     ap.add_argument("--superstep", type=int, default=20)
@@ -534,8 +548,9 @@ def main():
         sizes = gen.batch_sizes(0, a.batch_jobs)
         batch = gen.generate_many(gen.config_batch_job,
                                   [(0, m, int(sizes[m])) for m in range(a.batch_jobs)])
-        log("batched input: %d jobs, %d spheres in %.1fs" % (len(batch), sum(s.n for s in batch),
-                                                              time.perf_counter() - t))
+        log("batched input: %d jobs, %d spheres in %.1fs (%d to grow)" % (
+            len(batch), sum(s.n for s in batch), time.perf_counter() - t,
+            sum(1 for s in batch if s.meta.get("grow"))))
     dense = None
     if not a.no_dense:
         t = time.perf_counter()
@@ -543,14 +558,16 @@ def main():
         log("dense start: %d spheres in %.1fs" % (dense.n, time.perf_counter() - t))
     serve_in = None
     if not a.no_serve:
-        t = time.perf_counter()
-        arr, tmpl, steps, sizes = gen.serve_requests(gen.SEED_BASE + 9000, a.serve_horizon,
-                                                     rate=a.serve_rate)
-        templates = gen.generate_many(gen.config_batch_job,
-                                      [(1, m, int(sizes[m])) for m in range(len(sizes))])
-        serve_in = (templates, arr, tmpl, steps)
-        log("serving input: %d requests over %.0fs, %d templates in %.1fs" % (
-            len(arr), a.serve_horizon, len(templates), time.perf_counter() - t))
+        # the served requests' scenes are drawn on host threads while the
+        # GPU legs run (the serving clock starts once all are there); the
+        # process pools above are done by then
+        import concurrent.futures as cf
+        arr, sizes, steps = gen.serve_requests(gen.SEED_BASE + 9000, a.serve_requests,
+                                               rate=a.serve_rate)
+        gen.build_helper()
+        ex = cf.ThreadPoolExecutor(max(1, min(a.serve_gen_threads, os.cpu_count() or 1)))
+        futs = [ex.submit(gen.config_serve_job, q, int(sizes[q])) for q in range(len(sizes))]
+        serve_in = (futs, arr, steps, ex, time.perf_counter())
 
     import torch
     torch.cuda.set_device(0)
@@ -689,13 +706,27 @@ def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
             "contact_kernels_roofline": contact_kernels_of(rows),
             "kernels": kernels_of(rows, headline=False)}
     if batch:
-        from paper_1503_03553_amd import PREC_FP64, PREC_MIXED
+        from paper_1503_03553_amd import PREC_FP64, PREC_MIXED, pack
+        # jobs above the volume fraction RSA reaches quickly are grown to it
+        # first, all in one pool (not timed)
+        t = time.perf_counter()
+        gi = [k for k, sc in enumerate(batch) if sc.meta.get("grow")]
+        grown = pack.grow_pool([batch[k] for k in gi], increments=a.grow_increments,
+                               steps_per_increment=a.grow_steps, stream=stream)
+        import gen
+        for k, st in zip(gi, grown):
+            batch[k] = gen.grown_scene(batch[k], st["x"], st["v"], st["w"])
+        grow_s = time.perf_counter() - t
+        log("batched: %d jobs grown in %.1fs" % (len(gi), grow_s))
         b = run_batched(batch, a.batch_steps, a.warmup, stream, a.tune_steps, log)
         brows = phase_rows(b["prof"], b["n"], 0, 0, False, 24)
         value = b["n"] * a.batch_steps / b["seconds"]
+        phis = [sc.meta.get("phi", 0.0) for sc in batch]
         out["batched"] = {"value": round(value, 1),
                           "unit": "particle-steps/s",
                           "jobs": len(batch), "particles": b["n"], "steps": a.batch_steps,
+                          "phi_range": [round(min(phis), 3), round(max(phis), 3)],
+                          "grown_jobs": len(gi), "growth_seconds": round(grow_s, 2),
                           "ms_per_step": round(b["seconds"] / a.batch_steps * 1e3, 4),
                           "ms_per_step_with_events":
                               round(b["seconds_profiled"] / a.batch_steps * 1e3, 4),
@@ -716,25 +747,6 @@ def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
             out["batched"]["same_jobs_one_at_a_time"] = dict(alone, steps=a.alone_steps)
             out["batched"]["vs_fp64_plain_same_jobs"] = round(value / alone["fp64"]["value"], 3)
 
-    if serve_in is not None:
-        templates, arr, tmpl, steps = serve_in
-        st, sat = run_serving(templates, arr, tmpl, steps, stream, a.serve_budget, a.superstep,
-                              log)
-        out["serving"] = {"rate_jobs_per_s": a.serve_rate, "horizon_s": a.serve_horizon,
-                          "requests": int(len(arr)), "budget_particles": a.serve_budget,
-                          "superstep": "adaptive, %d to start, about 50 ms each" % a.superstep,
-                          "p50_latency_s": round(st["p50_s"], 4),
-                          "p99_latency_s": round(st["p99_s"], 4),
-                          "wait_p50_s": round(st["wait_p50_s"], 4),
-                          "wait_p99_s": round(st["wait_p99_s"], 4),
-                          "value": round(st["particle_steps_per_s"], 1),
-                          "unit": "particle-steps/s", "makespan_s": round(st["makespan_s"], 3),
-                          "failed": st["failed"],
-                          "all_at_once": {"value": round(sat["particle_steps_per_s"], 1),
-                                          "makespan_s": round(sat["makespan_s"], 3),
-                                          "p50_latency_s": round(sat["p50_s"], 4),
-                                          "p99_latency_s": round(sat["p99_s"], 4)}}
-
     if not a.no_ablation:
         sizes = [int(v) for v in a.ablation_sizes.split(",") if v]
         out["ablation_fused_vs_split"] = {
@@ -744,6 +756,41 @@ def run_others(a, out, sc, batch, serve_in, stream, log, dense=None):
                     "action_reaction = each pair's force once, applied to both",
             "steps": a.ablation_steps, "warmup": 5,
             "rows": run_ablation(sizes, a.ablation_steps, 5, stream, log)}
+
+    if serve_in is not None:
+        futs, arr, steps, ex, t = serve_in
+        scenes = [f.result() for f in futs]
+        ex.shutdown()
+        log("serving input: %d requests over %.0fs, %d spheres, ready %.1fs after the start" % (
+            len(arr), float(arr[-1]) if len(arr) else 0.0, sum(sc.n for sc in scenes),
+            time.perf_counter() - t))
+        res = run_serving(scenes, arr, steps, stream, a.serve_budget, a.superstep, log,
+                          at_once_too=a.serve_all_at_once)
+        st = res[0]
+        out["serving"] = {"rate_jobs_per_s": a.serve_rate,
+                          "arrival_span_s": round(float(arr[-1]), 2) if len(arr) else 0.0,
+                          "requests": int(len(arr)),
+                          "particles_total": int(sum(sc.n for sc in scenes)),
+                          "offered_particle_steps_per_s":
+                              round(sum(sc.n * int(k) for sc, k in zip(scenes, steps)) /
+                                    max(float(arr[-1]), 1e-9), 1) if len(arr) else 0.0,
+                          "budget_particles": a.serve_budget,
+                          "superstep": "adaptive, %d to start, about 50 ms each" % a.superstep,
+                          "p50_latency_s": round(st["p50_s"], 4),
+                          "p99_latency_s": round(st["p99_s"], 4),
+                          "wait_p50_s": round(st["wait_p50_s"], 4),
+                          "wait_p99_s": round(st["wait_p99_s"], 4),
+                          "service_p50_s": round(st["service_p50_s"], 4),
+                          "service_p99_s": round(st["service_p99_s"], 4),
+                          "value": round(st["particle_steps_per_s"], 1),
+                          "unit": "particle-steps/s", "makespan_s": round(st["makespan_s"], 3),
+                          "failed": st["failed"]}
+        if len(res) > 1:
+            sat = res[1]
+            out["serving"]["all_at_once"] = {"value": round(sat["particle_steps_per_s"], 1),
+                                             "makespan_s": round(sat["makespan_s"], 3),
+                                             "p50_latency_s": round(sat["p50_s"], 4),
+                                             "p99_latency_s": round(sat["p99_s"], 4)}
 
     if not a.no_cpu:
         import gen

@@ -192,24 +192,53 @@ def config_dilute(seed=None, n=1_000_000, p_touch=0.5, touch_max=2e-3):
                    meta=dict(phi=0.1, p_touch=p_touch))
 
 
-def config_batch_job(k, m, n=None):
-    """Job m of a batched workload: N log-uniform in [1k, 200k], phi ~ U[0.1, 0.4]
-    by RSA (touch-seeded, largest spheres first; RSA jams before 0.5),
-    restitution ~ U[0.3, 0.9], mu ~ U[0.1, 0.5]."""
+def config_batch_job(k, m, n=None, phi_lo=0.1, phi_hi=0.5, n_lo=1e3, n_hi=2e5, rsa_max=0.35,
+                     phi0=0.30):
+    """Job m of a batched workload: N log-uniform in [n_lo, n_hi], phi ~
+    U[phi_lo, phi_hi], restitution ~ U[0.3, 0.9], mu ~ U[0.1, 0.5], walls,
+    gravity, 500 steps.  Up to rsa_max the spheres are placed at phi by RSA
+    (touch-seeded, largest first); above it (where RSA slows down and jams
+    short of 0.5) they are placed by RSA at phi0 with radii shrunk by
+    (phi0 / phi)^(1/3) and marked for growth to their full radii (meta
+    r_full; the scene then carries the growth material, restitution 0.1 and
+    no friction, without gravity, and meta the job's own material and
+    gravity for dense_run_scene)."""
     seed = SEED_BASE + 1000 * k + m
     rng = np.random.Generator(np.random.PCG64(seed))
     if n is None:
-        n = int(np.exp(rng.uniform(np.log(1e3), np.log(2e5))))
-    phi = float(rng.uniform(0.1, 0.4))
+        n = int(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi))))
+    phi = float(rng.uniform(phi_lo, phi_hi))
     eps = float(rng.uniform(0.3, 0.9))
     mu = float(rng.uniform(0.1, 0.5))
     r = lognormal_radii(rng, n)
     L = box_side(r, phi)
     lo, hi = np.zeros(3), np.full(3, L)
-    x = rsa(r, lo, hi, p_touch=0.5, seed=seed, big_first=True)
     mats = [Material.make(restitution=eps, mu=mu)]
-    return _finish(rng, x, r, lo, hi, mats, steps=500, name="batch-job-%d" % m,
-                   meta=dict(phi=phi))
+    g = (0.0, 0.0, -9.81)
+    if phi <= rsa_max:
+        x = rsa(r, lo, hi, p_touch=0.5, seed=seed, big_first=True)
+        return _finish(rng, x, r, lo, hi, mats, steps=500, name="batch-job-%d" % m,
+                       gravity=g, meta=dict(phi=phi, seed=seed))
+    r0 = f32(r * (phi0 / phi) ** (1.0 / 3.0))
+    x = rsa(r0, lo, hi, p_touch=0.5, seed=seed, big_first=True)
+    z = np.zeros((n, 3))
+    return Scene(lo=lo, hi=hi, x=x, v=z.copy(), w=z.copy(), r=r0, mat=np.zeros(n, np.uint16),
+                 materials=[Material.make(restitution=0.1, mu=0.0)], walls=WALL_ALL,
+                 gravity=(0.0, 0.0, 0.0), steps=500, name="batch-job-%d" % m,
+                 meta=dict(phi=phi, phi0=phi0, seed=seed, r_full=r, run_materials=mats,
+                           run_gravity=g, grow=True))
+
+
+def grown_scene(start, x, v, w):
+    """The run of a job grown from `start` (config_batch_job above rsa_max):
+    the grown state with the full radii, the job's own material and gravity."""
+    m = start.meta
+    return Scene(lo=start.lo.copy(), hi=start.hi.copy(), x=np.array(x, np.float64, copy=True),
+                 v=np.array(v, np.float64, copy=True), w=np.array(w, np.float64, copy=True),
+                 r=m["r_full"].copy(), mat=np.zeros(start.n, np.uint16),
+                 materials=list(m["run_materials"]), walls=start.walls, periodic=start.periodic,
+                 gravity=m["run_gravity"], steps=start.steps, name=start.name,
+                 meta=dict(phi=m["phi"], seed=m["seed"], grown=True))
 
 
 def rsa_tiled(r, lo, hi, splits=(4, 4, 4), p_touch=0.0, touch_max=2e-3, seed=0, threads=16,
@@ -321,26 +350,33 @@ def batch_sizes(k, jobs, lo=1e3, hi=2e5):
     return np.exp(rng.uniform(np.log(lo), np.log(hi), size=jobs)).astype(np.int64)
 
 
-def serve_requests(seed, horizon_s, rate=20.0, n_lo=1e3, n_hi=1e6, steps_lo=100,
-                   steps_hi=2000, templates=32):
-    """A Poisson arrival stream of simulation requests.
-
-    Returns (arrival times [s], template index, steps) for arrivals within
-    horizon_s at `rate` jobs/s, and the particle counts of the `templates`
-    scene templates (log-uniform in [n_lo, n_hi]); request q runs template
-    tmpl[q] for steps[q] steps (uniform integers in [steps_lo, steps_hi])."""
+def serve_requests(seed, n_requests=1000, rate=20.0, n_lo=1e3, n_hi=1e6, steps_lo=100,
+                   steps_hi=2000):
+    """A Poisson arrival stream of simulation requests: arrival times [s] of
+    n_requests requests at `rate` jobs/s (exponential gaps), and per request
+    its particle count (log-uniform in [n_lo, n_hi]) and steps (uniform
+    integers in [steps_lo, steps_hi]).  Request q's scene is
+    config_serve_job(q, n[q])."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    sizes = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=templates)).astype(np.int64)
-    t, arr = 0.0, []
-    while True:
-        t += rng.exponential(1.0 / rate)
-        if t >= horizon_s:
-            break
-        arr.append(t)
-    arr = np.array(arr)
-    tmpl = rng.integers(0, templates, size=arr.size)
-    steps = rng.integers(steps_lo, steps_hi + 1, size=arr.size)
-    return arr, tmpl, steps, sizes
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+    sizes = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), size=n_requests)).astype(np.int64)
+    steps = rng.integers(steps_lo, steps_hi + 1, size=n_requests)
+    return arr, sizes, steps
+
+
+def config_serve_job(q, n):
+    """The scene of serving request q: a batched-workload job of n particles
+    (own seed) with phi ~ U[0.1, 0.3], placed by RSA."""
+    return config_batch_job(2, q, n=int(n), phi_lo=0.1, phi_hi=0.3)
+
+
+def generate_threaded(fn, args, threads=16):
+    """fn(*a) for every a in args on a pool of threads (the RSA helper runs
+    without the interpreter lock), in order; no copies between processes."""
+    import concurrent.futures as cf
+    build_helper()
+    with cf.ThreadPoolExecutor(max(1, min(threads, os.cpu_count() or 1))) as ex:
+        return list(ex.map(lambda a: fn(*a), args))
 
 
 def generate_many(fn, args, workers=None):

@@ -98,3 +98,33 @@ def grown(start, increments=200, steps_per_increment=20, precision=PREC_MIXED, s
                   "median_overlap_over_r": float(np.median(dn / rr)) if dn.size else 0.0,
                   "increments": increments, "steps_per_increment": steps_per_increment}
     return g
+
+
+def grow_pool(starts, increments=200, steps_per_increment=20, precision=PREC_MIXED,
+              stream=None):
+    """grow() for many jobs at once: the starts run as the jobs of one pool,
+    each inflated to its own r_full in `increments` equal steps of its radius
+    scale with `steps_per_increment` steps after each increment.  Returns,
+    per start, the grown state (x, v, w in pid order)."""
+    from .binding import Pool, job_cells
+    if not starts:
+        return []
+    cells_of = [2.0 * float(np.max(sc.meta["r_full"])) * (1.0 + 1e-5) for sc in starts]
+    parts = sum(((sc.n + 127) // 128) * 128 for sc in starts)
+    ncell = sum(job_cells(sc, c) for sc, c in zip(starts, cells_of))
+    total = increments * steps_per_increment
+    pool = Pool(max_particles=max(parts, 128), max_cells=max(ncell, 1), max_jobs=len(starts),
+                precision=precision, stream=stream, flags=FLAG_NO_FORCE_OUTPUT)
+    try:
+        ids = [pool.add_scene(sc, steps=total + 1, cell_size=c) for sc, c in zip(starts, cells_of)]
+        s0 = [float(np.median(np.asarray(sc.r) / np.asarray(sc.meta["r_full"]))) for sc in starts]
+        for k in range(1, increments + 1):
+            for jid, sc, s in zip(ids, starts, s0):
+                rf = np.asarray(sc.meta["r_full"], np.float64)
+                r = rf if k == increments else np.minimum(rf * (s + (1.0 - s) * k / increments), rf)
+                pool.set_radii(jid, r)
+            pool.step(steps_per_increment)
+        pool.sync()
+        return [pool.get_state(jid) for jid in ids]
+    finally:
+        pool.close()

@@ -192,6 +192,7 @@ class Server:
             return dict(jobs=0)
         lat = np.array([r.latency for r in fin])
         wait = np.array([r.admitted - r.arrival for r in fin])
+        service = lat - wait
         span = max(r.done for r in fin) - min(r.arrival for r in fin)
         work = sum(r.work for r in fin if r.status in ("done", ""))
         return dict(jobs=len(fin), failed=sum(1 for r in fin if r.status == "failed"),
@@ -199,6 +200,8 @@ class Server:
                     mean_s=float(lat.mean()), max_s=float(lat.max()),
                     wait_p50_s=float(np.percentile(wait, 50)),
                     wait_p99_s=float(np.percentile(wait, 99)),
+                    service_p50_s=float(np.percentile(service, 50)),
+                    service_p99_s=float(np.percentile(service, 99)),
                     makespan_s=float(span), particle_steps=int(work),
                     particle_steps_per_s=float(work / span) if span > 0 else 0.0,
                     supersteps=self.supersteps)
