@@ -39,7 +39,15 @@ def test_counter_summaries_match_the_kernel_source_or_are_ignored():
     src = os.path.join(ROOT, "paper_1503_03553_amd", "csrc", "dem_kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     for name in ("hbm_traffic_dilute_1m.json", "valu_dilute_1m.json"):
-        rec = json.load(open(os.path.join(ROOT, "profiles", name)))
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            # no counter summary: the figures it would give are null
+            if name.startswith("hbm"):
+                assert bench.measured_traffic("k_force", "float") is None
+            else:
+                assert bench.valu_insts("force", "float") is None
+            continue
+        rec = json.load(open(path))
         if rec["kernels_source_sha256"] == sha:
             continue
         # a stale summary is never used
@@ -48,7 +56,8 @@ def test_counter_summaries_match_the_kernel_source_or_are_ignored():
         else:
             assert bench.valu_insts("force", "float") is None
     traffic = bench.measured_traffic("k_force", "float")
-    if traffic is not None:
+    if traffic is not None and os.path.exists(os.path.join(ROOT, "profiles",
+                                                           "hbm_traffic_dilute_1m.json")):
         rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic_dilute_1m.json")))
         key = [k for k in rec["per_launch_bytes"] if bench.kernel_is(k, "k_force", "float")]
         assert len(key) == 1 and traffic == rec["per_launch_bytes"][key[0]]
