@@ -176,22 +176,39 @@ __device__ inline bool wall_touch(const dem_wall& W, double cx, double cy, doubl
     return d2 < r * r && (W.kind == DEM_WALL_RECT || d2 > 0.0);
 }
 
+// Data that no kernel writes while it reads them (the job descriptors, the
+// tile maps) and the error word of the step, at workgroup-uniform addresses,
+// are read through the constant address space: scalar loads into SGPRs,
+// which wait on no vector load issued before them and take no vector
+// registers.  The scalar cache is invalidated at every kernel launch, so such
+// a load sees what earlier kernels of the stream wrote.
+template <typename T>
+using ConstPtr = const __attribute__((address_space(4))) T*;
+
+// Whether an earlier kernel of the step (or, at times, another workgroup of
+// this one) reported an error; the same answer for the whole workgroup.
 __device__ inline uint32_t skip_if_error(const Status* st, uint32_t* s_flag) {
-    if (threadIdx.x == 0) *s_flag = __atomic_load_n(&st->err, __ATOMIC_RELAXED);
+    const uint32_t e = ((ConstPtr<Status>)st)->err;
+    if (threadIdx.x == 0) *s_flag = e;
     __syncthreads();
     return *s_flag;
 }
 
 // The running job of a tile, or null for a free tile or a job that is
-// finished or failed.  The descriptor is read through a restrict-qualified
-// kernel argument at a workgroup-uniform address, so its fields come in
-// through scalar loads and stay in registers.
+// finished or failed.  The descriptor is read at a workgroup-uniform address
+// through the constant address space, so its fields come in through scalar
+// loads and stay in SGPRs.
 __device__ inline const Job* tile_job(const Job* __restrict__ jobs, const PoolView& P,
                                       uint32_t tile, uint32_t& jb) {
-    jb = P.tile_job[tile];
+    jb = ((ConstPtr<uint32_t>)P.tile_job)[tile];
     if (jb == NO_JOB) return nullptr;
-    const Job* J = jobs + jb;
-    return J->status == JOB_ACTIVE ? J : nullptr;
+    ConstPtr<Job> J = (ConstPtr<Job>)jobs + jb;
+    return J->status == JOB_ACTIVE ? (const Job*)J : nullptr;
+}
+
+// The key bits of a tile's segment (a job's tiles sort together).
+__device__ inline uint32_t tile_key_of(const PoolView& P, uint32_t tile) {
+    return ((ConstPtr<uint32_t>)P.tile_key)[tile];
 }
 
 // Exclusive scan of v over a workgroup of NW waves.
@@ -1268,9 +1285,9 @@ __device__ __forceinline__ void idle_tile(const PoolView& P, const Job* __restri
                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                           uint32_t* __restrict__ oldkeys, bool movers) {
     const uint32_t p0 = tile * TILE, ns = P.ns;
-    keys[p0 + t] = P.tile_key[tile] | P.lmask;
+    keys[p0 + t] = tile_key_of(P, tile) | P.lmask;
     vals[p0 + t] = p0 + t;
-    if (movers) oldkeys[p0 + t] = P.tile_key[tile] | P.lmask;
+    if (movers) oldkeys[p0 + t] = tile_key_of(P, tile) | P.lmask;
     if (jb != NO_JOB) {
         const uint32_t i = p0 + t;
         if (i < jobs[jb].p0 + jobs[jb].n) {
@@ -1369,7 +1386,7 @@ __device__ __forceinline__ void finish_tile(
         vw_b[ns + i] = make_double2(vz, wx);
         vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
         if (mat_b) mat_b[i] = (uint8_t)mi;
-        newkey = P.tile_key[tile] | cell_key(G, x, y, z);
+        newkey = tile_key_of(P, tile) | cell_key(G, x, y, z);
         keys[i] = newkey;
         vals[i] = i;
         if (fo) {
@@ -1386,7 +1403,7 @@ __device__ __forceinline__ void finish_tile(
             if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
         }
         if (movers) {
-            const uint32_t oldkey = P.tile_key[tile] | okey;
+            const uint32_t oldkey = tile_key_of(P, tile) | okey;
             oldkeys[i] = oldkey;
             moved = newkey != oldkey;
         }
@@ -1469,16 +1486,18 @@ __global__ __launch_bounds__(TILE) void k_force(
     uint2 orow0 = make_uint2(0, 0);
     uint8_t m80 = 0;
     if (HK) {
+        // the list length first, then the loads that do not need it, so
+        // that its round trip overlaps theirs
         const uint32_t ip = tile * TILE + t;
         d = deg[ip];
+        const uint32_t pq = perm[ip];
+        xi0 = xr[ip];
         if (d) deg[ip] = 0;
         const uint32_t c0 = d <= (uint32_t)HK ? d : 0u;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
             e0[m] = (uint32_t)m < c0 ? adj[(size_t)m * P.ns + ip] : make_uint2(0u, 0u);
-        const uint32_t pq = perm[ip];
         const uint32_t q = pq < P.ns ? pq : ip;
-        xi0 = xr[ip];
         v0 = vw[q];
         v1 = vw[P.ns + q];
         v2 = vw[2 * (size_t)P.ns + q];
@@ -1504,9 +1523,9 @@ __global__ __launch_bounds__(TILE) void k_force(
     const uint32_t n = J.p0 + J.n;  // end of the job's particles
     if (i >= n) {
         // ghost slot after the job's last particle: sorts last, stays in place
-        keys[i] = P.tile_key[tile] | P.lmask;
+        keys[i] = tile_key_of(P, tile) | P.lmask;
         vals[i] = i;
-        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
+        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
     }
     const uint32_t nt = (n - p0) < (uint32_t)TILE ? (n - p0) : (uint32_t)TILE;
     uint2 row = make_uint2(0, 0);
@@ -1675,9 +1694,9 @@ __global__ __launch_bounds__(TILE) void k_force_thread(
     const uint32_t i = p0 + t;
     const uint32_t n = J.p0 + J.n;
     if (i >= n) {
-        keys[i] = P.tile_key[tile] | P.lmask;
+        keys[i] = tile_key_of(P, tile) | P.lmask;
         vals[i] = i;
-        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
+        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
     }
     R acc[6] = {0, 0, 0, 0, 0, 0};
     uint32_t matched = 0;
@@ -1883,9 +1902,9 @@ __global__ __launch_bounds__(TILE) void k_ar_sum(
     const uint32_t i = p0 + t;
     const uint32_t n = J.p0 + J.n;
     if (i >= n) {
-        keys[i] = P.tile_key[tile] | P.lmask;
+        keys[i] = tile_key_of(P, tile) | P.lmask;
         vals[i] = i;
-        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
+        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
     }
     R acc[6] = {0, 0, 0, 0, 0, 0};
     double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -1978,9 +1997,9 @@ __global__ __launch_bounds__(TILE) void k_fused(
     const uint32_t i = p0 + t;
     const uint32_t n = J.p0 + J.n;
     if (i >= n) {
-        keys[i] = P.tile_key[tile] | P.lmask;
+        keys[i] = tile_key_of(P, tile) | P.lmask;
         vals[i] = i;
-        if (movers) oldkeys[i] = P.tile_key[tile] | P.lmask;
+        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
     }
     R acc[6] = {0, 0, 0, 0, 0, 0};
     uint32_t matched = 0, cnt = 0;
@@ -2143,7 +2162,7 @@ __global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ mov
     __shared__ uint32_t s_flag;
     const int t = threadIdx.x;
     // the count and the first movers are read before the error check
-    const uint32_t M = st->movers;
+    const uint32_t M = ((ConstPtr<Status>)st)->movers;
     const uint2 e0 = movers[t];  // t < 1024 <= MAX_MOVERS
     if (skip_if_error(st, &s_flag)) return;
     if (M == 0) return;
@@ -2235,7 +2254,7 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __re
     __shared__ uint32_t s_flag;
     // the mover count and the lane's keys are read before the error check,
     // so that they are in flight together
-    const uint32_t M = P.st->movers;
+    const uint32_t M = ((ConstPtr<Status>)P.st)->movers;
     const int t = threadIdx.x;
     const uint32_t N = P.ntiles * TILE;
     const uint32_t p0 = blockIdx.x * TILE, i = p0 + t;
