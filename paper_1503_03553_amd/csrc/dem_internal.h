@@ -152,9 +152,12 @@ struct PoolView {
 float detect_margin(const Geo& G);
 void launch_detect(const PoolView& P, int kmax, const Sorted& S, const uint2* cells, uint2* rows,
                    uint32_t* col_j, uint32_t slots, hipStream_t s);
-// With `movers` non-null the force kernel also writes the key of every
-// position before the step (`oldkeys`) and appends (new key, position) of
-// the particles whose key changed to `movers` (at most MAX_MOVERS).
+// The force kernel writes the sort's input.  With `movers` non-null (the
+// merge sort) that is the key of every position before the step (`oldkeys`)
+// and (new key, position) of the particles whose key changed, appended to
+// `movers` (at most MAX_MOVERS); otherwise (the radix sort) the new key and
+// index of every position (`keys`, `vals`), and the kernel empties the
+// bounds of the old cells.
 // X: the state the step reads (through perm), Y: the state it writes (in
 // sorted order); S: the sorted positions.
 void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
@@ -207,9 +210,11 @@ void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, 
                        const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
                        uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
                        uint32_t* oldkeys, uint2* movers, hipStream_t s);
-void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
-                       const uint2* movers, unsigned long long* mk, uint32_t* mp,
-                       uint32_t* keys_s, uint32_t* vals_s, hipStream_t s);
+// The merge sort also empties the cell bounds of the movers' old cells
+// (the force kernel leaves them in place with this sort).
+void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* movers,
+                       unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, uint32_t* vals_s,
+                       uint2* cells, hipStream_t s);
 // Sorts (keys, vals) by the low `bits` bits of keys; the result ends in
 // (keys_out, vals_out).  tmp buffers are the ping-pong partners.
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,

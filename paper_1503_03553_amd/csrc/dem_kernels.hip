@@ -1271,6 +1271,21 @@ __device__ __forceinline__ bool history_of(uint2 orw, uint32_t pid,
     return false;
 }
 
+// Sort input of a position that keeps its place (ghost slot, idle tile):
+// with the merge sort (movers given) only its key before the step, which is
+// also its key after; with the radix sort its key and index.
+__device__ __forceinline__ void fixed_sort_input(uint32_t* __restrict__ keys,
+                                                 uint32_t* __restrict__ vals,
+                                                 uint32_t* __restrict__ oldkeys, bool merge,
+                                                 uint32_t i, uint32_t key) {
+    if (merge) {
+        oldkeys[i] = key;
+    } else {
+        keys[i] = key;
+        vals[i] = i;
+    }
+}
+
 // A tile whose job is not running: keys that keep every position of the
 // tile in place; a finished job's state is carried over into the buffer
 // written.
@@ -1285,9 +1300,7 @@ __device__ __forceinline__ void idle_tile(const PoolView& P, const Job* __restri
                                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                           uint32_t* __restrict__ oldkeys, bool movers) {
     const uint32_t p0 = tile * TILE, ns = P.ns;
-    keys[p0 + t] = tile_key_of(P, tile) | P.lmask;
-    vals[p0 + t] = p0 + t;
-    if (movers) oldkeys[p0 + t] = tile_key_of(P, tile) | P.lmask;
+    fixed_sort_input(keys, vals, oldkeys, movers, p0 + t, tile_key_of(P, tile) | P.lmask);
     if (jb != NO_JOB) {
         const uint32_t i = p0 + t;
         if (i < jobs[jb].p0 + jobs[jb].n) {
@@ -1305,9 +1318,13 @@ __device__ __forceinline__ void idle_tile(const PoolView& P, const Job* __restri
 // lane of the workgroup: with `churn`, the churn counters (and, when `m` is
 // given, the contact count) into the tile's own slot; per-particle totals, gravity and the
 // semi-implicit Euler update in FP64 (section 3.4, "ForceGravity" and
-// "Integrate") into the buffer written; the new cell key ("CalcHash"); the
-// cell-change list.  With clear_cells, the first particle of each old cell
-// also empties that cell's bounds (the reorder writes those of the new order).
+// "Integrate") into the buffer written; the new cell key ("CalcHash") and the
+// sort's input: with the merge sort (movers given) the key before the step
+// and the cell-change list, with the radix sort the key and index.  With
+// clear_cells and the radix sort, the first particle of each old cell also
+// empties that cell's bounds (the reorder writes those of the new order); the
+// merge sort empties the old cells of the particles that changed cell, the
+// only cells that can be left empty.
 template <typename R>
 __device__ __forceinline__ void finish_tile(
     const PoolView& P, const Geo& G, const MatTable* __restrict__ mt, uint32_t tile, uint32_t jb,
@@ -1387,8 +1404,10 @@ __device__ __forceinline__ void finish_tile(
         vw_b[2 * (size_t)ns + i] = make_double2(wy, wz);
         if (mat_b) mat_b[i] = (uint8_t)mi;
         newkey = tile_key_of(P, tile) | cell_key(G, x, y, z);
-        keys[i] = newkey;
-        vals[i] = i;
+        if (!movers) {
+            keys[i] = newkey;
+            vals[i] = i;
+        }
         if (fo) {
             fo[i] = (R)Fx;
             fo[ns + i] = (R)Fy;
@@ -1398,7 +1417,7 @@ __device__ __forceinline__ void finish_tile(
             fo[5 * (size_t)ns + i] = acc[5];
         }
         const uint32_t okey = cell_key(G, a.x, a.y, a.z);
-        if (clear_cells) {
+        if (clear_cells && !movers) {
             const uint32_t lin = key_lin(G, okey);
             if (cells[lin].x == i) cells[lin] = make_uint2(0, 0);
         }
@@ -1523,9 +1542,7 @@ __global__ __launch_bounds__(TILE) void k_force(
     const uint32_t n = J.p0 + J.n;  // end of the job's particles
     if (i >= n) {
         // ghost slot after the job's last particle: sorts last, stays in place
-        keys[i] = tile_key_of(P, tile) | P.lmask;
-        vals[i] = i;
-        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
+        fixed_sort_input(keys, vals, oldkeys, movers != nullptr, i, tile_key_of(P, tile) | P.lmask);
     }
     const uint32_t nt = (n - p0) < (uint32_t)TILE ? (n - p0) : (uint32_t)TILE;
     uint2 row = make_uint2(0, 0);
@@ -1694,9 +1711,7 @@ __global__ __launch_bounds__(TILE) void k_force_thread(
     const uint32_t i = p0 + t;
     const uint32_t n = J.p0 + J.n;
     if (i >= n) {
-        keys[i] = tile_key_of(P, tile) | P.lmask;
-        vals[i] = i;
-        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
+        fixed_sort_input(keys, vals, oldkeys, movers != nullptr, i, tile_key_of(P, tile) | P.lmask);
     }
     R acc[6] = {0, 0, 0, 0, 0, 0};
     uint32_t matched = 0;
@@ -1902,9 +1917,7 @@ __global__ __launch_bounds__(TILE) void k_ar_sum(
     const uint32_t i = p0 + t;
     const uint32_t n = J.p0 + J.n;
     if (i >= n) {
-        keys[i] = tile_key_of(P, tile) | P.lmask;
-        vals[i] = i;
-        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
+        fixed_sort_input(keys, vals, oldkeys, movers != nullptr, i, tile_key_of(P, tile) | P.lmask);
     }
     R acc[6] = {0, 0, 0, 0, 0, 0};
     double4 a = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -1997,9 +2010,7 @@ __global__ __launch_bounds__(TILE) void k_fused(
     const uint32_t i = p0 + t;
     const uint32_t n = J.p0 + J.n;
     if (i >= n) {
-        keys[i] = tile_key_of(P, tile) | P.lmask;
-        vals[i] = i;
-        if (movers) oldkeys[i] = tile_key_of(P, tile) | P.lmask;
+        fixed_sort_input(keys, vals, oldkeys, movers != nullptr, i, tile_key_of(P, tile) | P.lmask);
     }
     R acc[6] = {0, 0, 0, 0, 0, 0};
     uint32_t matched = 0, cnt = 0;
@@ -2241,12 +2252,13 @@ __device__ inline uint32_t count_below_in(const K* lds, const K* glob, bool in_l
     return in_lds ? count_below(lds, m, v) : count_below(glob, m, v);
 }
 
-__global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __restrict__ keys,
+__global__ __launch_bounds__(TILE) void k_place(PoolView P, const Job* __restrict__ jobs,
                                                 const uint32_t* __restrict__ oldkeys,
                                                 const unsigned long long* __restrict__ mk,
                                                 const uint32_t* __restrict__ mp,
                                                 uint32_t* __restrict__ keys_s,
-                                                uint32_t* __restrict__ vals_s) {
+                                                uint32_t* __restrict__ vals_s,
+                                                uint2* __restrict__ cells) {
     __shared__ unsigned long long s_mk[LDS_MOVERS];
     __shared__ uint32_t s_mp[LDS_MOVERS];
     __shared__ unsigned long long s_ok[TILE];
@@ -2259,7 +2271,6 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __re
     const uint32_t N = P.ntiles * TILE;
     const uint32_t p0 = blockIdx.x * TILE, i = p0 + t;
     const uint32_t ok = oldkeys[i];
-    const bool moved = keys[i] != ok;
     if (skip_if_error(P.st, &s_flag)) return;
     auto key_of = [](uint32_t k, uint32_t p) { return ((unsigned long long)k << 32) | p; };
     if (M == 0) {
@@ -2289,9 +2300,16 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __re
         s_c[t] = c;
     }
     __syncthreads();
+    // a position is a mover's if the sorted mover positions hold it (none
+    // of the tile's unless movers leave from inside it)
+    uint32_t leave = s_c[0];
+    bool moved = false;
+    if (s_c[1] != s_c[0]) {
+        leave = count_below_in(s_mp, mp, in_lds, M, i);
+        moved = leave < M && (in_lds ? s_mp[leave] : mp[leave]) == i;
+    }
     if (!moved) {
-        uint32_t leave = s_c[0], arrive = s_c[2];
-        if (s_c[1] != s_c[0]) leave = count_below_in(s_mp, mp, in_lds, M, i);
+        uint32_t arrive = s_c[2];
         if (s_c[3] != s_c[2]) arrive = count_below_in(s_mk, mk, in_lds, M, key_of(ok, i));
         const uint32_t dest = i - leave + arrive;
         if (dest >= N) {  // inconsistent input: redo the step with the radix sort
@@ -2312,6 +2330,15 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const uint32_t* __re
         } else {
             keys_s[dest] = (uint32_t)(e >> 32);
             vals_s[dest] = (uint32_t)e;
+        }
+        // the mover's old cell may be left empty: its bounds are emptied
+        // here, and the reorder writes those of every cell the new order
+        // fills (the search of this step has read them already)
+        const uint32_t pos = (uint32_t)e;
+        if (pos < N) {
+            uint32_t jm;
+            const Job* J = tile_job(jobs, P, pos / TILE, jm);
+            if (J) cells[J->cell_base + key_lin(J->g, oldkeys[pos] & P.lmask)] = make_uint2(0, 0);
         }
     }
 }
@@ -2735,13 +2762,13 @@ void launch_detect_half(const PoolView& P, int kmax, const Sorted& S, const uint
 #undef DEM_HALF
 }
 
-void launch_merge_sort(const PoolView& P, const uint32_t* keys, const uint32_t* oldkeys,
-                       const uint2* movers, unsigned long long* mk, uint32_t* mp,
-                       uint32_t* keys_s, uint32_t* vals_s, hipStream_t s) {
+void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* movers,
+                       unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, uint32_t* vals_s,
+                       uint2* cells, hipStream_t s) {
     if (P.ntiles == 0) return;
     hipLaunchKernelGGL(k_mov_sort, dim3(1), dim3(1024), 0, s, movers, mk, mp, P.st);
-    hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, keys, oldkeys, mk, mp, keys_s,
-                       vals_s);
+    hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, oldkeys, mk, mp,
+                       keys_s, vals_s, cells);
 }
 
 size_t sort_hist_words(uint32_t n) {

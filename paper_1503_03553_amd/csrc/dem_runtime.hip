@@ -1058,7 +1058,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
     prof_record(s, slot, 2);
     uint32_t *ko, *vo;
     if (merge) {
-        launch_merge_sort(P, s->keys, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, s->vals_t,
+        launch_merge_sort(P, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, s->vals_t, s->cells,
                           s->stream);
         ko = s->keys_t;
         vo = s->vals_t;
