@@ -61,19 +61,21 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True,
         return 48 * n + 4 * m
     if phase == "force":
         # reads: sorted position 32, velocities 48 and old row 8 through the
-        # permutation 4, new row 8, cell bound 4; writes: integrated state 80,
-        # key, index and key before the step 12, F/T 24 (48 in FP64) when
-        # stored; per contact: partner index 4, partner permutation 4, new
-        # history 28; per old contact 28.  With the half search also the list
-        # counter read and reset 8 per particle, and per contact the list
-        # entry 8 and the partner index written 4.
+        # permutation 4, new row 8; writes: integrated state 80, F/T 24 (48 in
+        # FP64) when stored; the sort's input: with the merge sort the key
+        # before the step 4, with the radix sort key and index 8 and the old
+        # cell's bound read 4; per contact: partner index 4, partner
+        # permutation 4, new history 28; per old contact 28.  With the half
+        # search also the list counter read and reset 8 per particle, and per
+        # contact the list entry 8 and the partner index written 4.
         fo = (48 if fp64 else 24) if force_out else 0
         extra = 8 * n + 12 * m if half else 0
-        return (104 + 92 + fo) * n + 36 * m + 28 * m_old + extra
+        sort_in = 4 if merge else 12
+        return (100 + 80 + sort_in + fo) * n + 36 * m + 28 * m_old + extra
     if phase == "sort":
         if merge:
-            # keys before and after the step read, sorted index written, plus
-            # the few movers (negligible)
+            # keys before the step read, sorted keys and indices written,
+            # plus the few movers (negligible)
             return 12 * n
         passes = max(1, (key_bits + 7) // 8)
         return 20 * n * passes

@@ -399,7 +399,9 @@ __device__ __forceinline__ uint32_t candidate_ranges(const Geo& G, const double4
 
 // FP32 pre-filter of a candidate record: never rejects a pair that touches in
 // FP64 (NaN records of particles far from the box always pass).
-template <bool PER>
+// CUT: a two-level job's walk, which leaves candidates above the radius cut
+// to the wide scan.
+template <bool PER, bool CUT = true>
 struct PreFilter {
     float4 me;
     float Lx, Ly, Lz, Df, iLx, iLy, iLz, rm;
@@ -433,7 +435,7 @@ struct PreFilter {
             if (per & 4u) dz += (float)(-(int)rintf(dz * iLz)) * Lz;
         }
         const float sm = rm + b.w;
-        return !(dx * dx + dy * dy + dz * dz >= sm * sm) && b.w <= rc;
+        return !(dx * dx + dy * dy + dz * dz >= sm * sm) && (!CUT || b.w <= rc);
     }
 };
 
@@ -938,48 +940,59 @@ __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __
     }
     const PreFilter<PER> pre(G, a, J.margin);
     const PreFilter<false> pre0(G, a, J.margin);
+    const PreFilter<false, false> pre1(G, a, J.margin);
     constexpr uint32_t NONE = 0xFFFFFFFFu;
     uint32_t sc = 0;
     auto walk = [&](const auto& filt) {
-        // the plain kernel's walk: branch-free over the ranges with a
-        // sentinel range at the end, four records in flight
+        // the plain kernel's walk: branch-free over the ranges, four records
+        // in flight.  After the last range the walk stays on the particle's
+        // own position (a range of one entry behind the last), so every
+        // index it loads is a position; a count of the candidates left
+        // masks the slots past the end.
         if (nw == 0) return;
-        s_win[nw * DTILE + t] = make_uint2(NONE, NONE);
+        uint32_t left = 0;
+        for (uint32_t w2 = 0; w2 < nw; ++w2) {
+            const uint2 r2 = s_win[w2 * DTILE + t];
+            left += r2.y - r2.x;
+        }
+        s_win[nw * DTILE + t] = make_uint2(i, i + 1);
         uint32_t w = 0;
         uint2 rg = s_win[t];
         uint2 rn = s_win[DTILE + t];
         uint32_t j = rg.x;
         auto next = [&]() -> uint32_t {
             const uint32_t c = j;
-            const bool live = c != NONE;
-            const bool sw = live && c + 1 == rg.y;
-            j = !live ? NONE : (sw ? rn.x : c + 1);
+            const bool sw = c + 1 == rg.y;
+            j = sw ? rn.x : c + 1;
             rg.y = sw ? rn.y : rg.y;
             w += sw ? 1u : 0u;
             rn = s_win[min(w + 1, nw) * DTILE + t];
             return c;
         };
         uint32_t j0 = next(), j1 = next(), j2 = next(), j3 = next();
-        float4 q0 = xf[j0 < nsz ? j0 : i], q1 = xf[j1 < nsz ? j1 : i];
-        float4 q2 = xf[j2 < nsz ? j2 : i], q3 = xf[j3 < nsz ? j3 : i];
-#define DEM_HALF_STEP(Q, JQ)                                       \
+        float4 q0 = xf[j0], q1 = xf[j1], q2 = xf[j2], q3 = xf[j3];
+        // the four slots hold consecutive candidates, the oldest in slot 0
+#define DEM_HALF_STEP(Q, JQ, S)                                    \
     {                                                              \
-        if (JQ == NONE) break;                                     \
-        const bool hit = filt(Q);                                  \
+        const bool hit = (left > S) & filt(Q);                     \
         s_j[min(sc, (uint32_t)SB) * DTILE + t] = JQ;               \
         sc += hit ? 1u : 0u;                                       \
         JQ = next();                                               \
-        Q = xf[JQ < nsz ? JQ : i];                                 \
+        Q = xf[JQ];                                                \
     }
-        for (;;) {
-            DEM_HALF_STEP(q0, j0)
-            DEM_HALF_STEP(q1, j1)
-            DEM_HALF_STEP(q2, j2)
-            DEM_HALF_STEP(q3, j3)
+        while (left > 0) {
+            DEM_HALF_STEP(q0, j0, 0u)
+            DEM_HALF_STEP(q1, j1, 1u)
+            DEM_HALF_STEP(q2, j2, 2u)
+            DEM_HALF_STEP(q3, j3, 3u)
+            left = left > 4u ? left - 4u : 0u;
         }
 #undef DEM_HALF_STEP
     };
-    if (!PER || plain)
+    // a one-level job (no particle above the cut) skips the radius test
+    if ((!PER || plain) && G.nbig == 0)
+        walk(pre1);
+    else if (!PER || plain)
         walk(pre0);
     else
         walk(pre);

@@ -30,8 +30,12 @@ def test_kernel_bytes_of_the_two_searches():
     assert bench.kernel_bytes("detect", n, m, mo, False, 20, half=False) == 48 * n + 4 * m
     full = bench.kernel_bytes("force", n, m, mo, False, 20, half=False)
     half = bench.kernel_bytes("force", n, m, mo, False, 20)
-    assert full == 196 * n + 36 * m + 28 * mo
+    assert full == 184 * n + 36 * m + 28 * mo
     assert half - full == 8 * n + 12 * m
+    # the radix sort's input: key and index instead of the key before the
+    # step, and the old cell's bound read
+    radix = bench.kernel_bytes("force", n, m, mo, False, 20, half=False, merge=False)
+    assert radix - full == 8 * n
     assert bench.kernel_bytes("force", n, m, mo, True, 20, force_out=True, half=False) == full + 48 * n
 
 
