@@ -74,12 +74,16 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True,
         return (100 + 80 + sort_in + fo) * n + 36 * m + 28 * m_old + extra
     if phase == "sort":
         if merge:
-            # keys before the step read, sorted keys and indices written,
-            # plus the few movers (negligible)
-            return 12 * n
+            # keys before the step and the new state's positions read 36; at
+            # each new position the sorted key, position and FP32 record and
+            # the permutation written 56; plus the few movers (negligible)
+            return 92 * n
         passes = max(1, (key_bits + 7) // 8)
         return 20 * n * passes
     if phase == "reorder":
+        if merge:
+            # the sorted keys (neighbours from the cache) 4, cell bounds ~8
+            return 12 * n
         # sorted key and source index 8, gathered position 32, sorted position
         # and FP32 record written 48, permutation 4, cell bounds ~8
         return 100 * n
@@ -100,10 +104,11 @@ def method_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, merge=True
               state written 72, key and index 8; per contact partner index 4
               and new id and displacement 28; per old contact id and
               displacement 28; F and T 24 (48 in FP64) only when stored
-      sort    (stable sort of (key, index))  the implementation's bytes
+      sort    (stable sort of (key, index))  the implementation's bytes (the
+              merge sort's placement also writes the sorted positions)
       reorder (gather into cell order, cell bounds)  at most 168 (index 4,
-              record gathered 80 and written 80, bounds 4); the kernel gathers
-              only positions, so its own smaller count applies
+              record gathered 80 and written 80, bounds 4); the kernels move
+              only positions, so their own smaller count applies
     """
     impl = kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=force_out, merge=merge)
     if phase == "detect":

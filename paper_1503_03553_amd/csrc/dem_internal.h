@@ -210,22 +210,27 @@ void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, 
                        const double* tab_dt_old, uint32_t* tab_pid_new, double* tab_dt_new,
                        uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
                        uint32_t* oldkeys, uint2* movers, hipStream_t s);
-// The merge sort also empties the cell bounds of the movers' old cells
-// (the force kernel leaves them in place with this sort).
+// The merge sort: the sorted keys (keys_s) and, placed directly at their
+// new positions, the sorted position records S gathered from the state Y
+// just written and the permutation perm (new sorted position -> position in
+// Y).  S and perm are the buffers of the next step, not those this step
+// read.  It also empties the cell bounds of the movers' old cells (the force
+// kernel leaves them in place with this sort).
 void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* movers,
-                       unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, uint32_t* vals_s,
-                       uint2* cells, hipStream_t s);
+                       unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, const State& Y,
+                       const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s);
 // Sorts (keys, vals) by the low `bits` bits of keys; the result ends in
 // (keys_out, vals_out).  tmp buffers are the ping-pong partners.
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
                        uint32_t n, int bits, uint32_t* tile_hist, uint32_t* digit_tot,
                        uint32_t** keys_out, uint32_t** vals_out, const Status* st, hipStream_t s);
-// After the sort: the permutation (new sorted position -> position in Y),
-// the sorted position records gathered from Y, the cell bounds; then the
-// step ends for the `njobs` job descriptors (time, steps, status).
-void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
-                    const uint32_t* vals_s, const State& Y, const Sorted& S, uint32_t* perm,
-                    uint2* cells, hipStream_t s);
+// After the sort: with `gather` (the radix sort) the permutation (new
+// sorted position -> position in Y) and the sorted position records
+// gathered from Y into the next step's buffers S and perm; the cell bounds;
+// then the step ends for the `njobs` job descriptors (time, steps, status).
+void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, bool gather,
+                    const uint32_t* keys_s, const uint32_t* vals_s, const State& Y,
+                    const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s);
 // Replaces the radii of the positions [p0, p0 + n) of one job (rnew in
 // particle-id order) in the state X the next step reads and its sorted
 // records S.

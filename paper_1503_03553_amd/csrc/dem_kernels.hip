@@ -2270,25 +2270,44 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const Job* __restric
                                                 const unsigned long long* __restrict__ mk,
                                                 const uint32_t* __restrict__ mp,
                                                 uint32_t* __restrict__ keys_s,
-                                                uint32_t* __restrict__ vals_s,
+                                                const double4* __restrict__ xr_y,
+                                                double4* __restrict__ xs, float4* __restrict__ xf,
+                                                uint32_t* __restrict__ perm,
                                                 uint2* __restrict__ cells) {
     __shared__ unsigned long long s_mk[LDS_MOVERS];
     __shared__ uint32_t s_mp[LDS_MOVERS];
     __shared__ unsigned long long s_ok[TILE];
     __shared__ uint32_t s_c[4];
     __shared__ uint32_t s_flag;
-    // the mover count and the lane's keys are read before the error check,
-    // so that they are in flight together
+    // the mover count, the lane's key and its new state's position are read
+    // before the error check, so that they are in flight together
     const uint32_t M = ((ConstPtr<Status>)P.st)->movers;
     const int t = threadIdx.x;
     const uint32_t N = P.ntiles * TILE;
     const uint32_t p0 = blockIdx.x * TILE, i = p0 + t;
     const uint32_t ok = oldkeys[i];
+    const double4 pi = xr_y[i];
     if (skip_if_error(P.st, &s_flag)) return;
     auto key_of = [](uint32_t k, uint32_t p) { return ((unsigned long long)k << 32) | p; };
+    // the new order's sorted key, and for a particle of a running job its
+    // position record, FP32 record and source position, at `dest`
+    auto emit = [&](uint32_t dest, uint32_t key, uint32_t src, const double4& q, const Job* J) {
+        keys_s[dest] = key;
+        if (J) {
+            xs[dest] = q;
+            xf[dest] = far_record(J->g, q);
+            perm[dest] = src;
+        }
+    };
+    uint32_t jb;
+    const Job* Jt = tile_job(jobs, P, blockIdx.x, jb);
+    // a lane's own particle: in a running job, or in a finished one (whose
+    // positions map to themselves)
+    const Job* Ji = Jt && i < Jt->p0 + Jt->n ? Jt : nullptr;
+    if (!Jt && jb != NO_JOB && i < ((ConstPtr<Job>)jobs)[jb].p0 + ((ConstPtr<Job>)jobs)[jb].n)
+        perm[i] = i;
     if (M == 0) {
-        keys_s[i] = ok;
-        vals_s[i] = i;
+        emit(i, ok, i, pi, Ji);
         return;
     }
     const bool in_lds = M <= LDS_MOVERS;
@@ -2325,12 +2344,10 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const Job* __restric
         uint32_t arrive = s_c[2];
         if (s_c[3] != s_c[2]) arrive = count_below_in(s_mk, mk, in_lds, M, key_of(ok, i));
         const uint32_t dest = i - leave + arrive;
-        if (dest >= N) {  // inconsistent input: redo the step with the radix sort
+        if (dest >= N)  // inconsistent input: redo the step with the radix sort
             atomicOr(&P.st->err, ERR_MOVERS);
-        } else {
-            keys_s[dest] = ok;
-            vals_s[dest] = i;
-        }
+        else
+            emit(dest, ok, i, pi, Ji);
     }
     // the first tile also places the movers that sort before every position
     const uint32_t mlo = blockIdx.x == 0 ? 0u : s_c[2];
@@ -2338,21 +2355,18 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const Job* __restric
         const unsigned long long e = in_lds ? s_mk[m] : mk[m];
         const uint32_t lb = p0 + count_below(s_ok, (uint32_t)TILE, e);
         const uint32_t dest = lb - count_below_in(s_mp, mp, in_lds, M, lb) + m;
-        if (dest >= N) {
-            atomicOr(&P.st->err, ERR_MOVERS);
-        } else {
-            keys_s[dest] = (uint32_t)(e >> 32);
-            vals_s[dest] = (uint32_t)e;
-        }
-        // the mover's old cell may be left empty: its bounds are emptied
-        // here, and the reorder writes those of every cell the new order
-        // fills (the search of this step has read them already)
         const uint32_t pos = (uint32_t)e;
-        if (pos < N) {
-            uint32_t jm;
-            const Job* J = tile_job(jobs, P, pos / TILE, jm);
-            if (J) cells[J->cell_base + key_lin(J->g, oldkeys[pos] & P.lmask)] = make_uint2(0, 0);
+        if (dest >= N || pos >= N) {
+            atomicOr(&P.st->err, ERR_MOVERS);
+            continue;
         }
+        uint32_t jm;
+        const Job* J = tile_job(jobs, P, pos / TILE, jm);
+        emit(dest, (uint32_t)(e >> 32), pos, xr_y[pos], J);
+        // the mover's old cell may be left empty: its bounds are emptied
+        // here, and the bounds kernel writes those of every cell the new
+        // order fills (the search of this step has read them already)
+        if (J) cells[J->cell_base + key_lin(J->g, oldkeys[pos] & P.lmask)] = make_uint2(0, 0);
     }
 }
 
@@ -2500,10 +2514,14 @@ __device__ inline void tick_job(const PoolView& P, Job* jobs, uint32_t k) {
     if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
 }
 
-// One workgroup per tile.  The new sorted order: the permutation into the
-// buffer just written, the position records gathered from it, and the cell
-// bounds.  Positions of free tiles and ghost slots kept their place in the
-// sort and are left alone; a finished job's positions map to themselves.
+// One workgroup per tile.  The new sorted order: with GATHER (after the
+// radix sort) the permutation into the buffer just written, the position
+// records gathered from it (a finished job's positions map to themselves);
+// in every case the cell bounds and the step's counters.  The merge sort's
+// placement writes the permutation and records itself (k_place).  Positions
+// of free tiles and ghost slots kept their place in the sort and are left
+// alone.
+template <bool GATHER>
 __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restrict__ jobs,
                                                   const uint32_t* __restrict__ keys_s,
                                                   const uint32_t* __restrict__ vals_s,
@@ -2519,15 +2537,19 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     // so that all are in flight together (every index is a position; a lane
     // outside a running job ignores what it read)
     const uint32_t key = keys_s[i];
-    const uint32_t src = vals_s[i] < P.ns ? vals_s[i] : i;
-    const double4 p = xr_y[src];
+    uint32_t src = i;
+    double4 p = make_double4(0, 0, 0, 0);
+    if (GATHER) {
+        src = vals_s[i] < P.ns ? vals_s[i] : i;
+        p = xr_y[src];
+    }
     const uint32_t key_lo = i > 0 ? keys_s[i - 1] : 0u;
     const uint32_t key_hi = i + 1 < P.ns ? keys_s[i + 1] : 0u;
     if (skip_if_error(P.st, &s_flag)) return;
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
     if (!Jp) {
-        if (jb != NO_JOB && i < jobs[jb].p0 + jobs[jb].n) perm[i] = i;
+        if (GATHER && jb != NO_JOB && i < jobs[jb].p0 + jobs[jb].n) perm[i] = i;
         return;
     }
     const Job& J = *Jp;
@@ -2543,9 +2565,11 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     if (i >= end) return;
     // a source index is a position by construction; checked (above) so that
     // a sort defect can never read outside the arrays
-    xs[i] = p;
-    xf[i] = far_record(G, p);
-    perm[i] = src;
+    if (GATHER) {
+        xs[i] = p;
+        xf[i] = far_record(G, p);
+        perm[i] = src;
+    }
     const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
     if (i == J.p0 || key_lo != key) cells[lin].x = i;
     if (i == end - 1 || key_hi != key) cells[lin].y = i + 1;
@@ -2776,12 +2800,12 @@ void launch_detect_half(const PoolView& P, int kmax, const Sorted& S, const uint
 }
 
 void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* movers,
-                       unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, uint32_t* vals_s,
-                       uint2* cells, hipStream_t s) {
+                       unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, const State& Y,
+                       const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s) {
     if (P.ntiles == 0) return;
     hipLaunchKernelGGL(k_mov_sort, dim3(1), dim3(1024), 0, s, movers, mk, mp, P.st);
     hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, oldkeys, mk, mp,
-                       keys_s, vals_s, cells);
+                       keys_s, Y.xr, S.xr, S.xf, perm, cells);
 }
 
 size_t sort_hist_words(uint32_t n) {
@@ -2827,12 +2851,17 @@ void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipS
                            cells);
 }
 
-void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, const uint32_t* keys_s,
-                    const uint32_t* vals_s, const State& Y, const Sorted& S, uint32_t* perm,
-                    uint2* cells, hipStream_t s) {
-    if (P.ntiles > 0)
-        hipLaunchKernelGGL(k_reorder, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, keys_s, vals_s,
-                           Y.xr, S.xr, S.xf, perm, cells);
+void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, bool gather,
+                    const uint32_t* keys_s, const uint32_t* vals_s, const State& Y,
+                    const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s) {
+    if (P.ntiles > 0) {
+        if (gather)
+            hipLaunchKernelGGL(k_reorder<true>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
+                               keys_s, vals_s, Y.xr, S.xr, S.xf, perm, cells);
+        else
+            hipLaunchKernelGGL(k_reorder<false>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
+                               keys_s, vals_s, Y.xr, S.xr, S.xf, perm, cells);
+    }
     const uint32_t nb = (njobs + 255) / 256;
     hipLaunchKernelGGL(k_tick, dim3(nb ? nb : 1), dim3(256), 0, s, P, jobs, njobs);
 }

@@ -129,13 +129,17 @@ struct dem_pool {
     std::vector<Buf> bufs;
     size_t device_bytes = 0;
     State S[2]{};                     // state buffers; S[cur] holds the current state
-    Sorted srt{};                     // sorted position records of the current order
+    // sorted position records and permutation (sorted position -> position
+    // in the state buffer) of the order a step reads, one pair per state
+    // buffer: a step reads those of S[o] and writes those of S[w], so that an
+    // abandoned step leaves the ones it started from intact
+    Sorted srt[2]{};
     uint2* cells = nullptr;
     uint2* rows[2] = {nullptr, nullptr};
     uint32_t* col_j = nullptr;
     uint32_t* tab_pid[2] = {nullptr, nullptr};
     double* tab_dt[2] = {nullptr, nullptr};
-    uint32_t* prev = nullptr;
+    uint32_t* prev[2] = {nullptr, nullptr};
     uint32_t *keys = nullptr, *vals = nullptr, *keys_t = nullptr, *vals_t = nullptr;
     uint32_t* tile_hist = nullptr;
     uint32_t* digit_tot = nullptr;
@@ -470,9 +474,9 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     const uint64_t np = max_tiles * TILE;
     uint64_t b = 0;
     b += 2 * np * (32 + 48 + 1);       // two state buffers
-    b += np * (32 + 16);               // sorted positions and their FP32 records
+    b += 2 * np * (32 + 16);           // sorted positions and their FP32 records, two steps
     b += np * 2 * 8;                   // contact rows, two steps
-    b += np * 6 * 4;                   // prev, keys and values (two buffers), keys before
+    b += np * 7 * 4;                   // permutation (two), keys and values (two), keys before
     b += (uint64_t)MAX_MOVERS * 20;    // mover lists
     b += np * 6 * (fp64 ? 8 : 4);      // per-particle F, T
     b += max_cells * 8;                // cell bounds
@@ -482,7 +486,7 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
     b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4 + DEM_MAX_WALLS * sizeof(dem_wall));
     b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
-    b += 48 * ARENA_ALIGN;  // alignment of each buffer in an arena
+    b += 52 * ARENA_ALIGN;  // alignment of each buffer in an arena
     return b;
 }
 
@@ -529,7 +533,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     s->free_cells.push_back({0, s->max_cells});
     const size_t np = (size_t)mt * TILE;
     dem_status r = DEM_OK;
-    void *xa, *va, *ma, *xsa, *xfa, *xb, *vb, *mb;
+    void *xa, *va, *ma, *xsa, *xfa, *xsb, *xfb, *xb, *vb, *mb;
 #define ALLOC_OR_FAIL(call)   \
     do {                      \
         r = (call);           \
@@ -543,6 +547,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc(s, np, &ma));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xsa));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(float4), &xfa));
+    ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xsb));
+    ALLOC_OR_FAIL(dalloc(s, np * sizeof(float4), &xfb));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xb));
     ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &vb));
     ALLOC_OR_FAIL(dalloc(s, np, &mb));
@@ -552,12 +558,15 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     s->S[1].xr = (double4*)xb;
     s->S[1].vw = (double2*)vb;
     s->S[1].mat = (uint8_t*)mb;
-    s->srt.xr = (double4*)xsa;
-    s->srt.xf = (float4*)xfa;
+    s->srt[0].xr = (double4*)xsa;
+    s->srt[0].xf = (float4*)xfa;
+    s->srt[1].xr = (double4*)xsb;
+    s->srt[1].xf = (float4*)xfb;
     ALLOC_OR_FAIL(dalloc_t(s, s->max_cells, &s->cells));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[0]));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[1]));
-    ALLOC_OR_FAIL(dalloc_t(s, np, &s->prev));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->prev[0]));
+    ALLOC_OR_FAIL(dalloc_t(s, np, &s->prev[1]));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->keys));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->vals));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->keys_t));
@@ -786,9 +795,9 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     State& X = s->S[s->cur];
     upv(X.xr + p0, pl.xr);
     if (r == DEM_OK && n)
-        r = hip_status(hipMemcpyAsync(s->srt.xr + p0, X.xr + p0, n * sizeof(double4),
+        r = hip_status(hipMemcpyAsync(s->srt[s->cur].xr + p0, X.xr + p0, n * sizeof(double4),
                                       hipMemcpyDeviceToDevice, s->stream));
-    upv(s->srt.xf + p0, pl.xf);
+    upv(s->srt[s->cur].xf + p0, pl.xf);
     upv(X.vw + p0, pl.vw0);
     upv(X.vw + np + p0, pl.vw1);
     upv(X.vw + 2 * np + p0, pl.vw2);
@@ -799,7 +808,7 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     std::vector<uint32_t> idp(span);
     std::iota(idp.begin(), idp.end(), p0);
     up(s->rows[s->cur] + p0, zr.data(), span * sizeof(uint2));
-    up(s->prev + p0, idp.data(), span * 4);
+    up(s->prev[s->cur] + p0, idp.data(), span * 4);
     std::vector<TileStats> z(J.ntiles);
     if (J.ntiles) std::memset(z.data(), 0, z.size() * sizeof(TileStats));
     up(s->ts + J.tile0, z.data(), J.ntiles * sizeof(TileStats));
@@ -1021,45 +1030,45 @@ dem_status enqueue_step(dem_pool* s, int o) {
     prof_record(s, slot, 0);
     const bool half = half_search(s->flags);
     if (half)
-        launch_detect_half(P, s->kmax, s->srt, s->cells, s->deg, s->adj, s->stream);
+        launch_detect_half(P, s->kmax, s->srt[o], s->cells, s->deg, s->adj, s->stream);
     else if (!fused)
-        launch_detect(P, s->kmax, s->srt, s->cells, s->rows[w], s->col_j, s->slots, s->stream);
+        launch_detect(P, s->kmax, s->srt[o], s->cells, s->rows[w], s->col_j, s->slots, s->stream);
     prof_record(s, slot, 1);
     // the merge sort unless a recent step had too many cell changes
     const bool merge = s->radix_left == 0 && !(s->flags & DEM_FLAG_RADIX_SORT);
     if (s->radix_left) s->radix_left--;
     void* fo = (s->flags & DEM_FLAG_NO_FORCE_OUTPUT) ? nullptr : s->fo;
     if (s->flags & DEM_FLAG_ACTION_REACTION)
-        launch_action_reaction(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o],
-                               s->prev, s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w],
+        launch_action_reaction(P, s->fp64, s->srt[o], X, Y, s->rows[w], s->col_j, s->rows[o],
+                               s->prev[o], s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w],
                                s->cap, s->pf, s->cells, s->keys, s->vals, fo,
                                merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr,
                                s->stream);
     else if (s->flags & DEM_FLAG_THREAD_SPLIT)
-        launch_force_thread(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
+        launch_force_thread(P, s->fp64, s->srt[o], X, Y, s->rows[w], s->col_j, s->rows[o], s->prev[o],
                             s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap,
                             s->cells, s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
                             merge ? s->movers : nullptr, s->stream);
     else if (fused)
-        launch_fused(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
+        launch_fused(P, s->fp64, s->srt[o], X, Y, s->rows[w], s->col_j, s->rows[o], s->prev[o],
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->slots,
                      s->cells, s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
                      merge ? s->movers : nullptr, s->stream);
     else if (half)
-        launch_force_half(P, s->fp64, s->kmax, s->srt, X, Y, s->deg, s->adj, s->rows[w], s->col_j,
-                          s->slots, s->rows[o], s->prev, s->tab_pid[o], s->tab_dt[o],
+        launch_force_half(P, s->fp64, s->kmax, s->srt[o], X, Y, s->deg, s->adj, s->rows[w], s->col_j,
+                          s->slots, s->rows[o], s->prev[o], s->tab_pid[o], s->tab_dt[o],
                           s->tab_pid[w], s->tab_dt[w], s->cap, s->cells, s->keys, s->vals, fo,
                           merge ? s->oldkeys : nullptr, merge ? s->movers : nullptr, s->stream);
     else
-        launch_force(P, s->fp64, s->srt, X, Y, s->rows[w], s->col_j, s->rows[o], s->prev,
+        launch_force(P, s->fp64, s->srt[o], X, Y, s->rows[w], s->col_j, s->rows[o], s->prev[o],
                      s->tab_pid[o], s->tab_dt[o], s->tab_pid[w], s->tab_dt[w], s->cap, s->cells,
                      s->keys, s->vals, fo, merge ? s->oldkeys : nullptr,
                      merge ? s->movers : nullptr, s->stream);
     prof_record(s, slot, 2);
     uint32_t *ko, *vo;
     if (merge) {
-        launch_merge_sort(P, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, s->vals_t, s->cells,
-                          s->stream);
+        launch_merge_sort(P, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, Y, s->srt[w],
+                          s->prev[w], s->cells, s->stream);
         ko = s->keys_t;
         vo = s->vals_t;
     } else {
@@ -1068,7 +1077,8 @@ dem_status enqueue_step(dem_pool* s, int o) {
                           s->st, s->stream);
     }
     prof_record(s, slot, 3);
-    launch_reorder(P, s->jobs_d, s->max_jobs, ko, vo, Y, s->srt, s->prev, s->cells, s->stream);
+    launch_reorder(P, s->jobs_d, s->max_jobs, !merge, ko, vo, Y, s->srt[w], s->prev[w], s->cells,
+                   s->stream);
     prof_record(s, slot, 4);
     HIPCHK(hipGetLastError());
     return DEM_OK;
@@ -1193,7 +1203,7 @@ dem_status sync_impl(dem_pool* s) {
         HIPCHK(hipMemcpy(s->st, &z, sizeof(Status), hipMemcpyHostToDevice));
         // the abandoned step may have emptied cell bounds (the force kernel
         // does so as it runs): restore those of the order it started from
-        launch_rebuild_cells(view(s), s->srt, s->cells, s->stream);
+        launch_rebuild_cells(view(s), s->srt[o], s->cells, s->stream);
         HIPCHK(hipGetLastError());
         s->prof_used = 0;
         const size_t k = s->pending.size();
@@ -1470,7 +1480,8 @@ dem_status set_radii_impl(dem_pool* s, int slot, const float* radius) {
     if (r == DEM_OK) r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
     if (r != DEM_OK) return r;
     const uint32_t p0 = J.tile0 * TILE;
-    launch_set_radii(p0, (uint32_t)n, (const float*)s->keys_t, s->S[s->cur], s->srt, s->stream);
+    launch_set_radii(p0, (uint32_t)n, (const float*)s->keys_t, s->S[s->cur], s->srt[s->cur],
+                     s->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     s->staging.clear();

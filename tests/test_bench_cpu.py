@@ -80,8 +80,13 @@ def test_method_bytes_count_the_method_not_the_implementation():
     for ph in ("detect", "force"):
         assert bench.kernel_bytes(ph, n, m, mo, False, 20) > bench.method_bytes(ph, n, m, mo,
                                                                                 False, 20)
-    # the reorder gathers positions only: its own count is below the method's 168
-    assert bench.method_bytes("reorder", n, m, mo, False, 20) == 100 * n
+    # the kernels move positions only: their own counts are below the
+    # method's 168 for the gather into cell order (after the merge sort the
+    # placement writes the sorted positions and the reorder only the bounds)
+    assert bench.method_bytes("reorder", n, m, mo, False, 20, merge=False) == 100 * n
+    assert bench.method_bytes("reorder", n, m, mo, False, 20) == 12 * n
+    assert bench.method_bytes("sort", n, m, mo, False, 20) + \
+        bench.method_bytes("reorder", n, m, mo, False, 20) < 168 * n
     rows = bench.phase_rows({"detect": (0.05, 1), "force": (0.07, 1)}, n, m, mo, False, 20)
     c = bench.contact_kernels_of(rows)
     assert c["bytes_per_step"] == 40 * n + 4 * m + 176 * n + 32 * m + 28 * mo
