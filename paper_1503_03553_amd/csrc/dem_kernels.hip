@@ -1495,7 +1495,11 @@ __global__ __launch_bounds__(TILE) void k_force(
     // the velocities and the chunk's forces; with HK, first the partner ids
     // of the lists (HK slots per particle)
     constexpr size_t VWF = sizeof(double2) * 3 * TILE + sizeof(R) * 6 * TILE;
-    constexpr size_t LST = (size_t)HK * TILE * 4;
+    // at most 16 list slots per lane are held in LDS: a longer list (only
+    // after a row overflow, and rare then) reads its further partner ids
+    // from the list itself, so 32 slots need no more LDS than 16
+    constexpr uint32_t LK = HK < 16 ? (uint32_t)HK : 16u;
+    constexpr size_t LST = (size_t)LK * TILE * 4;
     __shared__ __align__(16) unsigned char s_u[VWF > LST ? VWF : LST];
     double2(*const s_vw)[TILE] = reinterpret_cast<double2(*)[TILE]>(s_u);
     R(*const s_f)[TILE] = reinterpret_cast<R(*)[TILE]>(s_u + sizeof(double2) * 3 * TILE);
@@ -1594,11 +1598,12 @@ __global__ __launch_bounds__(TILE) void k_force(
 #pragma unroll
         for (int m = 0; m < 4; ++m)
             if ((uint32_t)m < cnt) s_lp[m * TILE + t] = e0[m].y;
-        for (uint32_t k = 4; k < cnt; ++k) s_lp[k * TILE + t] = adj[(size_t)k * ns + i].y;
+        for (uint32_t k = 4; k < cnt && k < LK; ++k) s_lp[k * TILE + t] = adj[(size_t)k * ns + i].y;
         auto place = [&](const uint2 e, uint32_t k) {
             uint32_t rank = 0;
             for (uint32_t m = 0; m < cnt; ++m) {
-                const uint32_t pm = s_lp[m * TILE + t];
+                const uint32_t pm = (HK <= 16 || m < LK) ? s_lp[m * TILE + t]
+                                                         : adj[(size_t)m * ns + i].y;
                 rank += (pm < e.y || (pm == e.y && m < k)) ? 1u : 0u;
             }
             col_out[rbase + ex + rank] = e.x;
@@ -2190,6 +2195,31 @@ __global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ mov
     const uint2 e0 = movers[t];  // t < 1024 <= MAX_MOVERS
     if (skip_if_error(st, &s_flag)) return;
     if (M == 0) return;
+    if (M <= 64) {
+        // few movers (the common case): the first wavefront sorts both
+        // orders in registers, one mover per lane, with the same bitonic
+        // network across lanes (lane t and lane t ^ j compare-exchange;
+        // the lower lane keeps the minimum in an ascending block)
+        if (t >= 64) return;
+        unsigned long long k = (uint32_t)t < M ? ((unsigned long long)e0.x << 32) | e0.y : ~0ull;
+        uint32_t p = (uint32_t)t < M ? e0.y : 0xFFFFFFFFu;
+        for (int kk = 2; kk <= 64; kk <<= 1) {
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const uint32_t klo = __shfl_xor((uint32_t)k, j, 64);
+                const uint32_t khi = __shfl_xor((uint32_t)(k >> 32), j, 64);
+                const unsigned long long ko = ((unsigned long long)khi << 32) | klo;
+                const uint32_t po = __shfl_xor(p, j, 64);
+                const bool keep_min = ((t & j) == 0) == ((t & kk) == 0);
+                k = keep_min ? (ko < k ? ko : k) : (ko > k ? ko : k);
+                p = keep_min ? (po < p ? po : p) : (po > p ? po : p);
+            }
+        }
+        if ((uint32_t)t < M) {
+            mk[t] = k;
+            mp[t] = p;
+        }
+        return;
+    }
     uint32_t n2 = 1;
     while (n2 < M) n2 <<= 1;
     for (uint32_t q = t; q < n2; q += 1024) {
@@ -2630,7 +2660,7 @@ __global__ __launch_bounds__(TILE) void k_set_radii(uint32_t p0, uint32_t n,
 
 // End of a step: every running job advances (one thread per job).
 __global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
-    if (__atomic_load_n(&P.st->err, __ATOMIC_RELAXED)) return;
+    if (((ConstPtr<Status>)P.st)->err) return;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) {
         P.st->steps_done += 1;
