@@ -796,13 +796,22 @@ __device__ __forceinline__ void wide_scan(const Geo& G, const uint2* __restrict_
             xh = xh > xc + 2 ? xc + 2 : xh;
             const uint32_t row = ((uint32_t)z * (uint32_t)ny + (uint32_t)y) * (uint32_t)nx;
             uint32_t a1 = 0xFFFFFFFFu, e1 = 0u, a2 = 0xFFFFFFFFu, e2 = 0u;
-            for (int x = xl; x <= xh; ++x) {
-                // a window of at most 5 cells on a periodic axis of at least
-                // 5 wraps at most once; its wrapped cells form the second range
-                const bool wrapped = x < 0 || x >= nx;
+            // the window's (at most 5) cell bounds are all loaded before any
+            // is merged; a window of at most 5 cells on a periodic axis of at
+            // least 5 wraps at most once, and its wrapped cells form the
+            // second range
+            uint2 cb[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int x = xc - 2 + k;
                 const int xw = x < 0 ? x + nx : (x >= nx ? x - nx : x);
-                const uint2 c = cells[row + (uint32_t)xw];
-                if (wrapped) merge_range(c, a2, e2); else merge_range(c, a1, e1);
+                const bool in = x >= xl && x <= xh && xw >= 0 && xw < nx;
+                cb[k] = in ? cells[row + (uint32_t)xw] : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int x = xc - 2 + k;
+                if (x < 0 || x >= nx) merge_range(cb[k], a2, e2); else merge_range(cb[k], a1, e1);
             }
             if (e1 > a1) { lo1 = a1; n1 = e1 - a1; }
             if (e2 > a2) { lo2 = a2; n2 = e2 - a2; }
