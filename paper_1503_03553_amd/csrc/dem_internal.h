@@ -216,9 +216,13 @@ void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, 
 // Y).  S and perm are the buffers of the next step, not those this step
 // read.  It also empties the cell bounds of the movers' old cells (the force
 // kernel leaves them in place with this sort).
+// It also ends the step for the `njobs` job descriptors P.jobs: each is
+// written, advanced (time, steps, status) or unchanged, to jobs_next, the
+// descriptors the next step reads.
 void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* movers,
                        unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, const State& Y,
-                       const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s);
+                       const Sorted& S, uint32_t* perm, uint2* cells, Job* jobs_next,
+                       uint32_t njobs, hipStream_t s);
 // Sorts (keys, vals) by the low `bits` bits of keys; the result ends in
 // (keys_out, vals_out).  tmp buffers are the ping-pong partners.
 void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
@@ -227,8 +231,9 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
 // After the sort: with `gather` (the radix sort) the permutation (new
 // sorted position -> position in Y) and the sorted position records
 // gathered from Y into the next step's buffers S and perm; the cell bounds;
-// then the step ends for the `njobs` job descriptors (time, steps, status).
-void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, bool gather,
+// the step's count.  With `gather` the step then ends for the `njobs` job
+// descriptors P.jobs, written to jobs_next (the merge sort does this itself).
+void launch_reorder(const PoolView& P, Job* jobs_next, uint32_t njobs, bool gather,
                     const uint32_t* keys_s, const uint32_t* vals_s, const State& Y,
                     const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s);
 // Replaces the radii of the positions [p0, p0 + n) of one job (rnew in

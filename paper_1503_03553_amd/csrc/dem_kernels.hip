@@ -2181,6 +2181,33 @@ __global__ __launch_bounds__(TILE) void k_clear_cells(PoolView P, const Job* __r
     if (c[lin].x == i) c[lin] = make_uint2(0, 0);
 }
 
+// End of a step for one job: time, step count and shear offsets advance; a
+// job that produced a non-finite state is marked failed.
+// The descriptors are double-buffered: the kernels of a step read `in`, and
+// the end of the step writes every descriptor, advanced or copied, to `out`,
+// which the next step reads.  So the end of a step can run before the
+// step's last kernels (which still read `in`), and a step abandoned at any
+// point leaves the descriptors it started from intact.
+__device__ inline void tick_job(const Job* __restrict__ in, Job* __restrict__ out,
+                                const uint32_t* __restrict__ job_fail, uint32_t k) {
+    Job J = in[k];
+    if (J.status == JOB_ACTIVE) {
+        if (job_fail[k]) {
+            J.status = JOB_FAILED;
+        } else {
+            const double t = J.t + J.g.dt;
+            J.t = t;
+            if (J.g.le) {
+                J.g.le_shift = fmod(J.g.le_dv * t, J.g.L[0]);
+                J.g.le_shift_next = fmod(J.g.le_dv * (t + J.g.dt), J.g.L[0]);
+            }
+            J.steps_done += 1;
+            if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
+        }
+    }
+    out[k] = J;
+}
+
 // ------------------------------------------------------------ merge sort
 // Between two steps few particles change cell.  The others keep their key
 // and are still in key order, so the stable order of the step is the merge
@@ -2192,7 +2219,11 @@ __global__ __launch_bounds__(TILE) void k_clear_cells(PoolView P, const Job* __r
 // position (bitonic networks in LDS); k_place then places every particle.
 __global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ movers,
                                                    unsigned long long* __restrict__ mk,
-                                                   uint32_t* __restrict__ mp, const Status* st) {
+                                                   uint32_t* __restrict__ mp, const Status* st,
+                                                   const Job* __restrict__ jin,
+                                                   Job* __restrict__ jout,
+                                                   const uint32_t* __restrict__ job_fail,
+                                                   uint32_t njobs) {
     // both orders at once: (key, position) in s_k, position in s_p, each
     // compare-exchange stage of the bitonic network applied to both arrays
     __shared__ unsigned long long s_k[MAX_MOVERS];
@@ -2203,6 +2234,8 @@ __global__ __launch_bounds__(1024) void k_mov_sort(const uint2* __restrict__ mov
     const uint32_t M = ((ConstPtr<Status>)st)->movers;
     const uint2 e0 = movers[t];  // t < 1024 <= MAX_MOVERS
     if (skip_if_error(st, &s_flag)) return;
+    // the end of the step for every job (its force kernel has run)
+    for (uint32_t k = (uint32_t)t; k < njobs; k += 1024) tick_job(jin, jout, job_fail, k);
     if (M == 0) return;
     if (M <= 64) {
         // few movers (the common case): the first wavefront sorts both
@@ -2534,24 +2567,6 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 }
 
 // ------------------------------------------------------------------ reorder
-// End of a step for one job: time, step count and shear offsets advance; a
-// job that produced a non-finite state is marked failed.
-__device__ inline void tick_job(const PoolView& P, Job* jobs, uint32_t k) {
-    Job& J = jobs[k];
-    if (J.status != JOB_ACTIVE) return;
-    if (P.job_fail[k]) {
-        J.status = JOB_FAILED;
-        return;
-    }
-    const double t = J.t + J.g.dt;
-    J.t = t;
-    if (J.g.le) {
-        J.g.le_shift = fmod(J.g.le_dv * t, J.g.L[0]);
-        J.g.le_shift_next = fmod(J.g.le_dv * (t + J.g.dt), J.g.L[0]);
-    }
-    J.steps_done += 1;
-    if (J.steps_left != 0xFFFFFFFFu && --J.steps_left == 0) J.status = JOB_DONE;
-}
 
 // One workgroup per tile.  The new sorted order: with GATHER (after the
 // radix sort) the permutation into the buffer just written, the position
@@ -2585,6 +2600,12 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     const uint32_t key_lo = i > 0 ? keys_s[i - 1] : 0u;
     const uint32_t key_hi = i + 1 < P.ns ? keys_s[i + 1] : 0u;
     if (skip_if_error(P.st, &s_flag)) return;
+    if (tile == 0 && threadIdx.x == 0) {
+        // the step completes: it counts, and the next one's cell changes
+        // start from zero
+        P.st->steps_done += 1;
+        P.st->movers = 0;
+    }
     uint32_t jb;
     const Job* Jp = tile_job(jobs, P, tile, jb);
     if (!Jp) {
@@ -2668,14 +2689,11 @@ __global__ __launch_bounds__(TILE) void k_set_radii(uint32_t p0, uint32_t n,
 }
 
 // End of a step: every running job advances (one thread per job).
-__global__ void k_tick(PoolView P, Job* __restrict__ jobs, uint32_t njobs) {
+__global__ void k_tick(PoolView P, const Job* __restrict__ in, Job* __restrict__ out,
+                       uint32_t njobs) {
     if (((ConstPtr<Status>)P.st)->err) return;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0) {
-        P.st->steps_done += 1;
-        P.st->movers = 0;
-    }
-    if (k < njobs) tick_job(P, jobs, k);
+    if (k < njobs) tick_job(in, out, P.job_fail, k);
 }
 
 // ------------------------------------------------------------------ launch
@@ -2840,9 +2858,11 @@ void launch_detect_half(const PoolView& P, int kmax, const Sorted& S, const uint
 
 void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* movers,
                        unsigned long long* mk, uint32_t* mp, uint32_t* keys_s, const State& Y,
-                       const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s) {
+                       const Sorted& S, uint32_t* perm, uint2* cells, Job* jobs_next,
+                       uint32_t njobs, hipStream_t s) {
+    hipLaunchKernelGGL(k_mov_sort, dim3(1), dim3(1024), 0, s, movers, mk, mp, P.st, P.jobs,
+                       jobs_next, P.job_fail, njobs);
     if (P.ntiles == 0) return;
-    hipLaunchKernelGGL(k_mov_sort, dim3(1), dim3(1024), 0, s, movers, mk, mp, P.st);
     hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, oldkeys, mk, mp,
                        keys_s, Y.xr, S.xr, S.xf, perm, cells);
 }
@@ -2890,7 +2910,7 @@ void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipS
                            cells);
 }
 
-void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, bool gather,
+void launch_reorder(const PoolView& P, Job* jobs_next, uint32_t njobs, bool gather,
                     const uint32_t* keys_s, const uint32_t* vals_s, const State& Y,
                     const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s) {
     if (P.ntiles > 0) {
@@ -2901,8 +2921,12 @@ void launch_reorder(const PoolView& P, Job* jobs, uint32_t njobs, bool gather,
             hipLaunchKernelGGL(k_reorder<false>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
                                keys_s, vals_s, Y.xr, S.xr, S.xf, perm, cells);
     }
-    const uint32_t nb = (njobs + 255) / 256;
-    hipLaunchKernelGGL(k_tick, dim3(nb ? nb : 1), dim3(256), 0, s, P, jobs, njobs);
+    // after the merge sort the step has ended already (k_mov_sort)
+    if (gather) {
+        const uint32_t nb = (njobs + 255) / 256;
+        hipLaunchKernelGGL(k_tick, dim3(nb ? nb : 1), dim3(256), 0, s, P, P.jobs, jobs_next,
+                           njobs);
+    }
 }
 
 

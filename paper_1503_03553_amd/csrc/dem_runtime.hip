@@ -154,7 +154,10 @@ struct dem_pool {
     uint2* adj = nullptr;                 //   and adjacency lists (adj_slots entries each)
     int adj_slots = 0;
     MatTable* mats = nullptr;
-    Job* jobs_d = nullptr;
+    // job descriptors, two buffers: a step reads jobs_d[o] (o: the state
+    // buffer it reads) and its end writes jobs_d[w]; jobs_d[cur] holds those
+    // the next step reads
+    Job* jobs_d[2] = {nullptr, nullptr};
     dem_wall* walls_d = nullptr;          // DEM_MAX_WALLS extra walls per job slot
     uint32_t* job_fail = nullptr;
     uint32_t* tile_job = nullptr;
@@ -484,7 +487,7 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     if (flags & DEM_FLAG_ACTION_REACTION) b += np * slots * 6 * (fp64 ? 8 : 4);  // pair forces
     if (half_search(flags)) b += np * (4 + 8 * 8);  // adjacency lists (8 slots; more in a clump)
     b += sort_hist_words((uint32_t)np) * 4 + 256 * 4;
-    b += max_jobs * (sizeof(MatTable) + sizeof(Job) + 4 + DEM_MAX_WALLS * sizeof(dem_wall));
+    b += max_jobs * (sizeof(MatTable) + 2 * sizeof(Job) + 4 + DEM_MAX_WALLS * sizeof(dem_wall));
     b += max_tiles * (8 + sizeof(TileStats)) + sizeof(Status);
     b += 52 * ARENA_ALIGN;  // alignment of each buffer in an arena
     return b;
@@ -579,7 +582,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc_t(s, MAX_MOVERS, &s->mp));
     ALLOC_OR_FAIL(dalloc(s, 6 * np * (fp64 ? 8 : 4), &s->fo));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->mats));
-    ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->jobs_d));
+    ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->jobs_d[0]));
+    ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->jobs_d[1]));
     ALLOC_OR_FAIL(dalloc_t(s, (size_t)max_jobs * DEM_MAX_WALLS, &s->walls_d));
     ALLOC_OR_FAIL(dalloc_t(s, max_jobs, &s->job_fail));
     ALLOC_OR_FAIL(dalloc_t(s, mt, &s->tile_job));
@@ -604,7 +608,8 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     if (e == hipSuccess) e = hipMemset(s->rows[1], 0, np * sizeof(uint2));
     if (e == hipSuccess) e = hipMemset(s->fo, 0, 6 * np * (fp64 ? 8 : 4));
     if (e == hipSuccess && s->deg) e = hipMemset(s->deg, 0, np * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(s->jobs_d, 0, max_jobs * sizeof(Job));
+    if (e == hipSuccess) e = hipMemset(s->jobs_d[0], 0, max_jobs * sizeof(Job));
+    if (e == hipSuccess) e = hipMemset(s->jobs_d[1], 0, max_jobs * sizeof(Job));
     if (e == hipSuccess) e = hipMemset(s->job_fail, 0, max_jobs * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(s->S[0].mat, 0, np);
     if (e == hipSuccess) e = hipMemset(s->S[1].mat, 0, np);
@@ -838,7 +843,7 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     jd.xw = s->walls_d + (size_t)slot * DEM_MAX_WALLS;
     if (!J.walls.empty()) up(s->walls_d + (size_t)slot * DEM_MAX_WALLS, J.walls.data(),
                              J.walls.size() * sizeof(dem_wall));
-    up(s->jobs_d + slot, &jd, sizeof(Job));
+    up(s->jobs_d[s->cur] + slot, &jd, sizeof(Job));
     const uint32_t zero = 0;
     up(s->job_fail + slot, &zero, sizeof(zero));
     return r;
@@ -989,7 +994,7 @@ dem_status remove_job(dem_pool* s, int slot) {
 // ------------------------------------------------------------ step pipeline
 PoolView view(dem_pool* s) {
     PoolView P;
-    P.jobs = s->jobs_d;
+    P.jobs = s->jobs_d[s->cur];
     P.job_fail = s->job_fail;
     P.tile_job = s->tile_job;
     P.tile_key = s->tile_key;
@@ -1012,7 +1017,9 @@ void prof_record(dem_pool* s, size_t slot, int ev) {
 dem_status enqueue_step(dem_pool* s, int o) {
     const int w = 1 - o;
     PoolView P = view(s);
-    // the step reads the state of buffer o and writes buffer w
+    P.jobs = s->jobs_d[o];
+    // the step reads the state and job descriptors of buffer o and writes
+    // those of buffer w
     State X = s->S[o], Y = s->S[w];
     if (!s->any_multi_mat) X.mat = Y.mat = nullptr;
     size_t slot = 0;
@@ -1068,7 +1075,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
     uint32_t *ko, *vo;
     if (merge) {
         launch_merge_sort(P, s->oldkeys, s->movers, s->mk, s->mp, s->keys_t, Y, s->srt[w],
-                          s->prev[w], s->cells, s->stream);
+                          s->prev[w], s->cells, s->jobs_d[w], s->max_jobs, s->stream);
         ko = s->keys_t;
         vo = s->vals_t;
     } else {
@@ -1077,7 +1084,7 @@ dem_status enqueue_step(dem_pool* s, int o) {
                           s->st, s->stream);
     }
     prof_record(s, slot, 3);
-    launch_reorder(P, s->jobs_d, s->max_jobs, !merge, ko, vo, Y, s->srt[w], s->prev[w], s->cells,
+    launch_reorder(P, s->jobs_d[w], s->max_jobs, !merge, ko, vo, Y, s->srt[w], s->prev[w], s->cells,
                    s->stream);
     prof_record(s, slot, 4);
     HIPCHK(hipGetLastError());
@@ -1203,7 +1210,9 @@ dem_status sync_impl(dem_pool* s) {
         HIPCHK(hipMemcpy(s->st, &z, sizeof(Status), hipMemcpyHostToDevice));
         // the abandoned step may have emptied cell bounds (the force kernel
         // does so as it runs): restore those of the order it started from
-        launch_rebuild_cells(view(s), s->srt[o], s->cells, s->stream);
+        PoolView Pv = view(s);
+        Pv.jobs = s->jobs_d[o];
+        launch_rebuild_cells(Pv, s->srt[o], s->cells, s->stream);
         HIPCHK(hipGetLastError());
         s->prof_used = 0;
         const size_t k = s->pending.size();
@@ -1215,7 +1224,7 @@ dem_status sync_impl(dem_pool* s) {
 }
 
 dem_status read_job(dem_pool* s, int slot, Job& jd) {
-    HIPCHK(hipMemcpy(&jd, s->jobs_d + slot, sizeof(Job), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&jd, s->jobs_d[s->cur] + slot, sizeof(Job), hipMemcpyDeviceToHost));
     return DEM_OK;
 }
 
@@ -1427,7 +1436,7 @@ dem_status set_state_impl(dem_pool* s, int slot, const double* x, const double* 
     r = upload_job(s, slot, pl, jd.t, jd.steps_left);
     if (r != DEM_OK) return r;
     // keep the device time, step count and status
-    r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
+    r = upload(s, s->jobs_d[s->cur] + slot, &jd, sizeof(Job));
     if (r != DEM_OK) return r;
     HIPCHK(hipStreamSynchronize(s->stream));
     s->staging.clear();
@@ -1477,7 +1486,7 @@ dem_status set_radii_impl(dem_pool* s, int slot, const float* radius) {
     jd.g.nbig = J.geo.nbig;
     // the radii travel through the sort's scratch keys (unused between steps)
     r = upload(s, s->keys_t, radius, n * sizeof(float));
-    if (r == DEM_OK) r = upload(s, s->jobs_d + slot, &jd, sizeof(Job));
+    if (r == DEM_OK) r = upload(s, s->jobs_d[s->cur] + slot, &jd, sizeof(Job));
     if (r != DEM_OK) return r;
     const uint32_t p0 = J.tile0 * TILE;
     launch_set_radii(p0, (uint32_t)n, (const float*)s->keys_t, s->S[s->cur], s->srt[s->cur],
@@ -1936,7 +1945,7 @@ dem_status dem_pool_poll(dem_pool* s, uint64_t* done, uint32_t cap, uint32_t* n_
     dem_status r = sync_impl(s);
     if (r != DEM_OK) return r;
     std::vector<Job> jd(s->max_jobs);
-    HIPCHK(hipMemcpy(jd.data(), s->jobs_d, s->max_jobs * sizeof(Job), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(jd.data(), s->jobs_d[s->cur], s->max_jobs * sizeof(Job), hipMemcpyDeviceToHost));
     uint32_t k = 0;
     for (uint32_t q = 0; q < s->max_jobs && k < cap; ++q) {
         HostJob& J = s->jobs[q];
