@@ -53,10 +53,26 @@ _P = ctypes.POINTER(Params)
 _vp = ctypes.c_void_p
 
 
+def build_sanitized() -> str:
+    """The same source built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (for tests that run the oracle under them: load it with DEM_ORACLE_SO set to
+    the returned path, libasan preloaded)."""
+    src = os.path.join(_HERE, "dem_oracle.c")
+    so = os.path.join(_HERE, "liboracle_san.so")
+    if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+        tmp = so + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O1", "-g", "-fsanitize=address,undefined",
+                               "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                               "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-shared",
+                               "-fPIC", "-o", tmp, src, "-lm"])
+        os.replace(tmp, so)
+    return so
+
+
 def lib():
     global _LIB
     if _LIB is None:
-        L = ctypes.CDLL(build())
+        L = ctypes.CDLL(os.environ.get("DEM_ORACLE_SO") or build())
         L.orc_alpha.restype = ctypes.c_double
         L.orc_alpha.argtypes = [ctypes.c_double]
         L.orc_mass.restype = ctypes.c_double
