@@ -117,9 +117,13 @@ struct State {
 // The records the contact search reads, in the sorted order of the step:
 // the FP64 position record and its compact FP32 form ((x, y, z) - lo and the
 // radius; NaN coordinates beyond 3 box lengths).
+// The sorted order of a step: the contact search's FP32 records in sorted
+// order, and the permutation into the state buffer it is paired with, whose
+// FP64 records (position, radius, id) serve every sorted position through it.
 struct Sorted {
-    double4* xr;
-    float4* xf;
+    const double4* xr;   // the paired state buffer's records (read through perm)
+    uint32_t* perm;      // sorted position -> position in that state buffer
+    float4* xf;          // FP32 records (x - lo, y - lo, z - lo, r), sorted order
 };
 
 __host__ __device__ inline uint64_t pack_meta(float r, uint32_t pid) {
@@ -159,7 +163,8 @@ void launch_detect(const PoolView& P, int kmax, const Sorted& S, const uint2* ce
 // index of every position (`keys`, `vals`), and the kernel empties the
 // bounds of the old cells.
 // X: the state the step reads (through perm), Y: the state it writes (in
-// sorted order); S: the sorted positions.
+// sorted order); S: the sorted order (FP32 records, and X's records through
+// its permutation).
 void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X, const State& Y,
                   const uint2* rows, const uint32_t* col_j, const uint2* rows_old,
                   const uint32_t* perm,
@@ -211,10 +216,9 @@ void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, 
                        uint64_t cap, uint2* cells, uint32_t* keys, uint32_t* vals, void* fo,
                        uint32_t* oldkeys, uint2* movers, hipStream_t s);
 // The merge sort: the sorted keys (keys_s) and, placed directly at their
-// new positions, the sorted position records S gathered from the state Y
-// just written and the permutation perm (new sorted position -> position in
-// Y).  S and perm are the buffers of the next step, not those this step
-// read.  It also empties the cell bounds of the movers' old cells (the force
+// new positions, the FP32 records S.xf of the state Y just written and the
+// permutation perm (new sorted position -> position in Y).  S and perm are
+// the buffers of the next step, not those this step read.  It also empties the cell bounds of the movers' old cells (the force
 // kernel leaves them in place with this sort).
 // It also ends the step for the `njobs` job descriptors P.jobs: each is
 // written, advanced (time, steps, status) or unchanged, to jobs_next, the
@@ -229,19 +233,19 @@ void launch_radix_sort(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint3
                        uint32_t n, int bits, uint32_t* tile_hist, uint32_t* digit_tot,
                        uint32_t** keys_out, uint32_t** vals_out, const Status* st, hipStream_t s);
 // After the sort: with `gather` (the radix sort) the permutation (new
-// sorted position -> position in Y) and the sorted position records
-// gathered from Y into the next step's buffers S and perm; the cell bounds;
+// sorted position -> position in Y) and the FP32 records gathered from Y
+// into the next step's buffers S.xf and perm; the cell bounds;
 // the step's count.  With `gather` the step then ends for the `njobs` job
 // descriptors P.jobs, written to jobs_next (the merge sort does this itself).
 void launch_reorder(const PoolView& P, Job* jobs_next, uint32_t njobs, bool gather,
                     const uint32_t* keys_s, const uint32_t* vals_s, const State& Y,
                     const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s);
 // Replaces the radii of the positions [p0, p0 + n) of one job (rnew in
-// particle-id order) in the state X the next step reads and its sorted
-// records S.
+// particle-id order) in the state X the next step reads and in the FP32
+// records of its sorted order S.
 void launch_set_radii(uint32_t p0, uint32_t n, const float* rnew, const State& X, const Sorted& S,
                       hipStream_t s);
-// Rewrites the cell bounds of the current order from the sorted positions.
+// Rewrites the cell bounds of the current order from its positions (S).
 void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipStream_t s);
 size_t sort_hist_words(uint32_t n);
 // Shear offset of the image along x at time t: D(t) = (shear_rate L_y t) mod L_x.

@@ -439,13 +439,29 @@ struct PreFilter {
     }
 };
 
+// The position record (FP64 position, radius and id) of a sorted position:
+// the record in the state buffer the step reads, through the permutation.
+// The sorted order keeps only the contact search's FP32 records; the FP64
+// records are read where they are.
+// A permutation entry is read for any position a lane may load, also ghost
+// slots and free tiles, whose entries no step writes: an entry outside the
+// arrays is taken as the position itself, so every load stays in bounds.
+struct SortedPos {
+    const double4* __restrict__ xr;   // the state buffer the step reads
+    const uint32_t* __restrict__ perm;  // sorted position -> position in it
+    uint32_t n;                         // positions in both arrays
+    __device__ __forceinline__ double4 operator[](uint32_t j) const {
+        const uint32_t q = perm[j];
+        return xr[q < n ? q : j];
+    }
+};
+
 // Exact FP64 re-walk of a lane's `nw` candidate ranges (win(k) gives range
 // k) into its column of s_j; returns the number of contacts found.
 template <int KMAX, bool PER, typename Win>
 __device__ __forceinline__ uint32_t rewalk_exact(const PoolView& P, const Geo& G, const double4& a,
                                                  double ri, uint32_t i, int t, uint32_t nw,
-                                                 Win win, const double4* __restrict__ xr,
-                                                 uint32_t* s_j) {
+                                                 Win win, SortedPos xr, uint32_t* s_j) {
     // more survivors than the row holds (a particle far from the box, whose
     // FP32 record passes every comparison, or a tight clump): walk the
     // candidates again with the exact FP64 test, so only more real contacts
@@ -483,8 +499,7 @@ __device__ __forceinline__ uint32_t rewalk_exact(const PoolView& P, const Geo& G
 template <int KMAX, bool PER, typename Win>
 __device__ __forceinline__ uint32_t detect_row(const PoolView& P, const Geo& G, const double4& a,
                                                double ri, uint32_t i, int t, uint32_t sc,
-                                               uint32_t nw, Win win,
-                                               const double4* __restrict__ xr, uint32_t* s_j,
+                                               uint32_t nw, Win win, SortedPos xr, uint32_t* s_j,
                                                uint2* pcol, int pstride,
                                                const dem_wall* __restrict__ xw, uint32_t nxw) {
     auto pid_at = [&](int k) -> uint32_t& { return pcol[k * pstride].x; };
@@ -614,7 +629,7 @@ __device__ __forceinline__ void write_rows(const PoolView& P, uint32_t tile, int
 // rows into its own region of the contact list.
 template <int KMAX, bool PER>
 __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restrict__ jobs,
-                                                  const double4* __restrict__ xr,
+                                                  SortedPos xr,
                                                   const float4* __restrict__ xf,
                                                   const uint2* __restrict__ cells,
                                                   uint2* __restrict__ rows,
@@ -732,7 +747,7 @@ __global__ __launch_bounds__(DTILE) void k_detect(PoolView P, const Job* __restr
 // stride DTILE).
 template <bool PER, typename Append>
 __device__ __forceinline__ void wide_scan(const Geo& G, const uint2* __restrict__ cells,
-                                          const double4* __restrict__ xr, uint32_t nsz,
+                                          SortedPos xr, uint32_t nsz,
                                           const double4& b, uint32_t bi, int lane,
                                           uint32_t* s_w, Append append) {
     const int nx = G.nc[0], ny = G.nc[1], nz = G.nc[2];
@@ -890,7 +905,7 @@ __device__ __forceinline__ void wide_scan(const Geo& G, const uint2* __restrict_
 // wavefront then runs the wide scan of its own big particles.
 template <int KMAX, bool PER>
 __global__ __launch_bounds__(DTILE) void k_detect_half(PoolView P, const Job* __restrict__ jobs,
-                                                       const double4* __restrict__ xr,
+                                                       SortedPos xr,
                                                        const float4* __restrict__ xf,
                                                        const uint2* __restrict__ cells,
                                                        uint32_t* __restrict__ deg,
@@ -1156,7 +1171,7 @@ template <typename R>
 __device__ __forceinline__ PairTerms<R> pair_terms(
     const Geo& G, const MatTable* __restrict__ mt, uint32_t code, const double4& a,
     const double2& a0, const double2& a1, const double2& a2, int mi,
-    const double4* __restrict__ xr, const double2* __restrict__ vw,
+    const double4* __restrict__ xr_x, const double2* __restrict__ vw,
     const uint8_t* __restrict__ mat, const uint32_t* __restrict__ perm, uint32_t ns,
     const dem_wall* __restrict__ xw) {
     PairTerms<R> p;
@@ -1164,9 +1179,11 @@ __device__ __forceinline__ PairTerms<R> pair_terms(
     const double rid = (double)meta_r(a.w);
     const R mass_i = (R)(mt->mass_pref[mi] * rid * rid * rid);
     if (code < FACE) {
+        // the partner's records, all in the state buffer read, through the
+        // permutation
         const uint32_t j = code;
-        const double4 b = xr[j];
         const uint32_t qj = perm[j];
+        const double4 b = xr_x[qj];
         const double2 b0 = vw[qj], b1 = vw[ns + qj], b2 = vw[2 * (size_t)ns + qj];
         p.mj = mat ? mat[qj] : 0;
         p.pid = meta_pid(b.w);
@@ -1489,7 +1506,7 @@ __device__ __forceinline__ void finish_tile(
 // as above; the lists' counters are reset, also when the step is abandoned.
 template <typename R, int HK = 0>
 __global__ __launch_bounds__(TILE) void k_force(
-    const double4* __restrict__ xr, const double4* __restrict__ xr_x,
+    const double4* __restrict__ xr_x,
     const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
     double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
     const uint2* __restrict__ rows, const uint32_t* __restrict__ col_j,
@@ -1536,13 +1553,13 @@ __global__ __launch_bounds__(TILE) void k_force(
         const uint32_t ip = tile * TILE + t;
         d = deg[ip];
         const uint32_t pq = perm[ip];
-        xi0 = xr[ip];
         if (d) deg[ip] = 0;
         const uint32_t c0 = d <= (uint32_t)HK ? d : 0u;
 #pragma unroll
         for (int m = 0; m < 4; ++m)
             e0[m] = (uint32_t)m < c0 ? adj[(size_t)m * P.ns + ip] : make_uint2(0u, 0u);
         const uint32_t q = pq < P.ns ? pq : ip;
+        xi0 = xr_x[q];
         v0 = vw[q];
         v1 = vw[P.ns + q];
         v2 = vw[2 * (size_t)P.ns + q];
@@ -1630,11 +1647,11 @@ __global__ __launch_bounds__(TILE) void k_force(
             s_vw[2][t] = v2;
         }
     } else if (i < n) {
-        // own position in sorted order; velocities through the permutation
+        // own records through the permutation
         const uint32_t q = perm[i];
         row = rows[i];
         orow = rows_old[q];
-        s_x[t] = xr[i];
+        s_x[t] = xr_x[q];
         s_vw[0][t] = vw[q];
         s_vw[1][t] = vw[ns + q];
         s_vw[2][t] = vw[2 * (size_t)ns + q];
@@ -1665,8 +1682,8 @@ __global__ __launch_bounds__(TILE) void k_force(
             const double4 a = s_x[o];
             const int mi = s_mat[o];
             const PairTerms<R> p = pair_terms<R>(G, mt, HK ? col_out[g] : col_j[g], a, s_vw[0][o],
-                                                 s_vw[1][o], s_vw[2][o], mi, xr, vw, mat, perm, ns,
-                                                 J.xw);
+                                                 s_vw[1][o], s_vw[2][o], mi, xr_x, vw, mat, perm,
+                                                 ns, J.xw);
             double dtx, dty, dtz;
             matched += history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
                                         dtz) ? 1u : 0u;
@@ -1708,7 +1725,7 @@ __global__ __launch_bounds__(TILE) void k_force(
 // kernel; the per-contact terms and the summation order are the same.
 template <typename R>
 __global__ __launch_bounds__(TILE) void k_force_thread(
-    const double4* __restrict__ xr, const double4* __restrict__ xr_x,
+    const double4* __restrict__ xr_x,
     const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
     double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
     const uint2* __restrict__ rows, const uint32_t* __restrict__ col_j,
@@ -1750,7 +1767,7 @@ __global__ __launch_bounds__(TILE) void k_force_thread(
         const uint32_t q = perm[i];
         const uint2 row = rows[i];
         orow = rows_old[q];
-        a = xr[i];
+        a = xr_x[q];
         a0 = vw[q];
         a1 = vw[ns + q];
         a2 = vw[2 * (size_t)ns + q];
@@ -1760,8 +1777,8 @@ __global__ __launch_bounds__(TILE) void k_force_thread(
         } else {
             for (uint32_t k = row.x; k < row.x + row.y; ++k) {
                 const uint32_t code = col_j[k];
-                const PairTerms<R> p = pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr, vw, mat,
-                                                     perm, ns, J.xw);
+                const PairTerms<R> p = pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr_x, vw,
+                                                     mat, perm, ns, J.xw);
                 double dtx, dty, dtz;
                 matched += history_of<true>(orow, p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
                                             dtz) ? 1u : 0u;
@@ -1800,7 +1817,7 @@ __global__ __launch_bounds__(TILE) void k_force_thread(
 // pair that carried history twice, as both of its directed contacts did.
 template <typename R>
 __global__ __launch_bounds__(TILE) void k_pair_force(
-    const double4* __restrict__ xr, const double2* __restrict__ vw,
+    const double4* __restrict__ xr_x, const double2* __restrict__ vw,
     const uint8_t* __restrict__ mat, const uint2* __restrict__ rows,
     const uint32_t* __restrict__ col_j, const uint2* __restrict__ rows_old,
     const uint32_t* __restrict__ perm, const uint32_t* __restrict__ tab_pid_old,
@@ -1836,7 +1853,7 @@ __global__ __launch_bounds__(TILE) void k_pair_force(
         const uint32_t q = perm[i];
         row = rows[i];
         orow = rows_old[q];
-        s_x[t] = xr[i];
+        s_x[t] = xr_x[q];
         s_vw[0][t] = vw[q];
         s_vw[1][t] = vw[ns + q];
         s_vw[2][t] = vw[2 * (size_t)ns + q];
@@ -1864,7 +1881,7 @@ __global__ __launch_bounds__(TILE) void k_pair_force(
         uint32_t pid = code;
         bool own = true;
         if (code < FACE) {
-            pid = meta_pid(xr[code].w);
+            pid = meta_pid(xr_x[perm[code]].w);
             own = pid > meta_pid(a.w);
         }
         double dtx = 0.0, dty = 0.0, dtz = 0.0;
@@ -1872,7 +1889,7 @@ __global__ __launch_bounds__(TILE) void k_pair_force(
         if (own) {
             const int mi = s_mat[o];
             const PairTerms<R> p = pair_terms<R>(G, mt, code, a, s_vw[0][o], s_vw[1][o],
-                                                 s_vw[2][o], mi, xr, vw, mat, perm, ns, J.xw);
+                                                 s_vw[2][o], mi, xr_x, vw, mat, perm, ns, J.xw);
             if (history_of<true>(s_old[o], p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty, dtz))
                 matched += code < FACE ? 2u : 1u;
             const int pr = mi * MAXMAT + p.mj;
@@ -1916,7 +1933,7 @@ __global__ __launch_bounds__(TILE) void k_pair_force(
 // step as in the force kernel.
 template <typename R>
 __global__ __launch_bounds__(TILE) void k_ar_sum(
-    const double4* __restrict__ xr, const double4* __restrict__ xr_x,
+    const double4* __restrict__ xr_x,
     const double2* __restrict__ vw, const uint8_t* __restrict__ mat,
     double4* __restrict__ xr_b, double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b,
     const uint2* __restrict__ rows, const uint32_t* __restrict__ col_j,
@@ -1952,7 +1969,7 @@ __global__ __launch_bounds__(TILE) void k_ar_sum(
     int mi = 0;
     if (i < n) {
         const uint32_t q = perm[i];
-        a = xr[i];
+        a = xr_x[q];
         a0 = vw[q];
         a1 = vw[ns + q];
         a2 = vw[2 * (size_t)ns + q];
@@ -2003,7 +2020,7 @@ __global__ __launch_bounds__(TILE) void k_ar_sum(
 // afterwards.
 template <typename R, bool PER>
 __global__ __launch_bounds__(TILE) void k_fused(
-    PoolView P, const Job* __restrict__ jobs, const double4* __restrict__ xr,
+    PoolView P, const Job* __restrict__ jobs, SortedPos xr,
     const float4* __restrict__ xf, const double4* __restrict__ xr_x,
     const double2* __restrict__ vw, const uint8_t* __restrict__ mat, double4* __restrict__ xr_b,
     double2* __restrict__ vw_b, uint8_t* __restrict__ mat_b, uint2* __restrict__ rows,
@@ -2061,7 +2078,7 @@ __global__ __launch_bounds__(TILE) void k_fused(
             if (cnt < slots) {
                 const uint64_t g = slab + cnt;
                 const PairTerms<R> p =
-                    pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr, vw, mat, perm, ns, J.xw);
+                    pair_terms<R>(G, mt, code, a, a0, a1, a2, mi, xr_x, vw, mat, perm, ns, J.xw);
                 double dtx, dty, dtz;
                 matched += history_of<false>(orow, p.pid, tab_pid_old, tab_dt_old, cap, dtx, dty,
                                              dtz) ? 1u : 0u;
@@ -2164,7 +2181,7 @@ __global__ __launch_bounds__(TILE) void k_fused(
 // step started from empties that cell's bounds (the reorder writes those of
 // the new order).
 __global__ __launch_bounds__(TILE) void k_clear_cells(PoolView P, const Job* __restrict__ jobs,
-                                                      const double4* __restrict__ xr,
+                                                      SortedPos xr,
                                                       uint2* __restrict__ cells) {
     __shared__ uint32_t s_flag;
     if (skip_if_error(P.st, &s_flag)) return;
@@ -2343,7 +2360,7 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const Job* __restric
                                                 const uint32_t* __restrict__ mp,
                                                 uint32_t* __restrict__ keys_s,
                                                 const double4* __restrict__ xr_y,
-                                                double4* __restrict__ xs, float4* __restrict__ xf,
+                                                float4* __restrict__ xf,
                                                 uint32_t* __restrict__ perm,
                                                 uint2* __restrict__ cells) {
     __shared__ unsigned long long s_mk[LDS_MOVERS];
@@ -2362,11 +2379,10 @@ __global__ __launch_bounds__(TILE) void k_place(PoolView P, const Job* __restric
     if (skip_if_error(P.st, &s_flag)) return;
     auto key_of = [](uint32_t k, uint32_t p) { return ((unsigned long long)k << 32) | p; };
     // the new order's sorted key, and for a particle of a running job its
-    // position record, FP32 record and source position, at `dest`
+    // FP32 record and source position, at `dest`
     auto emit = [&](uint32_t dest, uint32_t key, uint32_t src, const double4& q, const Job* J) {
         keys_s[dest] = key;
         if (J) {
-            xs[dest] = q;
             xf[dest] = far_record(J->g, q);
             perm[dest] = src;
         }
@@ -2580,7 +2596,7 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
                                                   const uint32_t* __restrict__ keys_s,
                                                   const uint32_t* __restrict__ vals_s,
                                                   const double4* __restrict__ xr_y,
-                                                  double4* __restrict__ xs, float4* __restrict__ xf,
+                                                  float4* __restrict__ xf,
                                                   uint32_t* __restrict__ perm,
                                                   uint2* __restrict__ cells) {
     __shared__ uint32_t s_flag;
@@ -2626,7 +2642,6 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     // a source index is a position by construction; checked (above) so that
     // a sort defect can never read outside the arrays
     if (GATHER) {
-        xs[i] = p;
         xf[i] = far_record(G, p);
         perm[i] = src;
     }
@@ -2635,11 +2650,11 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
     if (i == end - 1 || key_hi != key) cells[lin].y = i + 1;
 }
 
-// Cell bounds of the current sorted order, from the sorted positions: after
+// Cell bounds of the current sorted order, from its positions: after
 // a step that was abandoned once the force kernel had started (it empties the
 // bounds of the cells it leaves), before that step is redone.
 __global__ __launch_bounds__(TILE) void k_rebuild_cells(PoolView P, const Job* __restrict__ jobs,
-                                                        const double4* __restrict__ xs,
+                                                        SortedPos xs,
                                                         uint2* __restrict__ cells) {
     const uint32_t tile = blockIdx.x;
     uint32_t jb;
@@ -2667,25 +2682,30 @@ __global__ __launch_bounds__(TILE) void k_rebuild_cells(PoolView P, const Job* _
 __global__ __launch_bounds__(TILE) void k_set_radii(uint32_t p0, uint32_t n,
                                                     const float* __restrict__ rnew,
                                                     double4* __restrict__ xr,
-                                                    double4* __restrict__ xs,
+                                                    const uint32_t* __restrict__ perm,
                                                     float4* __restrict__ xf) {
     const uint32_t q = blockIdx.x * TILE + threadIdx.x;
     if (q >= n) return;
     const uint32_t i = p0 + q;
-    auto with_r = [&](double w) {
-        const uint32_t pid = meta_pid(w);
-        const float r = pid < n ? rnew[pid] : meta_r(w);
-        return __longlong_as_double((long long)pack_meta(r, pid));
-    };
+    auto r_of = [&](double w) { return meta_pid(w) < n ? rnew[meta_pid(w)] : meta_r(w); };
+    // the sorted record at i: its particle id, which this kernel leaves as
+    // it is, is read through the permutation before any record changes
+    const uint32_t s = perm[i];
+    const float rs = r_of(xr[s < p0 + n && s >= p0 ? s : i].w);
     double4 a = xr[i];
-    a.w = with_r(a.w);
+    a.w = __longlong_as_double((long long)pack_meta(r_of(a.w), meta_pid(a.w)));
     xr[i] = a;
-    double4 b = xs[i];
-    b.w = with_r(b.w);
-    xs[i] = b;
     float4 f = xf[i];
-    f.w = meta_r(b.w);
+    f.w = rs;
     xf[i] = f;
+}
+
+// The step's count and the reset of its cell changes when no tile is in use
+// (the bounds kernel does both otherwise).
+__global__ void k_step_count(PoolView P) {
+    if (((ConstPtr<Status>)P.st)->err) return;
+    P.st->steps_done += 1;
+    P.st->movers = 0;
 }
 
 // End of a step: every running job advances (one thread per job).
@@ -2713,7 +2733,8 @@ void launch_detect(const PoolView& P, int kmax, const Sorted& S, const uint2* ce
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
 #define DEM_DETECT(K, PER)                                                                        \
-    hipLaunchKernelGGL((k_detect<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs, S.xr, S.xf,   \
+    hipLaunchKernelGGL((k_detect<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs,               \
+                       SortedPos{S.xr, S.perm, P.ns}, S.xf,                                            \
                        cells, rows, col_j, slots)
     const bool per = P.any_periodic;
     if (kmax <= 8) {
@@ -2735,12 +2756,12 @@ void launch_force(const PoolView& P, bool fp64, const Sorted& S, const State& X,
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
     if (fp64)
-        hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat,
+        hipLaunchKernelGGL(k_force<double>, dim3(nb), dim3(TILE), 0, s, X.xr, X.vw, X.mat,
                            Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo, P, P.jobs,
                            oldkeys, movers, nullptr, nullptr, nullptr, nullptr, 0u);
     else
-        hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat,
+        hipLaunchKernelGGL(k_force<float>, dim3(nb), dim3(TILE), 0, s, X.xr, X.vw, X.mat,
                            Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old, tab_dt_old,
                            tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo, P, P.jobs,
                            oldkeys, movers, nullptr, nullptr, nullptr, nullptr, 0u);
@@ -2756,7 +2777,7 @@ void launch_force_half(const PoolView& P, bool fp64, int kmax, const Sorted& S, 
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
 #define DEM_FORCE_HALF(R, K)                                                                      \
-    hipLaunchKernelGGL((k_force<R, K>), dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat, Y.xr, \
+    hipLaunchKernelGGL((k_force<R, K>), dim3(nb), dim3(TILE), 0, s, X.xr, X.vw, X.mat, Y.xr,       \
                        Y.vw, Y.mat, nullptr, nullptr, rows_old, perm, tab_pid_old, tab_dt_old,    \
                        tab_pid_new, tab_dt_new, cap, cells, keys, vals, (R*)fo, P, P.jobs,        \
                        oldkeys, movers, deg, adj, rows, col_j, slots)
@@ -2780,7 +2801,8 @@ void launch_fused(const PoolView& P, bool fp64, const Sorted& S, const State& X,
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
 #define DEM_FUSED(R, PER)                                                                          \
-    hipLaunchKernelGGL((k_fused<R, PER>), dim3(nb), dim3(TILE), 0, s, P, P.jobs, S.xr, S.xf, X.xr, \
+    hipLaunchKernelGGL((k_fused<R, PER>), dim3(nb), dim3(TILE), 0, s, P, P.jobs,                 \
+                       SortedPos{S.xr, S.perm, P.ns}, S.xf, X.xr,                                      \
                        X.vw, X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,  \
                        tab_dt_old, tab_pid_new, tab_dt_new, cap, slots, cells, keys, vals,        \
                        (R*)fo, oldkeys, movers)
@@ -2791,7 +2813,8 @@ void launch_fused(const PoolView& P, bool fp64, const Sorted& S, const State& X,
         if (per) DEM_FUSED(float, true); else DEM_FUSED(float, false);
     }
 #undef DEM_FUSED
-    hipLaunchKernelGGL(k_clear_cells, dim3(nb), dim3(TILE), 0, s, P, P.jobs, S.xr, cells);
+    hipLaunchKernelGGL(k_clear_cells, dim3(nb), dim3(TILE), 0, s, P, P.jobs,
+                       SortedPos{S.xr, S.perm, P.ns}, cells);
 }
 
 void launch_action_reaction(const PoolView& P, bool fp64, const Sorted& S, const State& X,
@@ -2804,10 +2827,10 @@ void launch_action_reaction(const PoolView& P, bool fp64, const Sorted& S, const
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
 #define DEM_AR(R)                                                                                  \
-    hipLaunchKernelGGL(k_pair_force<R>, dim3(nb), dim3(TILE), 0, s, S.xr, X.vw, X.mat, rows,      \
+    hipLaunchKernelGGL(k_pair_force<R>, dim3(nb), dim3(TILE), 0, s, X.xr, X.vw, X.mat, rows,      \
                        col_j, rows_old, perm, tab_pid_old, tab_dt_old, tab_pid_new, tab_dt_new,   \
                        cap, (R*)pf, P, P.jobs);                                                   \
-    hipLaunchKernelGGL(k_ar_sum<R>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw, X.mat, Y.xr,    \
+    hipLaunchKernelGGL(k_ar_sum<R>, dim3(nb), dim3(TILE), 0, s, X.xr, X.vw, X.mat, Y.xr,          \
                        Y.vw, Y.mat, rows, col_j, perm, tab_pid_new, (const R*)pf, cap, cells,     \
                        keys, vals, (R*)fo, P, P.jobs, oldkeys, movers)
     if (fp64) {
@@ -2827,12 +2850,12 @@ void launch_force_thread(const PoolView& P, bool fp64, const Sorted& S, const St
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
     if (fp64)
-        hipLaunchKernelGGL(k_force_thread<double>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw,
+        hipLaunchKernelGGL(k_force_thread<double>, dim3(nb), dim3(TILE), 0, s, X.xr, X.vw,
                            X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,
                            tab_dt_old, tab_pid_new, tab_dt_new, cap, cells, keys, vals, (double*)fo,
                            P, P.jobs, oldkeys, movers);
     else
-        hipLaunchKernelGGL(k_force_thread<float>, dim3(nb), dim3(TILE), 0, s, S.xr, X.xr, X.vw,
+        hipLaunchKernelGGL(k_force_thread<float>, dim3(nb), dim3(TILE), 0, s, X.xr, X.vw,
                            X.mat, Y.xr, Y.vw, Y.mat, rows, col_j, rows_old, perm, tab_pid_old,
                            tab_dt_old, tab_pid_new, tab_dt_new, cap, cells, keys, vals, (float*)fo,
                            P, P.jobs, oldkeys, movers);
@@ -2843,8 +2866,8 @@ void launch_detect_half(const PoolView& P, int kmax, const Sorted& S, const uint
     if (P.ntiles == 0) return;
     const uint32_t nb = P.ntiles;
 #define DEM_HALF(K, PER)                                                                           \
-    hipLaunchKernelGGL((k_detect_half<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs, S.xr,    \
-                       S.xf, cells, deg, adj)
+    hipLaunchKernelGGL((k_detect_half<K, PER>), dim3(nb), dim3(DTILE), 0, s, P, P.jobs,          \
+                       SortedPos{S.xr, S.perm, P.ns}, S.xf, cells, deg, adj)
     const bool per = P.any_periodic;
     if (kmax <= 8) {
         if (per) { DEM_HALF(8, true); } else { DEM_HALF(8, false); }
@@ -2864,7 +2887,7 @@ void launch_merge_sort(const PoolView& P, const uint32_t* oldkeys, const uint2* 
                        jobs_next, P.job_fail, njobs);
     if (P.ntiles == 0) return;
     hipLaunchKernelGGL(k_place, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, oldkeys, mk, mp,
-                       keys_s, Y.xr, S.xr, S.xf, perm, cells);
+                       keys_s, Y.xr, S.xf, perm, cells);
 }
 
 size_t sort_hist_words(uint32_t n) {
@@ -2901,25 +2924,27 @@ void launch_set_radii(uint32_t p0, uint32_t n, const float* rnew, const State& X
                       hipStream_t s) {
     if (n > 0)
         hipLaunchKernelGGL(k_set_radii, dim3((n + TILE - 1) / TILE), dim3(TILE), 0, s, p0, n, rnew,
-                           X.xr, S.xr, S.xf);
+                           X.xr, S.perm, S.xf);
 }
 
 void launch_rebuild_cells(const PoolView& P, const Sorted& S, uint2* cells, hipStream_t s) {
     if (P.ntiles > 0)
-        hipLaunchKernelGGL(k_rebuild_cells, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs, S.xr,
+        hipLaunchKernelGGL(k_rebuild_cells, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
+                           SortedPos{S.xr, S.perm, P.ns},
                            cells);
 }
 
 void launch_reorder(const PoolView& P, Job* jobs_next, uint32_t njobs, bool gather,
                     const uint32_t* keys_s, const uint32_t* vals_s, const State& Y,
                     const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s) {
+    if (P.ntiles == 0) hipLaunchKernelGGL(k_step_count, dim3(1), dim3(1), 0, s, P);
     if (P.ntiles > 0) {
         if (gather)
             hipLaunchKernelGGL(k_reorder<true>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
-                               keys_s, vals_s, Y.xr, S.xr, S.xf, perm, cells);
+                               keys_s, vals_s, Y.xr, S.xf, perm, cells);
         else
             hipLaunchKernelGGL(k_reorder<false>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
-                               keys_s, vals_s, Y.xr, S.xr, S.xf, perm, cells);
+                               keys_s, vals_s, Y.xr, S.xf, perm, cells);
     }
     // after the merge sort the step has ended already (k_mov_sort)
     if (gather) {

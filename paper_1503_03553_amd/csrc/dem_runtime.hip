@@ -129,10 +129,10 @@ struct dem_pool {
     std::vector<Buf> bufs;
     size_t device_bytes = 0;
     State S[2]{};                     // state buffers; S[cur] holds the current state
-    // sorted position records and permutation (sorted position -> position
-    // in the state buffer) of the order a step reads, one pair per state
-    // buffer: a step reads those of S[o] and writes those of S[w], so that an
-    // abandoned step leaves the ones it started from intact
+    // the sorted order a step reads (FP32 records, permutation into the
+    // state buffer, whose FP64 records it reads through it), one per state
+    // buffer: a step reads that of S[o] and writes that of S[w], so that an
+    // abandoned step leaves the one it started from intact
     Sorted srt[2]{};
     uint2* cells = nullptr;
     uint2* rows[2] = {nullptr, nullptr};
@@ -477,7 +477,7 @@ uint64_t pool_bytes(uint64_t max_tiles, uint64_t max_cells, uint64_t max_jobs, b
     const uint64_t np = max_tiles * TILE;
     uint64_t b = 0;
     b += 2 * np * (32 + 48 + 1);       // two state buffers
-    b += 2 * np * (32 + 16);           // sorted positions and their FP32 records, two steps
+    b += 2 * np * 16;                  // FP32 records of the sorted order, two steps
     b += np * 2 * 8;                   // contact rows, two steps
     b += np * 7 * 4;                   // permutation (two), keys and values (two), keys before
     b += (uint64_t)MAX_MOVERS * 20;    // mover lists
@@ -536,7 +536,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     s->free_cells.push_back({0, s->max_cells});
     const size_t np = (size_t)mt * TILE;
     dem_status r = DEM_OK;
-    void *xa, *va, *ma, *xsa, *xfa, *xsb, *xfb, *xb, *vb, *mb;
+    void *xa, *va, *ma, *xfa, *xfb, *xb, *vb, *mb;
 #define ALLOC_OR_FAIL(call)   \
     do {                      \
         r = (call);           \
@@ -548,9 +548,7 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xa));
     ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &va));
     ALLOC_OR_FAIL(dalloc(s, np, &ma));
-    ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xsa));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(float4), &xfa));
-    ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xsb));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(float4), &xfb));
     ALLOC_OR_FAIL(dalloc(s, np * sizeof(double4), &xb));
     ALLOC_OR_FAIL(dalloc(s, 3 * np * sizeof(double2), &vb));
@@ -561,15 +559,17 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     s->S[1].xr = (double4*)xb;
     s->S[1].vw = (double2*)vb;
     s->S[1].mat = (uint8_t*)mb;
-    s->srt[0].xr = (double4*)xsa;
     s->srt[0].xf = (float4*)xfa;
-    s->srt[1].xr = (double4*)xsb;
     s->srt[1].xf = (float4*)xfb;
     ALLOC_OR_FAIL(dalloc_t(s, s->max_cells, &s->cells));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[0]));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->rows[1]));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->prev[0]));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->prev[1]));
+    for (int k = 0; k < 2; ++k) {
+        s->srt[k].xr = s->S[k].xr;
+        s->srt[k].perm = s->prev[k];
+    }
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->keys));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->vals));
     ALLOC_OR_FAIL(dalloc_t(s, np, &s->keys_t));
@@ -615,6 +615,14 @@ dem_status create_pool(uint64_t max_particles, uint64_t max_cells, uint32_t max_
     if (e == hipSuccess) e = hipMemset(s->S[1].mat, 0, np);
     std::vector<uint32_t> tj(mt, NO_JOB);
     if (e == hipSuccess) e = hipMemcpy(s->tile_job, tj.data(), mt * 4, hipMemcpyHostToDevice);
+    {
+        // every permutation entry starts as the identity (ghost slots and
+        // free tiles keep theirs; the kernels also clamp what they read)
+        std::vector<uint32_t> id(np);
+        std::iota(id.begin(), id.end(), 0u);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k)
+            e = hipMemcpy(s->prev[k], id.data(), np * 4, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = hipMemset(s->tile_key, 0, mt * 4);
     if (e != hipSuccess) {
         destroy_pool(s);
@@ -795,13 +803,10 @@ dem_status upload_job(dem_pool* s, int slot, Placed& pl, double t0, uint32_t ste
     auto upv = [&](void* dst, auto& v) {
         if (r == DEM_OK) r = upload_vec(s, dst, v);
     };
-    // the state into the current buffer, in sorted order; the sorted
-    // position records are a copy of its positions
+    // the state into the current buffer, in sorted order (its permutation
+    // is the identity)
     State& X = s->S[s->cur];
     upv(X.xr + p0, pl.xr);
-    if (r == DEM_OK && n)
-        r = hip_status(hipMemcpyAsync(s->srt[s->cur].xr + p0, X.xr + p0, n * sizeof(double4),
-                                      hipMemcpyDeviceToDevice, s->stream));
     upv(s->srt[s->cur].xf + p0, pl.xf);
     upv(X.vw + p0, pl.vw0);
     upv(X.vw + np + p0, pl.vw1);
