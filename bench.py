@@ -75,18 +75,18 @@ def kernel_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, half=True,
     if phase == "sort":
         if merge:
             # keys before the step and the new state's positions read 36; at
-            # each new position the sorted key, position and FP32 record and
-            # the permutation written 56; plus the few movers (negligible)
-            return 92 * n
+            # each new position the sorted key, the FP32 record and the
+            # permutation written 24; plus the few movers (negligible)
+            return 60 * n
         passes = max(1, (key_bits + 7) // 8)
         return 20 * n * passes
     if phase == "reorder":
         if merge:
             # the sorted keys (neighbours from the cache) 4, cell bounds ~8
             return 12 * n
-        # sorted key and source index 8, gathered position 32, sorted position
-        # and FP32 record written 48, permutation 4, cell bounds ~8
-        return 100 * n
+        # sorted key and source index 8, gathered position 32, FP32 record
+        # written 16, permutation 4, cell bounds ~8
+        return 68 * n
     return 0
 
 
@@ -105,7 +105,7 @@ def method_bytes(phase, n, m, m_old, fp64, key_bits, force_out=False, merge=True
               and new id and displacement 28; per old contact id and
               displacement 28; F and T 24 (48 in FP64) only when stored
       sort    (stable sort of (key, index))  the implementation's bytes (the
-              merge sort's placement also writes the sorted positions)
+              merge sort's placement also writes the FP32 records)
       reorder (gather into cell order, cell bounds)  at most 168 (index 4,
               record gathered 80 and written 80, bounds 4); the kernels move
               only positions, so their own smaller count applies

@@ -82,9 +82,10 @@ def test_method_bytes_count_the_method_not_the_implementation():
                                                                                 False, 20)
     # the kernels move positions only: their own counts are below the
     # method's 168 for the gather into cell order (after the merge sort the
-    # placement writes the sorted positions and the reorder only the bounds)
-    assert bench.method_bytes("reorder", n, m, mo, False, 20, merge=False) == 100 * n
+    # placement writes the FP32 records and the reorder only the bounds)
+    assert bench.method_bytes("reorder", n, m, mo, False, 20, merge=False) == 68 * n
     assert bench.method_bytes("reorder", n, m, mo, False, 20) == 12 * n
+    assert bench.method_bytes("sort", n, m, mo, False, 20) == 60 * n
     assert bench.method_bytes("sort", n, m, mo, False, 20) + \
         bench.method_bytes("reorder", n, m, mo, False, 20) < 168 * n
     rows = bench.phase_rows({"detect": (0.05, 1), "force": (0.07, 1)}, n, m, mo, False, 20)
