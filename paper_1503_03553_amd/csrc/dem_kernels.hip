@@ -2584,13 +2584,14 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 
 // ------------------------------------------------------------------ reorder
 
-// One workgroup per tile.  The new sorted order: with GATHER (after the
-// radix sort) the permutation into the buffer just written, the position
-// records gathered from it (a finished job's positions map to themselves);
+// One workgroup per REORDER_TILES tiles.  The new sorted order: with GATHER
+// (after the radix sort) the permutation into the buffer just written, the
+// FP32 records made from it (a finished job's positions map to themselves);
 // in every case the cell bounds and the step's counters.  The merge sort's
 // placement writes the permutation and records itself (k_place).  Positions
 // of free tiles and ghost slots kept their place in the sort and are left
 // alone.
+constexpr uint32_t REORDER_TILES = 2;
 template <bool GATHER>
 __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restrict__ jobs,
                                                   const uint32_t* __restrict__ keys_s,
@@ -2600,54 +2601,71 @@ __global__ __launch_bounds__(TILE) void k_reorder(PoolView P, const Job* __restr
                                                   uint32_t* __restrict__ perm,
                                                   uint2* __restrict__ cells) {
     __shared__ uint32_t s_flag;
-    const uint32_t tile = blockIdx.x;
-    const uint32_t i = tile * TILE + threadIdx.x;
-    // the sorted key and source index, the gathered position and the
-    // neighbours' keys are read before the error check and the job lookup,
+    // REORDER_TILES tiles per workgroup, one position of each per lane: half
+    // the wavefronts, so that the whole grid is resident at once
+    constexpr uint32_t RT = REORDER_TILES;
+    const uint32_t t0 = blockIdx.x * RT;
+    // the sorted keys and source indices, the gathered positions and the
+    // neighbours' keys are read before the error check and the job lookups,
     // so that all are in flight together (every index is a position; a lane
     // outside a running job ignores what it read)
-    const uint32_t key = keys_s[i];
-    uint32_t src = i;
-    double4 p = make_double4(0, 0, 0, 0);
-    if (GATHER) {
-        src = vals_s[i] < P.ns ? vals_s[i] : i;
-        p = xr_y[src];
+    uint32_t key[RT], src[RT], key_lo[RT], key_hi[RT];
+    double4 p[RT];
+#pragma unroll
+    for (uint32_t r = 0; r < RT; ++r) {
+        const uint32_t i = (t0 + r) * TILE + threadIdx.x;
+        key[r] = key_lo[r] = key_hi[r] = 0u;
+        src[r] = i;
+        p[r] = make_double4(0, 0, 0, 0);
+        if (t0 + r < P.ntiles) {
+            key[r] = keys_s[i];
+            if (GATHER) {
+                src[r] = vals_s[i] < P.ns ? vals_s[i] : i;
+                p[r] = xr_y[src[r]];
+            }
+            key_lo[r] = i > 0 ? keys_s[i - 1] : 0u;
+            key_hi[r] = i + 1 < P.ns ? keys_s[i + 1] : 0u;
+        }
     }
-    const uint32_t key_lo = i > 0 ? keys_s[i - 1] : 0u;
-    const uint32_t key_hi = i + 1 < P.ns ? keys_s[i + 1] : 0u;
     if (skip_if_error(P.st, &s_flag)) return;
-    if (tile == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         // the step completes: it counts, and the next one's cell changes
         // start from zero
         P.st->steps_done += 1;
         P.st->movers = 0;
     }
-    uint32_t jb;
-    const Job* Jp = tile_job(jobs, P, tile, jb);
-    if (!Jp) {
-        if (GATHER && jb != NO_JOB && i < jobs[jb].p0 + jobs[jb].n) perm[i] = i;
-        return;
+#pragma unroll
+    for (uint32_t r = 0; r < RT; ++r) {
+        const uint32_t tile = t0 + r;
+        if (tile >= P.ntiles) break;
+        const uint32_t i = tile * TILE + threadIdx.x;
+        uint32_t jb;
+        const Job* Jp = tile_job(jobs, P, tile, jb);
+        if (!Jp) {
+            if (GATHER && jb != NO_JOB && i < jobs[jb].p0 + jobs[jb].n) perm[i] = i;
+            continue;
+        }
+        const Job& J = *Jp;
+        const Geo& G = J.g;
+        if (threadIdx.x == 0) {
+            // the step completed: its counters join the sums
+            TileStats& q = P.ts[tile];
+            q.m += q.m_step;
+            q.matched += q.matched_step;
+            q.old += q.old_step;
+        }
+        const uint32_t end = J.p0 + J.n;
+        if (i >= end) continue;
+        // a source index is a position by construction; checked (above) so
+        // that a sort defect can never read outside the arrays
+        if (GATHER) {
+            xf[i] = far_record(G, p[r]);
+            perm[i] = src[r];
+        }
+        const uint32_t lin = J.cell_base + key_lin(G, key[r] & P.lmask);
+        if (i == J.p0 || key_lo[r] != key[r]) cells[lin].x = i;
+        if (i == end - 1 || key_hi[r] != key[r]) cells[lin].y = i + 1;
     }
-    const Job& J = *Jp;
-    const Geo& G = J.g;
-    if (threadIdx.x == 0) {
-        // the step completed: its counters join the sums
-        TileStats& q = P.ts[tile];
-        q.m += q.m_step;
-        q.matched += q.matched_step;
-        q.old += q.old_step;
-    }
-    const uint32_t end = J.p0 + J.n;
-    if (i >= end) return;
-    // a source index is a position by construction; checked (above) so that
-    // a sort defect can never read outside the arrays
-    if (GATHER) {
-        xf[i] = far_record(G, p);
-        perm[i] = src;
-    }
-    const uint32_t lin = J.cell_base + key_lin(G, key & P.lmask);
-    if (i == J.p0 || key_lo != key) cells[lin].x = i;
-    if (i == end - 1 || key_hi != key) cells[lin].y = i + 1;
 }
 
 // Cell bounds of the current sorted order, from its positions: after
@@ -2939,11 +2957,12 @@ void launch_reorder(const PoolView& P, Job* jobs_next, uint32_t njobs, bool gath
                     const Sorted& S, uint32_t* perm, uint2* cells, hipStream_t s) {
     if (P.ntiles == 0) hipLaunchKernelGGL(k_step_count, dim3(1), dim3(1), 0, s, P);
     if (P.ntiles > 0) {
+        const uint32_t nwg = (P.ntiles + REORDER_TILES - 1) / REORDER_TILES;
         if (gather)
-            hipLaunchKernelGGL(k_reorder<true>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
+            hipLaunchKernelGGL(k_reorder<true>, dim3(nwg), dim3(TILE), 0, s, P, P.jobs,
                                keys_s, vals_s, Y.xr, S.xf, perm, cells);
         else
-            hipLaunchKernelGGL(k_reorder<false>, dim3(P.ntiles), dim3(TILE), 0, s, P, P.jobs,
+            hipLaunchKernelGGL(k_reorder<false>, dim3(nwg), dim3(TILE), 0, s, P, P.jobs,
                                keys_s, vals_s, Y.xr, S.xf, perm, cells);
     }
     // after the merge sort the step has ended already (k_mov_sort)
